@@ -1,0 +1,223 @@
+"""One explicit OTM step (Alg. 1) on the CPU in float64.
+
+State at the start of step n -> n+1 holds nodal positions x_I, displacement
+increments du_I, lumped masses m_I and nodal forces f_I of step n, and at
+the material points x_p, volume v_p, mass m_p, LME multiplier, F, b^e,
+epsbar, T, Cauchy stress sigma, the support lists and N, grad N at x_p,n.
+Alg. 1 is taken in rotated order: the mass/force assembly of its step 1 is
+done at the end of the previous step (and once at t = 0), so that
+
+  1. nodes:       du <- du + dt^2 f / m; x* = x + du; wall projection;
+                  x <- x*                     (central difference, nodal
+                                               equilibrium and position update
+                                               equations; Sec. 4.1 contact)
+  2. MP position: x_p <- sum_I N_I,n x_I,n+1  (MP coordinate equation)
+  3. kinematics:  dF = 1 + sum_I du_I (x) grad N_I,n ; F <- dF F ;
+                  v_p <- det(dF) v_p          (deformation gradient and
+                                               volume equations)
+  4. constitutive update                      (Sec. 4.1 / 4.2)
+  5. search of the support domains            (Alg. 3)
+  6. LME shape functions                      (Sec. 2.3)
+  7. lumped mass and nodal force              (nodal mass and residual
+       m_I = sum_p N_Ip m_p,                   equations, no body force,
+       f_I = -sum_p v_p sigma_p grad N_Ip      no tractions, no
+                                               stabilisation term)
+
+Readings: du_0 = dt v_0 at the nodes (the central difference needs one
+increment to start); the wall is rigid and frictionless: a node whose
+predicted gap g = (x* - x_bar).n is negative is projected onto the plane and
+its increment set to the projected motion.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import lme, material, search
+
+
+@dataclasses.dataclass
+class State:
+    x: np.ndarray
+    du: np.ndarray
+    m: np.ndarray
+    f: np.ndarray
+    xp: np.ndarray
+    vol: np.ndarray
+    mass: np.ndarray
+    lam: np.ndarray
+    F: np.ndarray
+    be: np.ndarray
+    epsbar: np.ndarray
+    T: np.ndarray
+    sigma: np.ndarray
+    offsets: np.ndarray
+    idx: np.ndarray
+    N: np.ndarray
+    dN: np.ndarray
+    n: int = 0
+
+    def copy(self):
+        return State(**{k: (v.copy() if isinstance(v, np.ndarray) else v)
+                        for k, v in dataclasses.asdict(self).items()})
+
+
+def params_from_workload(w, **over):
+    """Flat parameter dict from a workload object (duck-typed)."""
+    mat = w.material
+    p = dict(model=mat.model, E=mat.E, nu=mat.nu, rho0=mat.rho0, A=mat.A, B=mat.B,
+             n=mat.n, C=mat.C, m=mat.m, eps_dot0=mat.eps_dot0, T_r=mat.T_r, T_m=mat.T_m,
+             Cp=mat.Cp, chi=mat.chi, Y0=mat.Y0, H=mat.H,
+             beta=w.beta, r_list=w.r_list, cell_size=w.r_list * 1.0001,
+             lme_tol=1e-13 * w.h, lme_max_iter=50, rm_tol=1e-15, rm_max_iter=60,
+             wall=bool(w.wall), wall_x=np.array(w.wall_x, float),
+             wall_n=np.array(w.wall_n, float), dt=w.dt, rebuild_every=w.rebuild_every)
+    p.update(over)
+    return p
+
+
+# ------------------------------------------------------------------ pieces
+def assemble(st, p):
+    """Lumped nodal mass and internal force (nodal mass / residual equations),
+    summed per node in ascending (MP, pair) order."""
+    n_nodes = st.x.shape[0]
+    mp_of_pair = np.repeat(np.arange(st.xp.shape[0]), np.diff(st.offsets))
+    m = np.bincount(st.idx, weights=(st.N * st.mass[mp_of_pair]).real, minlength=n_nodes)
+    if np.iscomplexobj(st.N):
+        m = m + 1j * np.bincount(st.idx, weights=(st.N * st.mass[mp_of_pair]).imag,
+                                 minlength=n_nodes)
+    # f_I,i = - sum_p v_p sigma_p,ij dN_Ip,j
+    contrib = -st.vol[mp_of_pair, None] * np.einsum("qij,qj->qi", st.sigma[mp_of_pair], st.dN)
+    f = np.zeros((n_nodes, 3), dtype=contrib.dtype)
+    for i in range(3):
+        f[:, i] = np.bincount(st.idx, weights=contrib[:, i].real, minlength=n_nodes)
+        if np.iscomplexobj(contrib):
+            f[:, i] = f[:, i] + 1j * np.bincount(st.idx, weights=contrib[:, i].imag,
+                                                 minlength=n_nodes)
+    st.m, st.f = m, f
+
+
+def node_update(st, p):
+    """Central difference with lumped mass, then the rigid-wall projection."""
+    dt = p["dt"]
+    du = st.du + dt * dt * st.f / st.m[:, None]
+    xs = st.x + du
+    if p["wall"]:
+        nrm = np.asarray(p["wall_n"], float)
+        g = (xs - np.asarray(p["wall_x"], float)) @ nrm
+        hit = g.real < 0
+        xs = np.where(hit[:, None], xs - g[:, None] * nrm[None, :], xs)
+        du = np.where(hit[:, None], xs - st.x, du)
+    st.du = du
+    st.x = xs
+
+
+def mp_update(st, p):
+    """MP position, incremental deformation gradient, F, volume and the
+    constitutive update, all with the shape functions of step n."""
+    n_mp = st.xp.shape[0]
+    xI = st.x[st.idx]
+    duI = st.du[st.idx]
+    xp = np.zeros((n_mp, 3), dtype=np.result_type(st.N, xI))
+    for i in range(3):
+        xp[:, i] = _segsum(st.N * xI[:, i], st.offsets)
+    dF = np.broadcast_to(np.eye(3), (n_mp, 3, 3)).astype(np.result_type(duI, st.dN))
+    for i in range(3):
+        for j in range(3):
+            dF[:, i, j] = dF[:, i, j] + _segsum(duI[:, i] * st.dN[:, j], st.offsets)
+    F_new = dF @ st.F
+    J_dF = material.det3(dF)
+    if np.any(J_dF.real <= 0):
+        raise FloatingPointError("inverted material point (det dF <= 0) at "
+                                 f"{int(np.nonzero(J_dF.real <= 0)[0][0])}")
+    st.vol = J_dF * st.vol
+    st.xp = xp
+    J_new = material.det3(F_new)
+    if p["model"] == material.NEOHOOKE:
+        st.sigma = material.neo_hooke_cauchy(F_new, p["E"], p["nu"])
+    else:
+        sig, be, eb, T, _ = material.j2_update(p, dF, st.be, st.epsbar, st.T, J_new, p["dt"],
+                                               spectral=p.get("spectral", "eigh"),
+                                               polish=p.get("polish", 0))
+        st.sigma, st.be, st.epsbar, st.T = sig, be, eb, T
+    st.F = F_new
+
+
+def _segsum(vals, offsets):
+    """Sum of each CSR row, pairs taken in row order."""
+    out = np.zeros(offsets.shape[0] - 1, dtype=vals.dtype)
+    K = np.diff(offsets)
+    kmax = int(K.max()) if K.size else 0
+    for k in range(kmax):
+        rows = np.nonzero(K > k)[0]
+        out[rows] = out[rows] + vals[offsets[rows] + k]
+    return out
+
+
+def rebuild_lists(st, p, x_mp_real=None):
+    xm = st.xp.real if x_mp_real is None else x_mp_real
+    st.offsets, st.idx = search.neighbors_linked_cell(st.x.real, xm, p["r_list"],
+                                                       p["cell_size"])
+
+
+def shape(st, p):
+    st.lam, st.N, st.dN = lme.lme_shape(st.x, st.xp, st.offsets, st.idx, p["beta"],
+                                        p["lme_tol"], p["lme_max_iter"], st.lam,
+                                        extra_iter=p.get("polish", 0))
+
+
+# ------------------------------------------------------------------ driver
+def init_state(x_nodes, x_mp, vol, mass, v0_nodes, p, lists=None):
+    """t = 0: F = b^e = 1, epsbar = 0, T = T_r, sigma = 0, du = dt v0,
+    support search, shape functions, and the first mass/force assembly."""
+    n_mp = x_mp.shape[0]
+    n_nodes = x_nodes.shape[0]
+    I = np.eye(3)
+    st = State(x=np.array(x_nodes, dtype=np.float64), du=p["dt"] * np.asarray(v0_nodes, float),
+               m=np.zeros(n_nodes), f=np.zeros((n_nodes, 3)),
+               xp=np.array(x_mp, dtype=np.float64), vol=np.array(vol, dtype=np.float64),
+               mass=np.array(mass, dtype=np.float64), lam=np.zeros((n_mp, 3)),
+               F=np.tile(I, (n_mp, 1, 1)), be=np.tile(I, (n_mp, 1, 1)),
+               epsbar=np.zeros(n_mp), T=np.full(n_mp, float(p["T_r"])),
+               sigma=np.zeros((n_mp, 3, 3)), offsets=None, idx=None, N=None, dN=None)
+    if lists is None:
+        rebuild_lists(st, p)
+    else:
+        st.offsets, st.idx = lists
+    shape(st, p)
+    assemble(st, p)
+    return st
+
+
+def step(st, p, lists=None):
+    """One step n -> n+1 in place.  ``lists`` (offsets, idx) forces the
+    support lists (frozen-list runs); otherwise they are rebuilt every
+    ``rebuild_every`` steps."""
+    node_update(st, p)
+    mp_update(st, p)
+    st.n += 1
+    if lists is not None:
+        st.offsets, st.idx = lists
+    elif st.n % int(p["rebuild_every"]) == 0:
+        rebuild_lists(st, p)
+    shape(st, p)
+    assemble(st, p)
+    return st
+
+
+def neo_hooke_energy_density(F, E, nu):
+    lam, mu = material.lame(E, nu)
+    J = material.det3(F)
+    trb = (F * F).sum(axis=(-1, -2))
+    lnJ = np.log(J)
+    return 0.5 * mu * (trb - 3.0) - mu * lnJ + 0.5 * lam * lnJ ** 2
+
+
+def total_energy(st, p, vol0):
+    """Kinetic energy of the half-step velocity du/dt with the lumped mass
+    plus the stored Neo-Hookean energy (elastic workloads)."""
+    v = st.du / p["dt"]
+    ke = 0.5 * (st.m * (v * v).sum(axis=1)).sum()
+    pe = (vol0 * neo_hooke_energy_density(st.F, p["E"], p["nu"])).sum()
+    return ke, pe

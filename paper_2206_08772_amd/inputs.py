@@ -1,0 +1,232 @@
+"""Seeded synthetic workloads for the explicit OTM step.
+
+This module only builds inputs: a jittered node lattice, the tetrahedra of its
+hex cells, one material point (MP) at each tet centroid with the tet volume,
+the nodal initial velocity and the material constants.  It holds none of the
+method's arithmetic and is shared, as plain NumPy arrays, by the CPU oracle
+and by the GPU path.
+
+The paper's two benchmarks (Taylor rod impact, Sec. 4.1; serrated chip
+formation, Sec. 4.2) come with meshes and parameter tables that are not
+published with it, so every workload here is a same-shape stand-in:
+
+* nodes on the lattice (i h, j h, k h) inside the body, enumerated with z
+  slowest and x fastest, each coordinate jittered by U(-0.1 h, 0.1 h) in one
+  seeded draw of shape (n_nodes, 3);
+* every hex cell whose 8 corners are present is split into the 6 Kuhn tets
+  around its (0,0,0)-(1,1,1) diagonal;
+* one MP per tet at the centroid, volume |det| / 6, mass rho0 * volume,
+  ordered hex-cell-major then by tet index (so MPs that are close in space are
+  close in memory).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# Kuhn split of the unit cube: corner bit 1 = +x, bit 2 = +y, bit 4 = +z.
+KUHN_TETS = ((0, 1, 3, 7), (0, 1, 5, 7), (0, 2, 3, 7),
+             (0, 2, 6, 7), (0, 4, 5, 7), (0, 4, 6, 7))
+
+MODEL_NEOHOOKE = 0
+MODEL_J2_JC = 1
+MODEL_J2_LINEAR = 2
+
+
+@dataclasses.dataclass
+class Material:
+    model: int
+    E: float
+    nu: float
+    rho0: float
+    # Johnson-Cook flow stress (Sec. 4.2, JC hardening law)
+    A: float = 0.0
+    B: float = 0.0
+    n: float = 1.0
+    C: float = 0.0
+    m: float = 1.0
+    eps_dot0: float = 1.0
+    T_r: float = 293.0
+    T_m: float = 1356.0
+    Cp: float = 385.0
+    chi: float = 0.9          # Taylor-Quinney coefficient
+    # linear isotropic hardening (Sec. 4.1 yield function)
+    Y0: float = 0.0
+    H: float = 0.0
+
+    @property
+    def lame(self):
+        lam = self.E * self.nu / ((1 + self.nu) * (1 - 2 * self.nu))
+        mu = self.E / (2 * (1 + self.nu))
+        return lam, mu
+
+    @property
+    def wave_speed(self):
+        lam, mu = self.lame
+        return math.sqrt((lam + 2 * mu) / self.rho0)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    h: float
+    x_nodes: np.ndarray     # (n_nodes, 3) float64, jittered reference positions
+    X_nominal: np.ndarray   # (n_nodes, 3) float64, unjittered lattice points
+    x_mp: np.ndarray        # (n_mp, 3) float64, tet centroids
+    vol_mp: np.ndarray      # (n_mp,) tet volumes
+    mass_mp: np.ndarray     # (n_mp,) rho0 * volume
+    v0_nodes: np.ndarray    # (n_nodes, 3) initial nodal velocity
+    material: Material
+    dt: float
+    steps: int
+    gamma: float = 4.0
+    shape_cut: float = 1e-6
+    skin: float = 0.0
+    rebuild_every: int = 1
+    wall: bool = False
+    wall_x: tuple = (0.0, 0.0, 0.0)
+    wall_n: tuple = (0.0, 0.0, 1.0)
+
+    @property
+    def n_nodes(self):
+        return self.x_nodes.shape[0]
+
+    @property
+    def n_mp(self):
+        return self.x_mp.shape[0]
+
+    @property
+    def beta(self):
+        # beta = gamma / h^2 (Sec. 2.3)
+        return self.gamma / self.h ** 2
+
+    @property
+    def r_cut(self):
+        # support radius at which the Gaussian prior exp(-beta r^2) drops to
+        # the shape-value cut: r = h sqrt(-ln(cut) / gamma)
+        return self.h * math.sqrt(-math.log(self.shape_cut) / self.gamma)
+
+    @property
+    def r_list(self):
+        return self.r_cut + self.skin
+
+
+def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False):
+    """Lattice nodes inside a body, their jitter, the hex cells and tets.
+
+    ``inside(i, j, k)`` receives integer index arrays and returns a mask.
+    Returns (x_nodes, X_nominal, x_mp, vol_mp).
+    """
+    (i0, i1), (j0, j1), (k0, k1) = ijk_ranges
+    ni, nj, nk = i1 - i0 + 1, j1 - j0 + 1, k1 - k0 + 1
+    kk, jj, ii = np.meshgrid(np.arange(k0, k1 + 1), np.arange(j0, j1 + 1),
+                             np.arange(i0, i1 + 1), indexing="ij")
+    ii, jj, kk = ii.ravel(), jj.ravel(), kk.ravel()
+    mask = inside(ii, jj, kk)
+    node_id = np.full(mask.shape[0], -1, dtype=np.int64)
+    node_id[mask] = np.arange(int(mask.sum()))
+    node_id = node_id.reshape(nk, nj, ni)
+    X = np.stack([ii[mask], jj[mask], kk[mask]], axis=1).astype(np.float64) * h
+    rng = np.random.default_rng(seed)
+    jit = rng.uniform(-0.1 * h, 0.1 * h, size=X.shape)
+    x = X + jit
+    if clamp_z0:
+        x[:, 2] = np.maximum(x[:, 2], 0.0)
+
+    # hex cells with all 8 corners present, in (k, j, i) order
+    corners = []
+    for c in range(8):
+        di, dj, dk = c & 1, (c >> 1) & 1, (c >> 2) & 1
+        corners.append(node_id[dk:nk - 1 + dk, dj:nj - 1 + dj, di:ni - 1 + di].ravel())
+    corners = np.stack(corners, axis=1)
+    full = (corners >= 0).all(axis=1)
+    corners = corners[full]
+    tet_nodes = corners[:, np.array(KUHN_TETS)]          # (n_hex, 6, 4)
+    tet_nodes = tet_nodes.reshape(-1, 4)
+    p = x[tet_nodes]                                       # (n_mp, 4, 3)
+    x_mp = p.mean(axis=1)
+    e = p[:, 1:, :] - p[:, :1, :]
+    vol = np.abs(np.linalg.det(e)) / 6.0
+    return x, X, x_mp, vol
+
+
+def elastic_cube(n=10, h=1.0, seed=0, steps=10):
+    """Elastic cube: n^3 node lattice, Neo-Hookean E=200, nu=0.3, rho=1,
+    v_x = 0.01 sin(pi X / L) with X the nominal x and L = (n - 1) h."""
+    L = (n - 1) * h
+    x, X, x_mp, vol = _lattice_body(((0, n - 1),) * 3,
+                                    lambda i, j, k: np.ones(i.shape, bool), h, seed)
+    mat = Material(MODEL_NEOHOOKE, E=200.0, nu=0.3, rho0=1.0)
+    v0 = np.zeros_like(x)
+    v0[:, 0] = 0.01 * np.sin(np.pi * X[:, 0] / L)
+    dt = 0.1 * h / mat.wave_speed
+    return Workload("elastic_cube", h, x, X, x_mp, vol, mat.rho0 * vol, v0, mat, dt, steps)
+
+
+def jc_params(seed):
+    """Johnson-Cook constants drawn from copper-like ranges (Pa, SI units)."""
+    rng = np.random.default_rng(seed)
+    return dict(A=rng.uniform(80e6, 100e6), B=rng.uniform(250e6, 320e6),
+                n=rng.uniform(0.25, 0.35), C=rng.uniform(0.02, 0.03),
+                m=rng.uniform(1.0, 1.1))
+
+
+def taylor_rod(h, seed, radius=3.2e-3, length=21.12e-3, speed=190.0, steps=100,
+               model=MODEL_J2_JC, skin_h=0.0, rebuild_every=1, name="taylor_rod",
+               material=None):
+    """Cylinder of radius R and length L (z axis) on a jittered lattice,
+    flying at -speed along z into a rigid frictionless wall z = 0.
+
+    Copper elastic constants of the paper's Taylor rod (Sec. 4.1), JC flow
+    stress drawn from ``seed``, Taylor-Quinney 0.9.
+    """
+    nr = int(math.floor(radius / h))
+    nz = int(math.floor(length / h))
+
+    def inside(i, j, k):
+        return (i * h) ** 2 + (j * h) ** 2 <= radius ** 2
+
+    x, X, x_mp, vol = _lattice_body(((-nr, nr), (-nr, nr), (0, nz)), inside, h, seed,
+                                    clamp_z0=True)
+    if material is None:
+        material = Material(model, E=117e9, nu=0.35, rho0=8930.0, chi=0.9,
+                            T_r=293.0, T_m=1356.0, Cp=385.0, eps_dot0=1.0,
+                            Y0=400e6, H=100e6, **jc_params(seed))
+    v0 = np.zeros_like(x)
+    v0[:, 2] = -speed
+    dt = 0.1 * h / material.wave_speed
+    return Workload(name, h, x, X, x_mp, vol, material.rho0 * vol, v0, material, dt, steps,
+                    skin=skin_h * h, rebuild_every=rebuild_every, wall=True)
+
+
+def config_by_name(name):
+    """The named workloads.
+
+    elastic_cube   10^3 nodes, 4374 MPs, Neo-Hookean, 10 steps
+    taylor_rod     ~202k nodes / ~1.13M MPs, J2/JC + heating + wall, 100 steps
+    taylor_rod_xl  ~2.0M nodes / ~11.6M MPs, lists rebuilt every 10 steps with
+                   a 0.1 h skin, 200 steps
+    adjoint_rod    ~50k nodes / ~268k MPs, 200 steps (gradient workload)
+    small_rod      ~0.8k nodes / ~3.5k MPs rod for long oracle trajectories
+    """
+    if name == "elastic_cube":
+        return elastic_cube()
+    if name == "taylor_rod":
+        return taylor_rod(h=0.15033e-3, seed=1, steps=100)
+    if name == "taylor_rod_xl":
+        return taylor_rod(h=0.06978e-3, seed=2, steps=200, skin_h=0.1, rebuild_every=10,
+                          name="taylor_rod_xl")
+    if name == "adjoint_rod":
+        return taylor_rod(h=0.23863e-3, seed=3, steps=200, name="adjoint_rod")
+    if name == "small_rod":
+        return taylor_rod(h=0.8e-3, seed=5, radius=3.2e-3, length=10.4e-3, steps=100,
+                          name="small_rod")
+    raise KeyError(name)
+
+
+def random_cloud(n_nodes, n_mp, seed, box=1.0):
+    """Uniform random nodes and MPs in a cube (search tests)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0, box, (n_nodes, 3)), rng.uniform(0, box, (n_mp, 3))
