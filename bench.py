@@ -1,0 +1,299 @@
+#!/usr/bin/env python3
+"""Material-point steps per second of the explicit OTM step on one MI355X.
+
+Workload: the Taylor-rod-shaped cylinder (R = 3.2 mm, L = 21.12 mm,
+h = 0.15033 mm: 202,053 nodes, 1,132,320 tet-centroid MPs), J2 plasticity
+with Johnson-Cook hardening and adiabatic heating, rigid wall, support
+lists rebuilt every step.  A step is one full pass of the hot path: node
+update, MP update (kinematics + return map), linked-cell search, LME shape
+functions and nodal force assembly.
+
+The main line is float64 with atomic assembly; the mixed-precision mode and
+the deterministic (segmented) assembly are timed the same way and reported
+under "variants".  Inputs are resident in HBM before the timed region; the
+timed region is bracketed by device synchronisation and HIP events on the
+stream the kernels run on.  Per-phase durations come from events recorded by
+the library between its kernels (otm_step_profiled).
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 5]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+PHASES = ("node_update", "mp_update", "search", "lme", "assembly", "segmented", "end")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mp_update_taylor_rod.txt")
+
+
+# ------------------------------------------------------- algorithmic bytes
+def mp_pass_bytes(n_mp, n_nodes, P, precision, model):
+    """Minimum HBM bytes of one MP-pass launch (each array read or written
+    once).  Per pair: idx 4 + N 8 + grad N 24 (12 in mixed).  Per MP: read
+    offsets 8, vol 8, F-1 72 (36), b^e-1 48 (24), epsbar 8, T 8; write x_p 24,
+    vol 8, F-1, b^e-1, epsbar, T, sigma 48 (24).  Per node: x and du gathered
+    once, 48."""
+    r = 8 if precision == "fp64" else 4
+    pair = 4 + 8 + 3 * r
+    plastic = model != 0
+    read = 8 + 8 + 9 * r + (6 * r + 8 + 8 if plastic else 0)
+    write = 24 + 8 + 9 * r + 6 * r + (6 * r + 8 + 8 if plastic else 0)
+    return pair * P + (read + write) * n_mp + 48 * n_nodes
+
+
+def lme_bytes(n_mp, n_nodes, P, precision):
+    """Shape functions: per pair idx 4 read, N 8 and grad N 24 (12) written;
+    per MP offsets 8, x_p 24 and lambda 24 read, lambda 24 written; per node
+    x 24 gathered once."""
+    r = 8 if precision == "fp64" else 4
+    return (4 + 8 + 3 * r) * P + 80 * n_mp + 24 * n_nodes
+
+
+def assembly_bytes(n_mp, n_nodes, P, precision):
+    """Atomic assembly: per pair idx 4, N 8, grad N 24 (12) read; per MP
+    offsets 8, vol 8, mass 8, sigma 48 (24) read; per node m and f (32 B)
+    read-modify-written once."""
+    r = 8 if precision == "fp64" else 4
+    return (4 + 8 + 3 * r) * P + (24 + 6 * r) * n_mp + 64 * n_nodes
+
+
+def search_bytes(n_mp, n_nodes, P):
+    """Count and fill passes: x_p read twice (48), offsets written and read
+    (16), idx written (4 per pair); nodes binned once (x read 24, cell id
+    written and read 8, sorted copy written 32, read back by both passes
+    from cache at least once 32)."""
+    return 4 * P + 64 * n_mp + 96 * n_nodes
+
+
+def node_bytes(n_nodes):
+    return 160 * n_nodes
+
+
+def src_digest():
+    h = hashlib.sha256()
+    for f in ("mp_update.hip", "otm_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2206_08772_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per MP-pass launch from committed rocprofv3 counters, or
+    None if there are none or the kernel source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"^source_digest:\s*(\S+)", txt, re.M)
+    b = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
+    if not m or not b or m.group(1) != src_digest():
+        return None
+    return float(b.group(1))
+
+
+# ------------------------------------------------------------ GPU timing
+def hip_runtime():
+    """The HIP runtime already loaded by torch (events are created with it)."""
+    import ctypes as C
+    for name in ("libamdhip64.so", "libamdhip64.so.7", "libamdhip64.so.6"):
+        try:
+            rt = C.CDLL(name)
+            break
+        except OSError:
+            continue
+    else:
+        raise OSError("libamdhip64 not found")
+    rt.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+    rt.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+    rt.hipEventDestroy.argtypes = [C.c_void_p]
+    return rt
+
+
+def run_variant(w, precision, scatter, steps, warmup):
+    import ctypes as C
+    import torch
+    import otm_workloads as W
+    from paper_2206_08772_amd import _lib
+    from paper_2206_08772_amd.sim import Sim, _ptr, _stream
+
+    p = W.params_from_workload(w)
+    sim = Sim(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, precision=precision,
+              scatter=scatter)
+    sim.init()
+    for _ in range(warmup):
+        sim.step()
+    sim.check_diag()
+    torch.cuda.synchronize()
+    lib = _lib.lib()
+    rt = hip_runtime()
+    skip = ("segmented",) if scatter == "atomic" else ()
+    arrays = []
+    for _ in range(steps):
+        a = (C.c_void_p * len(PHASES))()
+        for k, name in enumerate(PHASES):
+            if name in skip:
+                a[k] = None
+            else:
+                ev = C.c_void_p()
+                assert rt.hipEventCreate(C.byref(ev)) == 0
+                a[k] = ev
+        arrays.append(a)
+    stream = _stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for k in range(steps):
+        _lib.check(lib.otm_step_profiled(C.byref(sim.st), C.byref(sim.p), sim.dt, 1, sim.mode,
+                                         sim.ws.ptr, sim.ws.nbytes, _ptr(sim.diag), arrays[k],
+                                         stream), "otm_step_profiled")
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    code, d = sim.check_diag()
+    used = [k for k in range(len(PHASES)) if PHASES[k] not in skip]
+    phase_ms = {}
+    ms = C.c_float()
+    for a, b in zip(used[:-1], used[1:]):
+        acc = 0.0
+        for s in range(steps):
+            assert rt.hipEventElapsedTime(C.byref(ms), arrays[s][a], arrays[s][b]) == 0
+            acc += ms.value
+        phase_ms[PHASES[a]] = acc / steps
+    for a in arrays:
+        for k in used:
+            rt.hipEventDestroy(a[k])
+    P = int(d.pairs_needed)
+    out = dict(ms_per_step=total_ms / steps, wall_s=wall, value=w.n_mp * steps / (total_ms / 1e3),
+               phase_ms=phase_ms, pairs=P, kbar=P / w.n_mp, max_support=int(d.max_support))
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline_entry(nbytes, ms):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4))
+
+
+# ------------------------------------------------------------ CPU baseline
+def cpu_baseline(seconds_budget=30.0):
+    """The oracle, as it is, on a bounded slab of the same rod (same h,
+    radius, material and seed; 12 lattice layers instead of 141), single
+    thread, timing steps after its t = 0 set-up."""
+    from threadpoolctl import threadpool_limits
+    import otm_workloads as W
+    from oracle import step as OST
+    h = 0.15033e-3
+    w = W.taylor_rod(h=h, seed=1, length=12.5 * h, name="taylor_rod_slab")
+    p = W.params_from_workload(w)
+    with threadpool_limits(limits=1):
+        st = OST.init_state(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p)
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            OST.step(st, p)
+            n += 1
+            if time.perf_counter() - t0 > seconds_budget / 3 or n >= 3:
+                break
+        dt = time.perf_counter() - t0
+    return dict(value=round(w.n_mp * n / dt, 1), unit="material-point steps/s", cores=1,
+                kind="oracle",
+                sample=f"NumPy oracle, 1 thread: {n} steps of a {w.n_mp}-MP, {w.n_nodes}-node "
+                       f"slab (12 lattice layers) of the same rod after its t=0 set-up; "
+                       f"{dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="taylor_rod")
+    ap.add_argument("--variants", default="mixed,segmented",
+                    help="extra timed variants: mixed, segmented (comma separated, or none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import otm_workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    w = W.config_by_name(args.workload)
+
+    main_run = run_variant(w, "fp64", "atomic", args.steps, args.warmup)
+    variants = {}
+    for v in [s for s in args.variants.split(",") if s and s != "none"]:
+        prec = "mixed" if v == "mixed" else "fp64"
+        scat = "segmented" if v == "segmented" else "atomic"
+        r = run_variant(w, prec, scat, args.steps, args.warmup)
+        pm = dict(r["phase_ms"])
+        if scat == "segmented":      # markers 4..6: influence lists, then the gather
+            pm["influence_lists"] = pm.pop("assembly")
+        variants[v] = dict(value=round(r["value"], 1), ms_per_step=round(r["ms_per_step"], 4),
+                           phase_ms={k: round(x, 4) for k, x in pm.items()})
+        if prec == "mixed":
+            nb = mp_pass_bytes(w.n_mp, w.n_nodes, r["pairs"], "mixed", w.material.model)
+            variants[v]["mp_pass_roofline"] = roofline_entry(nb, r["phase_ms"]["mp_update"])
+
+    P = main_run["pairs"]
+    ph = main_run["phase_ms"]
+    mp_b = mp_pass_bytes(w.n_mp, w.n_nodes, P, "fp64", w.material.model)
+    roof = roofline_entry(mp_b, ph["mp_update"])
+    roof["kernel"] = "k_mp_update<double> (MP pass: kinematics + J2/JC return map)"
+    roof["traffic"] = measured_traffic()
+    phases = {
+        "node_update": roofline_entry(node_bytes(w.n_nodes), ph["node_update"]),
+        "search": roofline_entry(search_bytes(w.n_mp, w.n_nodes, P), ph["search"]),
+        "lme": roofline_entry(lme_bytes(w.n_mp, w.n_nodes, P, "fp64"), ph["lme"]),
+        "assembly": roofline_entry(assembly_bytes(w.n_mp, w.n_nodes, P, "fp64"),
+                                   ph["assembly"]),
+    }
+    for k in phases:
+        phases[k]["ms"] = round(ph[k], 4)
+    phases["mp_update"] = dict(roof, ms=round(ph["mp_update"], 4))
+
+    line = {
+        "metric": "material-point steps/s (FP64 vs mixed, 1 GPU) + adjoint/forward time ratio",
+        "value": round(main_run["value"], 1),
+        "unit": "material-point steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: J2/Johnson-Cook rod, {w.n_nodes} nodes, "
+                               f"{w.n_mp} MPs, rebuild every step, atomic assembly",
+                   "n_nodes": w.n_nodes, "n_mp": w.n_mp, "pairs": P,
+                   "mean_support": round(main_run["kbar"], 3),
+                   "max_support": main_run["max_support"], "parallelism": "single GPU"},
+        "roofline": roof,
+        "phases": phases,
+        "variants": variants,
+        "adjoint_forward_ratio": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * otm.h -- C ABI of libotm.so, the explicit step of the Optimal Transportation
+ * Meshfree (OTM) method on one AMD Instinct MI355X (gfx950).
+ *
+ * The step follows Alg. 1 of the paper (Kumar, Gosselet, Huang, Weissenfels,
+ * Wriggers, "Parallel multiphysics simulation for the stabilized optimal
+ * transportation meshfree (OTM) method"): lumped mass and nodal force,
+ * central-difference update of the nodes, material-point (MP) positions and
+ * deformation gradients, constitutive update, linked-cell search of the
+ * support domains (Alg. 3) and local max-ent (LME) shape functions (Sec. 2.3).
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers into caller-owned buffers, unless
+ *    marked "host".  The library never allocates device memory: scratch space
+ *    comes from a caller-provided workspace of otm_workspace_bytes() bytes,
+ *    256-byte aligned.  The caller keeps ownership of everything it passes.
+ *  - Vector fields are structure-of-arrays: a "[3][n]" array holds all x
+ *    components, then all y, then all z.  Second-order tensors are stored per
+ *    component: F as [9][n] row major (F_ij at component 3*i+j), symmetric
+ *    tensors as [6][n] in the order xx, yy, zz, xy, yz, xz.
+ *  - Support lists are CSR over MPs: nbr_offsets[n_mp+1] (int64, offsets[0]=0)
+ *    and nbr_idx[] (int32 node ids, ascending within each MP).  Per-pair
+ *    arrays (N, dN) follow the same pair order; dN is [3][pair_capacity].
+ *  - Work is enqueued asynchronously on the caller's HIP stream.  Only
+ *    otm_build_neighbors and otm_diag_read synchronise that stream.
+ *  - Errors the host can see (null or misaligned pointers, negative sizes,
+ *    cell edge below the search radius, unknown enums, workspace too small)
+ *    are returned at once and nothing is enqueued.  Errors found on the device
+ *    (LME or return-map non-convergence, inverted or non-finite material
+ *    points, pair capacity exceeded) are recorded in the caller's device
+ *    otm_diag record and reported by otm_diag_read.
+ *  - No C++ exception crosses this interface.  The library keeps no state
+ *    between calls; calls on distinct streams with distinct buffers may run
+ *    concurrently.
+ */
+#ifndef OTM_H
+#define OTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t otm_status;
+enum {
+  OTM_OK = 0,
+  OTM_ERR_ARG = -1,          /* invalid argument (host check) */
+  OTM_ERR_CAPACITY = -2,     /* more support pairs than pair_capacity */
+  OTM_ERR_LME_NOCONV = -3,   /* LME Newton did not converge */
+  OTM_ERR_RM_NOCONV = -4,    /* return-map Newton did not converge */
+  OTM_ERR_INVERTED = -5,     /* det(dF) <= 0 at a material point */
+  OTM_ERR_NONFINITE = -6,    /* non-finite stress or position */
+  OTM_ERR_HIP = -7           /* a HIP runtime call failed */
+};
+
+/* arithmetic of the step */
+enum { OTM_FP64 = 0,     /* everything in float64 */
+       OTM_MIXED = 1 };  /* return map, stress, F, b^e, grad N and force
+                            products in float32; LME Newton, N, positions,
+                            volumes, masses and nodal accumulation in float64 */
+/* nodal force assembly */
+enum { OTM_SCATTER_ATOMIC = 0,      /* contributions summed per node in LDS
+                                       by each workgroup, then float64 atomic
+                                       adds; order varies from run to run */
+       OTM_SCATTER_SEGMENTED = 1 }; /* pairs sorted by node (influence lists),
+                                       fixed-order gather: bit-reproducible */
+/* constitutive model */
+enum { OTM_NEOHOOKE = 0,   /* compressible Neo-Hookean */
+       OTM_J2_JC = 1,      /* J2, Hencky, Johnson-Cook + adiabatic heating */
+       OTM_J2_LINEAR = 2 };/* J2, Hencky, linear isotropic hardening */
+
+/* Material, search, solver and contact parameters (host struct). */
+typedef struct otm_params {
+  int32_t model;          /* OTM_NEOHOOKE / OTM_J2_JC / OTM_J2_LINEAR */
+  int32_t wall_enabled;   /* rigid frictionless plane on/off */
+  double E, nu, rho0;     /* Young's modulus, Poisson ratio, reference density */
+  double A, B, n, C, m;   /* Johnson-Cook flow stress constants */
+  double eps_dot0;        /* JC reference plastic strain rate */
+  double T_r, T_m;        /* JC room and melting temperature */
+  double Cp, chi;         /* heat capacity, Taylor-Quinney coefficient */
+  double Y0, H;           /* linear hardening: initial yield, modulus */
+  double beta;            /* LME locality beta = gamma / h^2 */
+  double r_list;          /* support (search) radius, r_cut + skin */
+  double cell_size;       /* linked-cell edge, >= r_list */
+  double lme_tol;         /* LME stop: |sum N_I (x_p - x_I)|_2 <= lme_tol */
+  int32_t lme_max_iter;   /* LME Newton iteration cap */
+  int32_t rm_max_iter;    /* return-map Newton iteration cap */
+  double rm_tol;          /* return-map relative step / bracket tolerance */
+  double wall_x[3];       /* a point of the wall plane */
+  double wall_n[3];       /* unit normal of the wall, pointing into the body */
+  double eps_stab;        /* stabilisation penalty: must be 0 */
+  double body_force[3];   /* specific body force: must be 0 */
+} otm_params;
+
+/* Device state of one simulation (host struct of device pointers). */
+typedef struct otm_state {
+  int64_t n_nodes, n_mp;
+  int64_t pair_capacity;  /* length of nbr_idx and N; dN is [3][pair_capacity] */
+  int32_t precision;      /* OTM_FP64 or OTM_MIXED: types of the void* fields */
+  int32_t pad0;
+  /* nodes */
+  double* x;              /* [3][n_nodes] current positions */
+  double* du;             /* [3][n_nodes] displacement increment of the last step */
+  double* m;              /* [n_nodes] lumped mass */
+  double* f;              /* [3][n_nodes] internal force */
+  /* material points */
+  double* xp;             /* [3][n_mp] positions */
+  double* vol;            /* [n_mp] current volume */
+  const double* mass;     /* [n_mp] mass (constant) */
+  double* lam;            /* [3][n_mp] LME multiplier (warm start) */
+  void* Fd;               /* [9][n_mp] F - 1 (double, or float in OTM_MIXED) */
+  void* bed;              /* [6][n_mp] b^e - 1 (double / float) */
+  double* epsbar;         /* [n_mp] equivalent plastic strain */
+  double* T;              /* [n_mp] temperature */
+  void* sigma;            /* [6][n_mp] Cauchy stress (double / float) */
+  /* support lists and shape functions */
+  int64_t* nbr_offsets;   /* [n_mp+1] */
+  int32_t* nbr_idx;       /* [pair_capacity] */
+  double* N;              /* [pair_capacity] */
+  void* dN;               /* [3][pair_capacity] (double / float) */
+} otm_state;
+
+/* Device-side failure record (lives in device memory). */
+typedef struct otm_diag {
+  uint32_t flags;              /* bit k set <=> status -(k+1) happened */
+  int32_t max_support;         /* largest support size of the last search */
+  uint64_t n_lme_noconv, n_rm_noconv, n_inverted, n_nonfinite;
+  uint64_t first_lme_noconv;   /* smallest failing MP index (UINT64_MAX: none) */
+  uint64_t first_rm_noconv;
+  uint64_t first_inverted;
+  uint64_t first_nonfinite;
+  int64_t pairs_needed;        /* pair count of the last search */
+  int64_t reserved[3];
+} otm_diag;
+
+/* Human-readable name of a status code (static storage). */
+const char* otm_status_string(otm_status s);
+
+/* Bytes of workspace the calls below need for these sizes (256-aligned). */
+size_t otm_workspace_bytes(int64_t n_nodes, int64_t n_mp, int64_t pair_capacity);
+
+/* Clear a device otm_diag record (enqueued on s; graph-safe, no memset). */
+otm_status otm_diag_reset(otm_diag* diag, hipStream_t s);
+
+/* Synchronise s, copy the device record into *host_out (host) and return the
+ * status it encodes (the first failure kind in enum order, or OTM_OK). */
+otm_status otm_diag_read(const otm_diag* diag, otm_diag* host_out, hipStream_t s);
+
+/*
+ * Support-domain search (Sec. 3 linked-cell method, Alg. 3): for every MP p
+ * the nodes I with ((dx*dx + dy*dy) + dz*dz) <= r_list*r_list, dx = x_p - x_I,
+ * each operation rounded on its own (no fused multiply-add), so the lists
+ * are a function of the float64 inputs alone.  Nodes are binned into cells of
+ * edge cell_size (>= r_list; enlarged on the device if the node bounding box
+ * needs more cells than the workspace holds) and only the 27 cells around
+ * each MP's cell are tested.
+ *   x_nodes [3][n_nodes], x_mp [3][n_mp]: positions (device).
+ *   nbr_offsets [n_mp+1], nbr_idx [pair_capacity]: output CSR (device).
+ *   n_pairs_out (host): number of pairs found.
+ * Synchronises s once.  Returns OTM_ERR_CAPACITY (lists not written, count in
+ * *n_pairs_out) if more than pair_capacity pairs exist.
+ */
+otm_status otm_build_neighbors(int64_t n_nodes, const double* x_nodes, int64_t n_mp,
+                               const double* x_mp, double r_list, double cell_size,
+                               int64_t pair_capacity, int64_t* nbr_offsets, int32_t* nbr_idx,
+                               int64_t* n_pairs_out, void* ws, size_t ws_bytes, hipStream_t s);
+
+/*
+ * LME shape functions (Sec. 2.3): N_I = Z_I / Z with
+ * Z_I = exp(-beta |d_I|^2 + lambda . d_I), d_I = x_p - x_I, and lambda solving
+ * sum_I N_I d_I = 0 by damped Newton from the value in lam (in/out; zero for a
+ * cold start), stopping at |sum N_I d_I|_2 <= tol.  Gradients
+ * dN_I = -N_I J^{-1} d_I with J = sum N_I d_I d_I^T - r r^T (the derivative of
+ * the consistency condition; not printed in the paper).  Always float64
+ * arithmetic; dN is written as double (OTM_FP64) or float (OTM_MIXED) with
+ * component stride pair_capacity.  Non-convergence is recorded in diag.
+ */
+otm_status otm_lme_shape(int64_t n_nodes, const double* x_nodes, int64_t n_mp,
+                         const double* x_mp, const int64_t* nbr_offsets, const int32_t* nbr_idx,
+                         int64_t pair_capacity, double beta, double tol, int32_t max_iter,
+                         double* lam, double* N, void* dN, int32_t precision, otm_diag* diag,
+                         hipStream_t s);
+
+/*
+ * Start a simulation (t = 0): F = b^e = 1, epsbar = 0, T = T_r, sigma = 0,
+ * lam = 0, vol left as given (initial MP volumes), du = dt * v0 (v0 [3][n_nodes]
+ * device, the nodal initial velocity), then search, shape functions and the
+ * first mass/force assembly, so that otm_step can follow.
+ */
+otm_status otm_init(otm_state* st, const otm_params* p, double dt, const double* v0,
+                    int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
+                    hipStream_t s);
+
+/*
+ * Recompute support lists (if rebuild), shape functions and the nodal
+ * mass/force for the current positions and stress (e.g. after a capacity
+ * failure was fixed by a larger pair buffer).
+ */
+otm_status otm_refresh(otm_state* st, const otm_params* p, int32_t rebuild,
+                       int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
+                       hipStream_t s);
+
+/*
+ * One explicit step n -> n+1 (Alg. 1, rotated so that the mass/force assembly
+ * closes the step), state updated in place:
+ *   nodes   du += dt^2 f / m; x* = x + du; wall projection; x = x*
+ *   MPs     x_p = sum N_I x_I; dF = 1 + sum du_I (x) grad N_I; F = dF F;
+ *           v = det(dF) v; constitutive update (model in p)
+ *   search  if rebuild != 0 (else the lists of step n are kept; with a skin
+ *           in r_list they stay valid for several steps)
+ *   shapes  LME at the new MP positions (warm-started multipliers)
+ *   forces  m_I = sum N_I m_p;  f_I = -sum v_p sigma_p grad N_I
+ * scatter_mode selects the force assembly; the segmented mode keeps its
+ * influence lists in the workspace, so pass the same workspace on every call.
+ */
+otm_status otm_step(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
+                    int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
+                    hipStream_t s);
+
+/*
+ * otm_step with phase markers: events[k] (host array of 7 caller-created
+ * hipEvent_t; a NULL entry is skipped) is recorded on s at the start of
+ * phase k: 0 node update, 1 MP update, 2 search (or the point where it would
+ * run), 3 shape functions, 4 assembly (atomic mode) or influence lists
+ * (segmented mode), 5 segmented gather (segmented mode only), 6 end of step.
+ * Same work and results as otm_step.
+ */
+otm_status otm_step_profiled(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
+                             int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
+                             hipEvent_t* events, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OTM_H */

@@ -25,8 +25,8 @@ Readings adopted where the printed formulas are garbled or silent:
   converged Kirchhoff equivalent stress with rho0 (tau_v / rho0 equals
   sigma_v / rho);
 * the scalar return equation is solved by Newton safeguarded by bisection on
-  [0, (q_tr - sigma_Y0) / (3 mu)], stopping when the step or the bracket is
-  below 1e-15 of the iterate.
+  [0, (q_tr - sigma_Y0) / (3 mu)], stopping when its residual is below 1e-14
+  q_tr or the step or the bracket is below 1e-14 of the iterate.
 """
 from __future__ import annotations
 
@@ -142,14 +142,17 @@ def homologous_T(p, T):
     return np.where(ts.real < 0, 0.0 * ts, np.where(ts.real > 1, 1.0 + 0.0 * ts, ts))
 
 
-def solve_return(p, q_tr, epsbar, Tstar, dt, mu, tol=1e-15, max_iter=60, polish=0):
+def solve_return(p, q_tr, epsbar, Tstar, dt, mu, tol=1e-14, max_iter=60, polish=0):
     """Root of g(x) = q_tr - 3 mu x - sigma_Y(epsbar + x, x/dt, T*) on
     (0, x0], x0 = (q_tr - sigma_Y(epsbar, 0, T*)) / (3 mu), for MPs that
     yield; g is strictly decreasing so the root is unique.
 
-    Newton from x0, bracket kept on sign of g, bisection when the Newton
-    iterate leaves the bracket.  ``polish`` extra Newton steps after
-    convergence (complex-step runs)."""
+    Newton from x0, bracket kept on the sign of g, bisection when the Newton
+    iterate leaves the bracket.  Stops when the residual is at the rounding
+    level, |g| <= tol q_tr (the only test that can end the iteration for MPs
+    that barely yield, where the root is tiny), or when the Newton step or
+    the bracket is below tol of the iterate.  ``polish`` extra Newton steps
+    after convergence (complex-step runs)."""
     sy0, _ = flow_stress(p, epsbar, 0.0 * q_tr, dt, Tstar)
     x = (q_tr - sy0) / (3 * mu)
     lo = np.zeros_like(x.real)
@@ -160,16 +163,19 @@ def solve_return(p, q_tr, epsbar, Tstar, dt, mu, tol=1e-15, max_iter=60, polish=
         sy, dsy = flow_stress(p, epsbar, x, dt, Tstar)
         g = q_tr - 3 * mu * x - sy
         gp = -3 * mu - dsy
-        lo = np.where(~done & (g.real > 0), x.real, lo)
-        hi = np.where(~done & (g.real <= 0), x.real, hi)
-        xn = x - g / gp
-        outside = ~((xn.real > lo) & (xn.real < hi)) & ~done
-        xn = np.where(outside, 0.5 * (lo + hi), xn)
-        small = (np.abs(xn.real - x.real) <= tol * np.abs(xn.real)) | (hi - lo <= tol * hi)
         polishing = done & (left > 0)
         left = np.where(polishing, left - 1, left)
-        x = np.where(~done | polishing, xn, x)
-        done = done | small
+        resid_ok = ~done & (np.abs(g.real) <= tol * q_tr.real)
+        done = done | resid_ok
+        active = ~done
+        lo = np.where(active & (g.real > 0), x.real, lo)
+        hi = np.where(active & (g.real <= 0), x.real, hi)
+        xn = x - g / gp
+        outside = ~((xn.real > lo) & (xn.real < hi)) & active
+        xn = np.where(outside, 0.5 * (lo + hi), xn)
+        small = (np.abs(xn.real - x.real) <= tol * np.abs(xn.real)) | (hi - lo <= tol * hi)
+        x = np.where(active | polishing, xn, x)
+        done = done | (active & small)
         if done.all() and not (left > 0).any():
             break
     if not done.all():
@@ -203,7 +209,7 @@ def j2_update(p, dF, be_n, epsbar_n, T_n, J_new, dt, spectral="eigh", polish=0):
     if plastic.any():
         ip = np.nonzero(plastic)[0]
         x, _ = solve_return(p, q_tr[ip], epsbar_n[ip], Tstar[ip], dt, mu,
-                            tol=p.get("rm_tol", 1e-15), max_iter=p.get("rm_max_iter", 60),
+                            tol=p.get("rm_tol", 1e-14), max_iter=p.get("rm_max_iter", 60),
                             polish=polish)
         deps = deps.astype(x.dtype)
         deps[ip] = x

@@ -63,20 +63,6 @@ class State:
                         for k, v in dataclasses.asdict(self).items()})
 
 
-def params_from_workload(w, **over):
-    """Flat parameter dict from a workload object (duck-typed)."""
-    mat = w.material
-    p = dict(model=mat.model, E=mat.E, nu=mat.nu, rho0=mat.rho0, A=mat.A, B=mat.B,
-             n=mat.n, C=mat.C, m=mat.m, eps_dot0=mat.eps_dot0, T_r=mat.T_r, T_m=mat.T_m,
-             Cp=mat.Cp, chi=mat.chi, Y0=mat.Y0, H=mat.H,
-             beta=w.beta, r_list=w.r_list, cell_size=w.r_list * 1.0001,
-             lme_tol=1e-13 * w.h, lme_max_iter=50, rm_tol=1e-15, rm_max_iter=60,
-             wall=bool(w.wall), wall_x=np.array(w.wall_x, float),
-             wall_n=np.array(w.wall_n, float), dt=w.dt, rebuild_every=w.rebuild_every)
-    p.update(over)
-    return p
-
-
 # ------------------------------------------------------------------ pieces
 def assemble(st, p):
     """Lumped nodal mass and internal force (nodal mass / residual equations),

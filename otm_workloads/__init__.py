@@ -1,4 +1,4 @@
-"""Seeded synthetic workloads for the explicit OTM step.
+"""Seeded synthetic workloads for the explicit OTM step (inputs only).
 
 This module only builds inputs: a jittered node lattice, the tetrahedra of its
 hex cells, one material point (MP) at each tet centroid with the tet volume,
@@ -14,7 +14,8 @@ published with it, so every workload here is a same-shape stand-in:
   slowest and x fastest, each coordinate jittered by U(-0.1 h, 0.1 h) in one
   seeded draw of shape (n_nodes, 3);
 * every hex cell whose 8 corners are present is split into the 6 Kuhn tets
-  around its (0,0,0)-(1,1,1) diagonal;
+  around its (0,0,0)-(1,1,1) diagonal; lattice points that are the corner of
+  no such cell are dropped (they would be nodes without mass);
 * one MP per tet at the centroid, volume |det| / 6, mass rho0 * volume,
   ordered hex-cell-major then by tet index (so MPs that are close in space are
   close in memory).
@@ -145,6 +146,13 @@ def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False):
     corners = corners[full]
     tet_nodes = corners[:, np.array(KUHN_TETS)]          # (n_hex, 6, 4)
     tet_nodes = tet_nodes.reshape(-1, 4)
+    # lattice points that belong to no complete hex cell would carry no mass
+    # of their own: keep only the corners of the tets (order preserved)
+    used = np.zeros(x.shape[0], dtype=bool)
+    used[tet_nodes.ravel()] = True
+    renum = np.cumsum(used) - 1
+    x, X = x[used], X[used]
+    tet_nodes = renum[tet_nodes]
     p = x[tet_nodes]                                       # (n_mp, 4, 3)
     x_mp = p.mean(axis=1)
     e = p[:, 1:, :] - p[:, :1, :]
@@ -230,3 +238,19 @@ def random_cloud(n_nodes, n_mp, seed, box=1.0):
     """Uniform random nodes and MPs in a cube (search tests)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(0, box, (n_nodes, 3)), rng.uniform(0, box, (n_mp, 3))
+
+
+def params_from_workload(w, **over):
+    """Flat parameter dict of a workload: material constants, LME locality,
+    search radius and cell edge, solver tolerances, wall and time step.  Both
+    the oracle and the GPU library take their parameters from this dict."""
+    mat = w.material
+    p = dict(model=mat.model, E=mat.E, nu=mat.nu, rho0=mat.rho0, A=mat.A, B=mat.B,
+             n=mat.n, C=mat.C, m=mat.m, eps_dot0=mat.eps_dot0, T_r=mat.T_r, T_m=mat.T_m,
+             Cp=mat.Cp, chi=mat.chi, Y0=mat.Y0, H=mat.H,
+             beta=w.beta, r_list=w.r_list, cell_size=w.r_list * 1.0001,
+             lme_tol=1e-14 * w.h, lme_max_iter=50, rm_tol=1e-14, rm_max_iter=60,
+             wall=bool(w.wall), wall_x=np.array(w.wall_x, float),
+             wall_n=np.array(w.wall_n, float), dt=w.dt, rebuild_every=w.rebuild_every)
+    p.update(over)
+    return p

@@ -1,0 +1,296 @@
+// C ABI of libotm: argument checks, workspace layout and the launch sequence
+// of each entry point on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include "launch.h"
+#include "otm_common.h"
+
+namespace otm {
+
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t carve_workspace(void* base, size_t bytes, int64_t n_nodes, int64_t n_mp,
+                       int64_t pair_capacity, Workspace* w) {
+  const int64_t cap_cells = (n_nodes > 0 ? n_nodes : 0) + 1024;
+  int64_t scan_n = n_mp + 1;
+  if (cap_cells + 1 > scan_n) scan_n = cap_cells + 1;
+  if (n_nodes + 1 > scan_n) scan_n = n_nodes + 1;
+  const int64_t scan_blocks = (scan_n + kScanBlock - 1) / kScanBlock + 1;
+  const size_t sizes[] = {
+      align256(sizeof(Grid)),
+      align256(sizeof(double) * 6 * kBBoxBlocks),
+      align256(sizeof(int32_t) * (cap_cells + 1)),
+      align256(sizeof(int32_t) * cap_cells),
+      align256(sizeof(int32_t) * (size_t)n_nodes),
+      align256(sizeof(double4) * (size_t)n_nodes),
+      align256(sizeof(int64_t) * (size_t)scan_blocks),
+      align256(sizeof(int32_t) * (size_t)(n_mp / 64 + 2)),
+      align256(sizeof(int64_t) * (size_t)(n_nodes + 1)),
+      align256(sizeof(int32_t) * (size_t)n_nodes),
+      align256(sizeof(int32_t) * (size_t)pair_capacity),
+      align256(sizeof(int32_t) * (size_t)pair_capacity),
+      align256(sizeof(int32_t) * (size_t)kRowCapacity * (size_t)n_mp),
+      align256(sizeof(double4) * 2 * (size_t)n_nodes),
+  };
+  size_t total = 0;
+  for (size_t s : sizes) total += s;
+  if (base == nullptr || bytes < total || w == nullptr) return total;
+  char* c = (char*)base;
+  size_t o = 0;
+  auto take = [&](int k) { void* r = c + o; o += sizes[k]; return r; };
+  w->grid = (Grid*)take(0);
+  w->bbox_part = (double*)take(1);
+  w->cap_cells = cap_cells;
+  w->cell_start = (int32_t*)take(2);
+  w->cell_cursor = (int32_t*)take(3);
+  w->node_cell = (int32_t*)take(4);
+  w->sorted = (double4*)take(5);
+  w->scan_aux = (int64_t*)take(6);
+  w->block_max = (int32_t*)take(7);
+  w->tr_start = (int64_t*)take(8);
+  w->tr_cursor = (int32_t*)take(9);
+  w->tr_pairs = (int32_t*)take(10);
+  w->pair_mp = (int32_t*)take(11);
+  w->stage = (int32_t*)take(12);
+  w->nodes = (double4*)take(13);
+  return total;
+}
+
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+static bool dev_ok(const void* p, size_t a) { return p != nullptr && aligned(p, a); }
+
+static otm_status hip_status() {
+  return hipGetLastError() == hipSuccess ? OTM_OK : OTM_ERR_HIP;
+}
+
+static otm_status check_workspace(void* ws, size_t ws_bytes, int64_t n_nodes, int64_t n_mp,
+                                  int64_t cap, Workspace* w) {
+  if (ws == nullptr || !aligned(ws, 256)) return OTM_ERR_ARG;
+  const size_t need = carve_workspace(nullptr, 0, n_nodes, n_mp, cap, nullptr);
+  if (ws_bytes < need) return OTM_ERR_ARG;
+  carve_workspace(ws, ws_bytes, n_nodes, n_mp, cap, w);
+  return OTM_OK;
+}
+
+static otm_status check_params(const otm_params* p) {
+  if (p == nullptr) return OTM_ERR_ARG;
+  if (p->model < OTM_NEOHOOKE || p->model > OTM_J2_LINEAR) return OTM_ERR_ARG;
+  if (!(p->r_list > 0) || !(p->cell_size >= p->r_list) || !(p->beta > 0)) return OTM_ERR_ARG;
+  if (!(p->lme_tol > 0) || p->lme_max_iter < 1 || p->rm_max_iter < 1) return OTM_ERR_ARG;
+  if (!(p->E > 0) || !(p->nu > -1.0 && p->nu < 0.5) || !(p->rho0 > 0)) return OTM_ERR_ARG;
+  if (p->eps_stab != 0.0) return OTM_ERR_ARG;
+  if (p->body_force[0] != 0.0 || p->body_force[1] != 0.0 || p->body_force[2] != 0.0)
+    return OTM_ERR_ARG;
+  if (p->model == OTM_J2_JC && !(p->T_m > p->T_r && p->Cp > 0 && p->eps_dot0 > 0))
+    return OTM_ERR_ARG;
+  if (p->wall_enabled) {
+    const double nn = p->wall_n[0] * p->wall_n[0] + p->wall_n[1] * p->wall_n[1] +
+                      p->wall_n[2] * p->wall_n[2];
+    if (!(fabs(nn - 1.0) < 1e-12)) return OTM_ERR_ARG;
+  }
+  return OTM_OK;
+}
+
+static otm_status check_state(const otm_state* st) {
+  if (st == nullptr) return OTM_ERR_ARG;
+  if (st->n_nodes < 0 || st->n_mp < 0 || st->pair_capacity < 0) return OTM_ERR_ARG;
+  if (st->pair_capacity >= (int64_t(1) << 31)) return OTM_ERR_ARG;  // int32 pair ids
+  if (st->n_nodes >= (int64_t(1) << 31) || st->n_mp >= (int64_t(1) << 31)) return OTM_ERR_ARG;
+  if (st->precision != OTM_FP64 && st->precision != OTM_MIXED) return OTM_ERR_ARG;
+  const size_t rs = st->precision == OTM_FP64 ? 8 : 4;
+  if (!dev_ok(st->x, 8) || !dev_ok(st->du, 8) || !dev_ok(st->m, 8) || !dev_ok(st->f, 8))
+    return OTM_ERR_ARG;
+  if (!dev_ok(st->xp, 8) || !dev_ok(st->vol, 8) || !dev_ok(st->mass, 8) ||
+      !dev_ok(st->lam, 8) || !dev_ok(st->epsbar, 8) || !dev_ok(st->T, 8))
+    return OTM_ERR_ARG;
+  if (!dev_ok(st->Fd, rs) || !dev_ok(st->bed, rs) || !dev_ok(st->sigma, rs) ||
+      !dev_ok(st->dN, rs))
+    return OTM_ERR_ARG;
+  if (!dev_ok(st->nbr_offsets, 8) || !dev_ok(st->nbr_idx, 4) || !dev_ok(st->N, 8))
+    return OTM_ERR_ARG;
+  return OTM_OK;
+}
+
+static void mark(hipEvent_t* ev, int k, hipStream_t s) {
+  if (ev != nullptr && ev[k] != nullptr) (void)hipEventRecord(ev[k], s);
+}
+
+// search (optional) + shape functions + mass/force assembly
+// (packed: the node records in the workspace are current)
+static void refresh_impl(otm_state& st, const otm_params& p, bool rebuild, int32_t mode,
+                         const Workspace& w, otm_diag* diag, hipStream_t s,
+                         hipEvent_t* ev = nullptr, bool packed = false) {
+  if (!packed) launch_pack_nodes(st, w.nodes, s);
+  if (rebuild)
+    launch_search(st.n_nodes, st.x, st.n_mp, st.xp, p.r_list, p.cell_size, st.pair_capacity,
+                  st.nbr_offsets, st.nbr_idx, w, diag, s);
+  mark(ev, 3, s);
+  launch_lme(st.n_nodes, st.x, st.n_mp, st.xp, st.nbr_offsets, st.nbr_idx, st.pair_capacity,
+             p.beta, p.lme_tol, p.lme_max_iter, st.lam, st.N, st.dN, st.precision, w.nodes, diag,
+             s);
+  mark(ev, 4, s);
+  if (mode == OTM_SCATTER_ATOMIC) {
+    launch_assemble_atomic(st, s);
+  } else {
+    if (rebuild) launch_influence_lists(st, w, s);
+    mark(ev, 5, s);
+    launch_scatter_segmented(st, w, s);
+  }
+  mark(ev, 6, s);
+}
+
+}  // namespace otm
+
+using namespace otm;
+
+extern "C" {
+
+const char* otm_status_string(otm_status s) {
+  switch (s) {
+    case OTM_OK: return "OTM_OK";
+    case OTM_ERR_ARG: return "OTM_ERR_ARG: invalid argument";
+    case OTM_ERR_CAPACITY: return "OTM_ERR_CAPACITY: more support pairs than pair_capacity";
+    case OTM_ERR_LME_NOCONV: return "OTM_ERR_LME_NOCONV: LME Newton did not converge";
+    case OTM_ERR_RM_NOCONV: return "OTM_ERR_RM_NOCONV: return map did not converge";
+    case OTM_ERR_INVERTED: return "OTM_ERR_INVERTED: det(dF) <= 0 at a material point";
+    case OTM_ERR_NONFINITE: return "OTM_ERR_NONFINITE: non-finite stress or position";
+    case OTM_ERR_HIP: return "OTM_ERR_HIP: HIP runtime error";
+    default: return "unknown otm_status";
+  }
+}
+
+size_t otm_workspace_bytes(int64_t n_nodes, int64_t n_mp, int64_t pair_capacity) {
+  if (n_nodes < 0 || n_mp < 0 || pair_capacity < 0) return 0;
+  return carve_workspace(nullptr, 0, n_nodes, n_mp, pair_capacity, nullptr);
+}
+
+otm_status otm_diag_reset(otm_diag* diag, hipStream_t s) {
+  if (!dev_ok(diag, 8)) return OTM_ERR_ARG;
+  launch_diag_reset(diag, s);
+  return hip_status();
+}
+
+otm_status otm_diag_read(const otm_diag* diag, otm_diag* host_out, hipStream_t s) {
+  if (!dev_ok(diag, 8) || host_out == nullptr) return OTM_ERR_ARG;
+  if (hipMemcpyAsync(host_out, diag, sizeof(otm_diag), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return OTM_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return OTM_ERR_HIP;
+  for (int k = 0; k < 7; ++k)
+    if (host_out->flags & (1u << k)) return (otm_status)(-(k + 1));
+  return OTM_OK;
+}
+
+otm_status otm_build_neighbors(int64_t n_nodes, const double* x_nodes, int64_t n_mp,
+                               const double* x_mp, double r_list, double cell_size,
+                               int64_t pair_capacity, int64_t* nbr_offsets, int32_t* nbr_idx,
+                               int64_t* n_pairs_out, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (n_nodes < 0 || n_mp < 0 || pair_capacity < 0 || n_pairs_out == nullptr) return OTM_ERR_ARG;
+  if (pair_capacity >= (int64_t(1) << 31) || n_nodes >= (int64_t(1) << 31)) return OTM_ERR_ARG;
+  if (!(r_list > 0) || !(cell_size >= r_list)) return OTM_ERR_ARG;
+  if ((n_nodes > 0 && !dev_ok(x_nodes, 8)) || (n_mp > 0 && !dev_ok(x_mp, 8)) ||
+      !dev_ok(nbr_offsets, 8) || (pair_capacity > 0 && !dev_ok(nbr_idx, 4)))
+    return OTM_ERR_ARG;
+  Workspace w;
+  if (check_workspace(ws, ws_bytes, n_nodes, n_mp, pair_capacity, &w) != OTM_OK) return OTM_ERR_ARG;
+  if (n_nodes == 0) {
+    // no nodes: every support is empty
+    launch_fill_i64(nbr_offsets, n_mp + 1, 0, s);
+    *n_pairs_out = 0;
+    return hipStreamSynchronize(s) == hipSuccess ? hip_status() : OTM_ERR_HIP;
+  }
+  launch_search(n_nodes, x_nodes, n_mp, x_mp, r_list, cell_size, pair_capacity, nbr_offsets,
+                nbr_idx, w, nullptr, s);
+  if (hip_status() != OTM_OK) return OTM_ERR_HIP;
+  int64_t P = 0;
+  if (hipMemcpyAsync(&P, nbr_offsets + n_mp, sizeof(int64_t), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return OTM_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return OTM_ERR_HIP;
+  *n_pairs_out = P;
+  return P > pair_capacity ? OTM_ERR_CAPACITY : OTM_OK;
+}
+
+otm_status otm_lme_shape(int64_t n_nodes, const double* x_nodes, int64_t n_mp,
+                         const double* x_mp, const int64_t* nbr_offsets, const int32_t* nbr_idx,
+                         int64_t pair_capacity, double beta, double tol, int32_t max_iter,
+                         double* lam, double* N, void* dN, int32_t precision, otm_diag* diag,
+                         hipStream_t s) {
+  if (n_nodes < 0 || n_mp < 0 || pair_capacity < 0) return OTM_ERR_ARG;
+  if (!(beta > 0) || !(tol > 0) || max_iter < 1) return OTM_ERR_ARG;
+  if (precision != OTM_FP64 && precision != OTM_MIXED) return OTM_ERR_ARG;
+  const size_t rs = precision == OTM_FP64 ? 8 : 4;
+  if (n_mp == 0) return OTM_OK;
+  if (!dev_ok(x_nodes, 8) || !dev_ok(x_mp, 8) || !dev_ok(nbr_offsets, 8) || !dev_ok(lam, 8))
+    return OTM_ERR_ARG;
+  if (pair_capacity > 0 && (!dev_ok(nbr_idx, 4) || !dev_ok(N, 8) || !dev_ok(dN, rs)))
+    return OTM_ERR_ARG;
+  if (diag != nullptr && !aligned(diag, 8)) return OTM_ERR_ARG;
+  launch_lme(n_nodes, x_nodes, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity, beta, tol,
+             max_iter, lam, N, dN, precision, nullptr, diag, s);
+  return hip_status();
+}
+
+otm_status otm_refresh(otm_state* st, const otm_params* p, int32_t rebuild, int32_t scatter_mode,
+                       void* ws, size_t ws_bytes, otm_diag* diag, hipStream_t s) {
+  otm_status e;
+  if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
+  if (scatter_mode != OTM_SCATTER_ATOMIC && scatter_mode != OTM_SCATTER_SEGMENTED)
+    return OTM_ERR_ARG;
+  if (!dev_ok(diag, 8)) return OTM_ERR_ARG;
+  Workspace w;
+  if (check_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &w) != OTM_OK)
+    return OTM_ERR_ARG;
+  if (scatter_mode == OTM_SCATTER_ATOMIC) {
+    launch_zero(st->m, st->n_nodes, s);
+    launch_zero(st->f, 3 * st->n_nodes, s);
+  }
+  refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s);
+  return hip_status();
+}
+
+otm_status otm_init(otm_state* st, const otm_params* p, double dt, const double* v0,
+                    int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
+                    hipStream_t s) {
+  otm_status e;
+  if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
+  if (!(dt > 0) || (st->n_nodes > 0 && !dev_ok(v0, 8))) return OTM_ERR_ARG;
+  launch_init_fields(*st, *p, dt, v0, s);
+  return otm_refresh(st, p, 1, scatter_mode, ws, ws_bytes, diag, s);
+}
+
+static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
+                            int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
+                            hipEvent_t* ev, hipStream_t s) {
+  otm_status e;
+  if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
+  if (!(dt > 0)) return OTM_ERR_ARG;
+  if (scatter_mode != OTM_SCATTER_ATOMIC && scatter_mode != OTM_SCATTER_SEGMENTED)
+    return OTM_ERR_ARG;
+  if (!dev_ok(diag, 8)) return OTM_ERR_ARG;
+  Workspace w;
+  if (check_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &w) != OTM_OK)
+    return OTM_ERR_ARG;
+  mark(ev, 0, s);
+  launch_node_update(*st, *p, dt, scatter_mode == OTM_SCATTER_ATOMIC, w.nodes, s);
+  mark(ev, 1, s);
+  launch_mp_update(*st, *p, dt, w.nodes, diag, s);
+  mark(ev, 2, s);
+  refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true);
+  return hip_status();
+}
+
+otm_status otm_step(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
+                    int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
+                    hipStream_t s) {
+  return step_impl(st, p, dt, rebuild, scatter_mode, ws, ws_bytes, diag, nullptr, s);
+}
+
+otm_status otm_step_profiled(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
+                             int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
+                             hipEvent_t* events, hipStream_t s) {
+  if (events == nullptr) return OTM_ERR_ARG;
+  return step_impl(st, p, dt, rebuild, scatter_mode, ws, ws_bytes, diag, events, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Internal host-side launchers and workspace layout of libotm (not exported).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "otm.h"
+
+namespace otm {
+
+// Linked-cell grid parameters, computed on the device from the node bounding
+// box so that no host round trip is needed.
+struct Grid {
+  double lo[3];
+  double cell;
+  int32_t dims[3];
+  int32_t pad;
+  int64_t n_cells;
+};
+
+constexpr int kBBoxBlocks = 256;
+constexpr int kScanBlock = 4096;  // elements per scan workgroup (1024 threads x 4)
+constexpr int kRowCapacity = 40;  // search rows staged per MP before compaction
+
+struct Workspace {
+  Grid* grid;
+  double* bbox_part;     // [kBBoxBlocks][6]
+  int64_t cap_cells;
+  int32_t* cell_start;   // [cap_cells + 1]
+  int32_t* cell_cursor;  // [cap_cells]
+  int32_t* node_cell;    // [n_nodes]
+  double4* sorted;       // [n_nodes]: x, y, z, node id
+  int64_t* scan_aux;     // scan partial sums (int64 view)
+  int32_t* block_max;    // [n_mp / 64 + 1] largest support per search workgroup
+  int64_t* tr_start;     // [n_nodes + 1] influence-list offsets
+  int32_t* tr_cursor;    // [n_nodes]
+  int32_t* tr_pairs;     // [pair_capacity] pair ids sorted by node, then pair
+  int32_t* pair_mp;      // [pair_capacity] MP of each pair
+  int32_t* stage;        // [kRowCapacity][n_mp] sorted rows of the one-pass search
+  double4* nodes;        // [2 n_nodes] packed node records
+};
+
+// Lays the workspace out over [base, base + bytes).  Returns the bytes needed
+// (the layout is only written when base != nullptr and bytes suffice).
+size_t carve_workspace(void* base, size_t bytes, int64_t n_nodes, int64_t n_mp,
+                       int64_t pair_capacity, Workspace* w);
+
+// In-place inclusive prefix sums.
+void scan_inclusive(int64_t* a, int64_t n, int64_t* aux, hipStream_t s);
+void scan_inclusive(int32_t* a, int64_t n, int64_t* aux, hipStream_t s);
+
+// Search: counts into nbr_offsets, scans, and (fill) writes sorted lists if the
+// total fits pair_capacity.  Never synchronises.
+void launch_search(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const double* x_mp,
+                   double r_list, double cell_size, int64_t pair_capacity, int64_t* nbr_offsets,
+                   int32_t* nbr_idx, const Workspace& w, otm_diag* diag, hipStream_t s);
+
+// LME shape functions (float64 Newton; dN stored per precision).
+// ``packed`` (nullable): node records (x, y, z, 0) at even indices.
+void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const double* x_mp,
+                const int64_t* nbr_offsets, const int32_t* nbr_idx, int64_t pair_capacity,
+                double beta, double tol, int32_t max_iter, double* lam, double* N, void* dN,
+                int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s);
+
+// Nodes and material points.
+// Node records: packed[2 I] = (x, y, z, 0), packed[2 I + 1] = (du, 0).
+void launch_node_update(const otm_state& st, const otm_params& p, double dt, bool zero_mf,
+                        double4* packed, hipStream_t s);
+void launch_pack_nodes(const otm_state& st, double4* packed, hipStream_t s);
+void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
+                      const double4* packed, otm_diag* diag, hipStream_t s);
+void launch_init_fields(const otm_state& st, const otm_params& p, double dt, const double* v0,
+                        hipStream_t s);
+void launch_zero(double* a, int64_t n, hipStream_t s);
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s);
+void launch_fill_i64(int64_t* a, int64_t n, int64_t v, hipStream_t s);
+
+// Segmented (deterministic) assembly.
+void launch_influence_lists(const otm_state& st, const Workspace& w, hipStream_t s);
+void launch_scatter_segmented(const otm_state& st, const Workspace& w, hipStream_t s);
+// Atomic assembly (m and f must be zero beforehand).
+void launch_assemble_atomic(const otm_state& st, hipStream_t s);
+
+void launch_diag_reset(otm_diag* d, hipStream_t s);
+
+}  // namespace otm

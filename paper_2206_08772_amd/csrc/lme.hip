@@ -1,0 +1,257 @@
+// Local max-ent shape functions (Sec. 2.3) by a per-material-point damped
+// Newton solve for the Lagrange multiplier, in float64.
+//
+// A group of G lanes works on one MP; each lane keeps up to PPL of the MP's
+// pairs in registers (offset d = x_p - x_I and the prior -beta |d|^2), so one
+// Newton evaluation costs one exp per pair and 10 group reductions
+// (Z, r, S = sum e d d^T) by butterfly shuffles.  The 3x3 solve is repeated
+// in every lane of the group, so the group never diverges.  MPs with longer
+// supports than G*PPL take the same iteration with pairs re-read from memory.
+//
+// Newton reading (the paper gives none): start from the previous multiplier;
+// step -J^{-1} r with J = sum N d d^T - r r^T; Armijo backtracking on log Z
+// with sufficient-decrease factor 1e-4 plus a round-off allowance
+// 1e-12 (1 + |log Z|), up to 30 halvings; stop at |r|_2 <= tol.  Gradients
+// dN_I = -N_I J^{-1} d_I at the converged multiplier.
+#include "launch.h"
+#include "otm_common.h"
+
+namespace otm {
+
+// Node coordinates: SoA arrays, or the packed (x, y, z, 0) records the step
+// keeps in its workspace (one 32-byte load per node).
+struct NodeSrc {
+  const double* x;       // [3][n] (used when packed == nullptr)
+  const double4* packed; // record 2 I = (x, y, z, 0)
+  int64_t n;
+};
+OTM_DEV void node_xyz(const NodeSrc& s, int32_t I, double& a, double& b, double& c) {
+  if (s.packed != nullptr) {
+    const double4 v = s.packed[2 * (int64_t)I];
+    a = v.x; b = v.y; c = v.z;
+  } else {
+    a = s.x[I]; b = s.x[s.n + I]; c = s.x[2 * s.n + I];
+  }
+}
+
+struct Eval {
+  double logZ, Z, fmax;
+  double r[3];
+  double J[6];  // xx yy zz xy yz xz
+};
+
+template <int G, int PPL, bool CACHED>
+struct Pairs {
+  // cached offsets and priors (CACHED only)
+  double d[CACHED ? PPL : 1][3];
+  double prior[CACHED ? PPL : 1];
+};
+
+template <int G, int PPL, bool CACHED>
+OTM_DEV void lme_eval(const Pairs<G, PPL, CACHED>& pr, int lane, int K, int64_t off,
+                      const double px, const double py, const double pz, const NodeSrc& ns,
+                      const int32_t* __restrict__ idx, double beta, const double lam[3],
+                      Eval& ev, double ek[CACHED ? PPL : 1]) {
+  double fm = -INFINITY;
+  if constexpr (CACHED) {
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      if (k * G + lane < K) {
+        ek[k] = pr.prior[k] + (lam[0] * pr.d[k][0] + lam[1] * pr.d[k][1] + lam[2] * pr.d[k][2]);
+        fm = fmax(fm, ek[k]);
+      }
+    }
+  } else {
+    for (int q = lane; q < K; q += G) {
+      const int32_t I = idx[off + q];
+      double nx, ny, nz;
+      node_xyz(ns, I, nx, ny, nz);
+      const double dx = px - nx, dy = py - ny, dz = pz - nz;
+      const double f = -beta * ((dx * dx + dy * dy) + dz * dz) + (lam[0] * dx + lam[1] * dy + lam[2] * dz);
+      fm = fmax(fm, f);
+    }
+  }
+  fm = group_max<G>(fm);
+  double Z = 0, r0 = 0, r1 = 0, r2 = 0, s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+  auto accum = [&](double e, double dx, double dy, double dz) {
+    Z += e;
+    r0 += e * dx; r1 += e * dy; r2 += e * dz;
+    s0 += e * dx * dx; s1 += e * dy * dy; s2 += e * dz * dz;
+    s3 += e * dx * dy; s4 += e * dy * dz; s5 += e * dx * dz;
+  };
+  if constexpr (CACHED) {
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      if (k * G + lane < K) {
+        ek[k] = exp(ek[k] - fm);
+        accum(ek[k], pr.d[k][0], pr.d[k][1], pr.d[k][2]);
+      }
+    }
+  } else {
+    for (int q = lane; q < K; q += G) {
+      const int32_t I = idx[off + q];
+      double nx, ny, nz;
+      node_xyz(ns, I, nx, ny, nz);
+      const double dx = px - nx, dy = py - ny, dz = pz - nz;
+      const double f = -beta * ((dx * dx + dy * dy) + dz * dz) + (lam[0] * dx + lam[1] * dy + lam[2] * dz);
+      accum(exp(f - fm), dx, dy, dz);
+    }
+  }
+  Z = group_sum<G>(Z);
+  r0 = group_sum<G>(r0); r1 = group_sum<G>(r1); r2 = group_sum<G>(r2);
+  s0 = group_sum<G>(s0); s1 = group_sum<G>(s1); s2 = group_sum<G>(s2);
+  s3 = group_sum<G>(s3); s4 = group_sum<G>(s4); s5 = group_sum<G>(s5);
+  const double iz = 1.0 / Z;
+  ev.Z = Z;
+  ev.fmax = fm;
+  ev.logZ = log(Z) + fm;
+  ev.r[0] = r0 * iz; ev.r[1] = r1 * iz; ev.r[2] = r2 * iz;
+  ev.J[0] = s0 * iz - ev.r[0] * ev.r[0];
+  ev.J[1] = s1 * iz - ev.r[1] * ev.r[1];
+  ev.J[2] = s2 * iz - ev.r[2] * ev.r[2];
+  ev.J[3] = s3 * iz - ev.r[0] * ev.r[1];
+  ev.J[4] = s4 * iz - ev.r[1] * ev.r[2];
+  ev.J[5] = s5 * iz - ev.r[0] * ev.r[2];
+}
+
+template <typename DN>
+OTM_DEV void store_dn(DN* dN, int64_t cap, int64_t q, const double g[3]) {
+  dN[q] = (DN)g[0];
+  dN[cap + q] = (DN)g[1];
+  dN[2 * cap + q] = (DN)g[2];
+}
+
+template <int G, int PPL, bool CACHED, typename DN>
+OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, const double* __restrict__ xp,
+                       const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
+                       int64_t cap, double beta, double tol, int max_iter,
+                       double* __restrict__ lam_io, double* __restrict__ Nout,
+                       DN* __restrict__ dN, otm_diag* diag) {
+  const int64_t off = offsets[p];
+  const int K = (int)(offsets[p + 1] - off);
+  const double px = xp[p], py = xp[n_mp + p], pz = xp[2 * n_mp + p];
+  Pairs<G, PPL, CACHED> pr;
+  if constexpr (CACHED) {
+    // branch-free loads (the MP's first pair stands in for empty slots) so
+    // that all of them are in flight together
+    if (K > 0) {
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        const int q = k * G + lane;
+        const int32_t I = idx[off + (q < K ? q : 0)];
+        double nx, ny, nz;
+        node_xyz(ns, I, nx, ny, nz);
+        pr.d[k][0] = px - nx;
+        pr.d[k][1] = py - ny;
+        pr.d[k][2] = pz - nz;
+        pr.prior[k] = -beta * ((pr.d[k][0] * pr.d[k][0] + pr.d[k][1] * pr.d[k][1]) +
+                               pr.d[k][2] * pr.d[k][2]);
+      }
+    }
+  }
+  double lam[3] = {lam_io[p], lam_io[n_mp + p], lam_io[2 * n_mp + p]};
+  // ek holds the exponentials of the last evaluation; every line search
+  // ends with an accepted trial, so they always belong to the current lambda
+  double ek[CACHED ? PPL : 1];
+  Eval ev, et_ev;
+  lme_eval<G, PPL, CACHED>(pr, lane, K, off, px, py, pz, ns, idx, beta, lam, ev, ek);
+  bool converged = false;
+  for (int it = 0;; ++it) {
+    const double rn = sqrt(ev.r[0] * ev.r[0] + ev.r[1] * ev.r[1] + ev.r[2] * ev.r[2]);
+    if (rn <= tol) { converged = true; break; }
+    if (it >= max_iter) break;
+    double Mi[6], det;
+    sym_inv(ev.J, Mi, det);
+    const double tr = ev.J[0] + ev.J[1] + ev.J[2];
+    if (!(det > 1e-30 * tr * tr * tr) || !isfinite(det)) break;  // multiplier ran away
+    double delta[3];
+    sym_mul_vec(Mi, ev.r, delta);
+    delta[0] = -delta[0]; delta[1] = -delta[1]; delta[2] = -delta[2];
+    const double slope = ev.r[0] * delta[0] + ev.r[1] * delta[1] + ev.r[2] * delta[2];
+    double t = 1.0, lt[3];
+    for (int h = 0; h < 31; ++h) {
+      lt[0] = lam[0] + t * delta[0];
+      lt[1] = lam[1] + t * delta[1];
+      lt[2] = lam[2] + t * delta[2];
+      lme_eval<G, PPL, CACHED>(pr, lane, K, off, px, py, pz, ns, idx, beta, lt, et_ev, ek);
+      if (et_ev.logZ <= ev.logZ + 1e-4 * t * slope + 1e-12 * (1.0 + fabs(ev.logZ)) || h == 30)
+        break;
+      t *= 0.5;
+    }
+    lam[0] = lt[0]; lam[1] = lt[1]; lam[2] = lt[2];
+    ev = et_ev;
+  }
+  if (lane == 0) {
+    lam_io[p] = lam[0]; lam_io[n_mp + p] = lam[1]; lam_io[2 * n_mp + p] = lam[2];
+    if (!converged) diag_fail(diag, OTM_ERR_LME_NOCONV, (uint64_t)p);
+  }
+  double Mi[6], det;
+  sym_inv(ev.J, Mi, det);
+  const double iz = 1.0 / ev.Z;
+  auto finish = [&](int q, double e, double dx, double dy, double dz) {
+    const double Nq = e * iz;
+    const double d3[3] = {dx, dy, dz};
+    double g[3];
+    sym_mul_vec(Mi, d3, g);
+    g[0] *= -Nq; g[1] *= -Nq; g[2] *= -Nq;
+    Nout[off + q] = Nq;
+    store_dn<DN>(dN, cap, off + q, g);
+  };
+  if constexpr (CACHED) {
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      const int q = k * G + lane;
+      if (q < K) finish(q, ek[k], pr.d[k][0], pr.d[k][1], pr.d[k][2]);
+    }
+  } else {
+    for (int q = lane; q < K; q += G) {
+      const int32_t I = idx[off + q];
+      double nx, ny, nz;
+      node_xyz(ns, I, nx, ny, nz);
+      const double dx = px - nx, dy = py - ny, dz = pz - nz;
+      const double f = -beta * ((dx * dx + dy * dy) + dz * dz) + (lam[0] * dx + lam[1] * dy + lam[2] * dz);
+      finish(q, exp(f - ev.fmax), dx, dy, dz);
+    }
+  }
+}
+
+template <int G, int PPL, typename DN>
+__global__ __launch_bounds__(256) void k_lme(NodeSrc ns, int64_t n_mp, const double* __restrict__ xp,
+                                             const int64_t* __restrict__ offsets,
+                                             const int32_t* __restrict__ idx, int64_t cap,
+                                             double beta, double tol, int max_iter,
+                                             double* __restrict__ lam, double* __restrict__ N,
+                                             DN* __restrict__ dN, otm_diag* diag) {
+  constexpr int per_block = 256 / G;
+  const int64_t p = (int64_t)xcd_block() * per_block + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (p >= n_mp) return;  // whole group leaves together
+  if (offsets[n_mp] > cap) return;  // lists were not written (capacity)
+  const int K = (int)(offsets[p + 1] - offsets[p]);
+  if (K <= G * PPL)
+    lme_point<G, PPL, true, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
+                                max_iter, lam, N, dN, diag);
+  else
+    lme_point<G, PPL, false, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
+                                 max_iter, lam, N, dN, diag);
+}
+
+void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const double* x_mp,
+                const int64_t* nbr_offsets, const int32_t* nbr_idx, int64_t pair_capacity,
+                double beta, double tol, int32_t max_iter, double* lam, double* N, void* dN,
+                int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s) {
+  if (n_mp <= 0) return;
+  const NodeSrc ns{x_nodes, packed, n_nodes};
+  constexpr int G = 16, PPL = 3;
+  const unsigned nb = (unsigned)((n_mp + (256 / G) - 1) / (256 / G));
+  if (precision == OTM_FP64)
+    k_lme<G, PPL, double><<<nb, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx,
+                                             pair_capacity, beta, tol, max_iter, lam, N,
+                                             (double*)dN, diag);
+  else
+    k_lme<G, PPL, float><<<nb, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx,
+                                            pair_capacity, beta, tol, max_iter, lam, N,
+                                            (float*)dN, diag);
+}
+
+}  // namespace otm

@@ -1,0 +1,410 @@
+// Node update (central difference with lumped mass, rigid-wall projection)
+// and the material-point pass: positions, incremental deformation gradient,
+// F, volume and the constitutive update.
+//
+// Material-point pass, one workgroup per 256 MPs:
+//   phase 1 (gather): groups of 8 lanes walk one MP's pairs with unit stride,
+//     accumulate x_p = sum N_I x_I and H = dF - 1 = sum du_I (x) grad N_I,
+//     reduce by shuffles and park the 12 sums in LDS;
+//   phase 2 (update): one lane per MP reads its sums back and runs the
+//     constitutive update, so the heavy scalar code uses every lane.
+// The node update also writes each node as two 32-byte records (x, y, z, 0)
+// and (du, 0) to the workspace, so the gathers of the MP pass and of the
+// shape functions fetch a node with one or two loads instead of six.
+// Tensors near the identity are carried as deviations (F - 1, b^e - 1, dF - 1)
+// so that the float32 form of the mixed-precision mode keeps its accuracy.
+#include "launch.h"
+#include "otm_common.h"
+
+namespace otm {
+
+// ------------------------------------------------------------------- nodes
+__global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restrict__ x,
+                                                     double* __restrict__ du,
+                                                     double* __restrict__ m,
+                                                     double* __restrict__ f, double dt2,
+                                                     int wall, double wx0, double wx1,
+                                                     double wx2, double wn0, double wn1,
+                                                     double wn2, int zero_mf,
+                                                     double4* __restrict__ packed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double mi = m[i];
+  double u[3], xs[3], xo[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    xo[c] = x[c * n + i];
+    u[c] = du[c * n + i] + dt2 * f[c * n + i] / mi;
+    xs[c] = xo[c] + u[c];
+  }
+  if (wall) {
+    const double g = (xs[0] - wx0) * wn0 + (xs[1] - wx1) * wn1 + (xs[2] - wx2) * wn2;
+    if (g < 0.0) {
+      xs[0] -= g * wn0; xs[1] -= g * wn1; xs[2] -= g * wn2;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u[c] = xs[c] - xo[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    x[c * n + i] = xs[c];
+    du[c * n + i] = u[c];
+  }
+  if (zero_mf) {
+    m[i] = 0.0;
+    f[i] = 0.0; f[n + i] = 0.0; f[2 * n + i] = 0.0;
+  }
+  packed[2 * i] = make_double4(xs[0], xs[1], xs[2], 0.0);
+  packed[2 * i + 1] = make_double4(u[0], u[1], u[2], 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_pack_nodes(int64_t n, const double* __restrict__ x,
+                                                    const double* __restrict__ du,
+                                                    double4* __restrict__ packed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  packed[2 * i] = make_double4(x[i], x[n + i], x[2 * n + i], 0.0);
+  packed[2 * i + 1] = make_double4(du[i], du[n + i], du[2 * n + i], 0.0);
+}
+
+void launch_pack_nodes(const otm_state& st, double4* packed, hipStream_t s) {
+  const int64_t n = st.n_nodes;
+  if (n <= 0) return;
+  k_pack_nodes<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, st.x, st.du, packed);
+}
+
+void launch_node_update(const otm_state& st, const otm_params& p, double dt, bool zero_mf,
+                        double4* packed, hipStream_t s) {
+  const int64_t n = st.n_nodes;
+  if (n <= 0) return;
+  k_node_update<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+      n, st.x, st.du, st.m, st.f, dt * dt, p.wall_enabled, p.wall_x[0], p.wall_x[1],
+      p.wall_x[2], p.wall_n[0], p.wall_n[1], p.wall_n[2], zero_mf ? 1 : 0, packed);
+}
+
+// ----------------------------------------------------------- scalar math
+OTM_DEV double m_log1p(double v) { return log1p(v); }
+OTM_DEV float m_log1p(float v) { return log1pf(v); }
+OTM_DEV double m_expm1(double v) { return expm1(v); }
+OTM_DEV float m_expm1(float v) { return expm1f(v); }
+OTM_DEV double m_log(double v) { return log(v); }
+OTM_DEV float m_log(float v) { return logf(v); }
+OTM_DEV double m_pow(double a, double b) { return pow(a, b); }
+OTM_DEV float m_pow(float a, float b) { return powf(a, b); }
+OTM_DEV double m_sqrt(double v) { return sqrt(v); }
+OTM_DEV float m_sqrt(float v) { return sqrtf(v); }
+
+// Material constants in the working precision.
+template <typename R>
+struct Mat {
+  int model;
+  R K, mu, lamL;
+  R A, B, n, C, m, rate0dt, Tr, Tm, rhoCp, chi, Y0, H;
+  R tol;
+  int max_iter;
+};
+
+template <typename R>
+OTM_DEV void flow_stress(const Mat<R>& M, R eb, R x, R Ts, R& sy, R& dsy) {
+  if (M.model == OTM_J2_LINEAR) {
+    sy = M.Y0 + M.H * (eb + x);
+    dsy = M.H;
+    return;
+  }
+  const R e = eb + x;
+  R hard = M.A, dhard = R(INFINITY);
+  if (e > R(0)) {
+    const R en = m_pow(e, M.n);
+    hard = M.A + M.B * en;
+    dhard = M.B * M.n * en / e;
+  }
+  const R ratio = x / M.rate0dt;
+  R rate = R(1), drate = R(0);
+  if (ratio > R(1)) {
+    rate = R(1) + M.C * m_log(ratio);
+    drate = M.C / x;
+  }
+  const R therm = Ts > R(0) ? R(1) - m_pow(Ts, M.m) : R(1);
+  sy = hard * rate * therm;
+  dsy = (dhard * rate + hard * drate) * therm;
+}
+
+// Root of q - 3 mu x - sigma_Y(eb + x, x/dt, T*) on (0, (q - sigma_Y0)/(3 mu)]:
+// Newton from the right end, bracket kept on the sign, bisection when the
+// Newton iterate leaves the bracket.  Stops when the residual is at the
+// rounding level (|g| <= tol q; the only test that can end the iteration for
+// MPs that barely yield) or the step or bracket is below tol of the iterate.
+template <typename R>
+OTM_DEV R solve_return(const Mat<R>& M, R q, R eb, R Ts, R sy0, bool& ok) {
+  R x = (q - sy0) / (R(3) * M.mu);
+  R lo = R(0), hi = x;
+  ok = false;
+  for (int it = 0; it < M.max_iter; ++it) {
+    R sy, dsy;
+    flow_stress(M, eb, x, Ts, sy, dsy);
+    const R g = q - R(3) * M.mu * x - sy;
+    if (fabs(g) <= M.tol * q) { ok = true; break; }
+    const R gp = -R(3) * M.mu - dsy;
+    if (g > R(0)) lo = x; else hi = x;
+    R xn = x - g / gp;
+    if (!(xn > lo && xn < hi)) xn = R(0.5) * (lo + hi);
+    const bool small = fabs(xn - x) <= M.tol * fabs(xn) || (hi - lo) <= M.tol * hi;
+    x = xn;
+    if (small) { ok = true; break; }
+  }
+  return x;
+}
+
+// ----------------------------------------------------- material-point pass
+constexpr int kMpBlock = 256;
+constexpr int kGather = 8;  // lanes per MP in the gather phase
+
+template <typename R>
+__global__ __launch_bounds__(kMpBlock) void k_mp_update(
+    const double4* __restrict__ nodes, int64_t n_nodes, int64_t n_mp,
+    const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
+    int64_t cap, const double* __restrict__ N, const R* __restrict__ dN,
+    double* __restrict__ xp, double* __restrict__ vol, R* __restrict__ Fd, R* __restrict__ bed,
+    double* __restrict__ epsbar, double* __restrict__ T, R* __restrict__ sigma, Mat<R> M,
+    otm_diag* diag) {
+  __shared__ double sums[12][kMpBlock];
+  const int64_t base = (int64_t)xcd_block() * kMpBlock;
+  const int tid = threadIdx.x;
+  const bool lists_ok = offsets[n_mp] <= cap;
+  const bool have_nodes = n_nodes > 0 && cap > 0;
+
+  // phase 1: gather with 8 lanes per MP
+  {
+    const int lane = tid % kGather;
+    for (int r = 0; r < kMpBlock / (kMpBlock / kGather); ++r) {
+      const int local = r * (kMpBlock / kGather) + tid / kGather;
+      const int64_t p = base + local;
+      double a[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      if (p < n_mp && lists_ok && have_nodes) {
+        const int64_t o0 = offsets[p], o1 = offsets[p + 1];
+        // branch-free loads (pair 0 stands in past the row end, weight 0), so
+        // the compiler can keep all of them in flight together
+        auto add_pair = [&](int64_t q, bool use) {
+          const int64_t qq = use ? q : 0;
+          const int32_t I = use ? idx[qq] : 0;  // node 0 stands in (its values get weight 0)
+          const double w = use ? N[qq] : 0.0;
+          const double g0 = use ? (double)dN[qq] : 0.0;
+          const double g1 = use ? (double)dN[cap + qq] : 0.0;
+          const double g2 = use ? (double)dN[2 * cap + qq] : 0.0;
+          const double4 xv = nodes[2 * (int64_t)I], uv = nodes[2 * (int64_t)I + 1];
+          a[0] += w * xv.x;
+          a[1] += w * xv.y;
+          a[2] += w * xv.z;
+          a[3] += uv.x * g0; a[4] += uv.x * g1; a[5] += uv.x * g2;
+          a[6] += uv.y * g0; a[7] += uv.y * g1; a[8] += uv.y * g2;
+          a[9] += uv.z * g0; a[10] += uv.z * g1; a[11] += uv.z * g2;
+        };
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int64_t q = o0 + k * kGather + lane;
+          add_pair(q, q < o1);
+        }
+        for (int64_t q = o0 + 4 * kGather + lane; q < o1; q += kGather) add_pair(q, true);
+      }
+#pragma unroll
+      for (int c = 0; c < 12; ++c) a[c] = group_sum<kGather>(a[c]);
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sums[c][local] = a[c];
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 2: one lane per MP
+  const int64_t p = base + tid;
+  if (p >= n_mp || !lists_ok) return;
+  M3<double> H;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) H.a[i][j] = sums[3 + 3 * i + j][tid];
+  const double xnew[3] = {sums[0][tid], sums[1][tid], sums[2][tid]};
+  const double detdF = 1.0 + det_one_plus_minus_one(H);
+  if (!(detdF > 0.0)) diag_fail(diag, OTM_ERR_INVERTED, (uint64_t)p);
+  vol[p] = detdF * vol[p];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) xp[c * n_mp + p] = xnew[c];
+
+  // F - 1 <- H + Fd + H Fd
+  M3<R> h, fo, fn;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      h.a[i][j] = (R)H.a[i][j];
+      fo.a[i][j] = Fd[(3 * i + j) * n_mp + p];
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      fn.a[i][j] = h.a[i][j] + fo.a[i][j] +
+                   (h.a[i][0] * fo.a[0][j] + h.a[i][1] * fo.a[1][j] + h.a[i][2] * fo.a[2][j]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Fd[(3 * i + j) * n_mp + p] = fn.a[i][j];
+  const R Jm1 = det_one_plus_minus_one(fn);
+  const R J = R(1) + Jm1;
+
+  S3<R> sig;
+  if (M.model == OTM_NEOHOOKE) {
+    // sigma = (mu/J)(b - 1) + (lambda ln J / J) 1, b - 1 = X + X^T + X X^T
+    const int ii[6] = {0, 1, 2, 0, 1, 0}, jj[6] = {0, 1, 2, 1, 2, 2};
+    const R lnJ = m_log1p(Jm1);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int i = ii[c], j = jj[c];
+      const R bm1 = fn.a[i][j] + fn.a[j][i] +
+                    (fn.a[i][0] * fn.a[j][0] + fn.a[i][1] * fn.a[j][1] + fn.a[i][2] * fn.a[j][2]);
+      sig.v[c] = M.mu / J * bm1 + (c < 3 ? M.lamL * lnJ / J : R(0));
+    }
+  } else {
+    // trial elastic left Cauchy-Green tensor, as a deviation from 1:
+    // b_tr - 1 = H + H^T + H H^T + (1+H) Bd (1+H)^T
+    S3<R> bd;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) bd.v[c] = bed[c * n_mp + p];
+    const M3<R> B = full(bd);
+    M3<R> HB;  // (1 + H) Bd
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        HB.a[i][j] = B.a[i][j] + h.a[i][0] * B.a[0][j] + h.a[i][1] * B.a[1][j] + h.a[i][2] * B.a[2][j];
+    S3<R> dtr;
+    const int ii[6] = {0, 1, 2, 0, 1, 0}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int i = ii[c], j = jj[c];
+      // (1+H) Bd (1+H)^T = HB + HB H^T
+      const R hbh = HB.a[i][j] + HB.a[i][0] * h.a[j][0] + HB.a[i][1] * h.a[j][1] + HB.a[i][2] * h.a[j][2];
+      dtr.v[c] = h.a[i][j] + h.a[j][i] +
+                 (h.a[i][0] * h.a[j][0] + h.a[i][1] * h.a[j][1] + h.a[i][2] * h.a[j][2]) + hbh;
+    }
+    R d[3], V[3][3];
+    jacobi_eig(dtr, d, V);
+    R e[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) e[a] = R(0.5) * m_log1p(d[a]);
+    const R tr = e[0] + e[1] + e[2];
+    R dev[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / R(3);
+    const R q_tr = R(2) * M.mu * m_sqrt(R(1.5) * (dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]));
+    const double ebn = epsbar[p], Tn = T[p];
+    R Ts = R(0);
+    if (M.model == OTM_J2_JC) {
+      R t = (R)((Tn - (double)M.Tr) / ((double)M.Tm - (double)M.Tr));
+      Ts = t < R(0) ? R(0) : (t > R(1) ? R(1) : t);
+    }
+    R sy0, dsy0;
+    flow_stress(M, (R)ebn, R(0), Ts, sy0, dsy0);
+    R deps = R(0), c = R(0);
+    if (q_tr > sy0) {
+      bool ok;
+      deps = solve_return(M, q_tr, (R)ebn, Ts, sy0, ok);
+      if (!ok) diag_fail(diag, OTM_ERR_RM_NOCONV, (uint64_t)p);
+      c = R(3) * M.mu * deps / q_tr;
+    }
+    R bnew[3], tau[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const R ea = e[a] - c * dev[a];
+      bnew[a] = m_expm1(R(2) * ea);
+      tau[a] = (M.K * tr + R(2) * M.mu * (R(1) - c) * dev[a]) / J;
+    }
+    const S3<R> bn = spectral_compose(V, bnew);
+    sig = spectral_compose(V, tau);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) bed[k * n_mp + p] = bn.v[k];
+    epsbar[p] = ebn + (double)deps;
+    if (M.model == OTM_J2_JC)
+      T[p] = Tn + (double)(M.chi * (R(1) - c) * q_tr * deps / M.rhoCp);
+  }
+  bool finite = isfinite(xnew[0]) && isfinite(xnew[1]) && isfinite(xnew[2]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    sigma[k * n_mp + p] = sig.v[k];
+    finite = finite && isfinite((double)sig.v[k]);
+  }
+  if (!finite) diag_fail(diag, OTM_ERR_NONFINITE, (uint64_t)p);
+}
+
+template <typename R>
+static Mat<R> make_mat(const otm_params& p, double dt) {
+  Mat<R> M;
+  const double lamL = p.E * p.nu / ((1 + p.nu) * (1 - 2 * p.nu));
+  const double mu = p.E / (2 * (1 + p.nu));
+  M.model = p.model;
+  M.K = (R)(lamL + 2.0 * mu / 3.0);
+  M.mu = (R)mu;
+  M.lamL = (R)lamL;
+  M.A = (R)p.A; M.B = (R)p.B; M.n = (R)p.n; M.C = (R)p.C; M.m = (R)p.m;
+  M.rate0dt = (R)(dt * p.eps_dot0);
+  M.Tr = (R)p.T_r; M.Tm = (R)p.T_m;
+  M.rhoCp = (R)(p.rho0 * p.Cp);
+  M.chi = (R)p.chi;
+  M.Y0 = (R)p.Y0; M.H = (R)p.H;
+  const double eps = sizeof(R) == 8 ? 2.2e-16 : 1.2e-7;
+  M.tol = (R)(p.rm_tol > 4 * eps ? p.rm_tol : 4 * eps);
+  M.max_iter = p.rm_max_iter;
+  return M;
+}
+
+void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
+                      const double4* packed, otm_diag* diag, hipStream_t s) {
+  const int64_t n = st.n_mp;
+  if (n <= 0) return;
+  const unsigned nb = (unsigned)((n + kMpBlock - 1) / kMpBlock);
+  if (st.precision == OTM_FP64)
+    k_mp_update<double><<<nb, kMpBlock, 0, s>>>(
+        packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const double*)st.dN, st.xp, st.vol, (double*)st.Fd, (double*)st.bed, st.epsbar, st.T,
+        (double*)st.sigma, make_mat<double>(p, dt), diag);
+  else
+    k_mp_update<float><<<nb, kMpBlock, 0, s>>>(
+        packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const float*)st.dN, st.xp, st.vol, (float*)st.Fd, (float*)st.bed, st.epsbar, st.T,
+        (float*)st.sigma, make_mat<float>(p, dt), diag);
+}
+
+// ------------------------------------------------------------------- t = 0
+template <typename R>
+__global__ void k_init_mp(int64_t n, R* Fd, R* bed, R* sigma, double* epsbar, double* T,
+                          double* lam, double Tr) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  for (int c = 0; c < 9; ++c) Fd[c * n + p] = R(0);
+  for (int c = 0; c < 6; ++c) { bed[c * n + p] = R(0); sigma[c * n + p] = R(0); }
+  epsbar[p] = 0.0;
+  T[p] = Tr;
+  lam[p] = 0.0; lam[n + p] = 0.0; lam[2 * n + p] = 0.0;
+}
+
+__global__ void k_init_nodes(int64_t n, double* du, const double* v0, double dt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < 3; ++c) du[c * n + i] = dt * v0[c * n + i];
+}
+
+void launch_init_fields(const otm_state& st, const otm_params& p, double dt, const double* v0,
+                        hipStream_t s) {
+  if (st.n_mp > 0) {
+    const unsigned nb = (unsigned)((st.n_mp + 255) / 256);
+    if (st.precision == OTM_FP64)
+      k_init_mp<double><<<nb, 256, 0, s>>>(st.n_mp, (double*)st.Fd, (double*)st.bed,
+                                           (double*)st.sigma, st.epsbar, st.T, st.lam, p.T_r);
+    else
+      k_init_mp<float><<<nb, 256, 0, s>>>(st.n_mp, (float*)st.Fd, (float*)st.bed,
+                                          (float*)st.sigma, st.epsbar, st.T, st.lam, p.T_r);
+  }
+  if (st.n_nodes > 0)
+    k_init_nodes<<<(unsigned)((st.n_nodes + 255) / 256), 256, 0, s>>>(st.n_nodes, st.du, v0, dt);
+}
+
+}  // namespace otm

@@ -1,0 +1,210 @@
+// Device helpers shared by the OTM kernels: failure record, wave-level
+// reductions, XCD-aware block numbering and small 3x3 tensor algebra.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "otm.h"
+
+#define OTM_DEV __device__ __forceinline__
+#define OTM_HD __host__ __device__ __forceinline__
+
+namespace otm {
+
+constexpr int kWave = 64;
+
+// ----------------------------------------------------------------- failures
+// Flag bit k corresponds to status -(k+1).
+OTM_DEV void diag_fail(otm_diag* d, otm_status code, uint64_t index) {
+  if (d == nullptr) return;
+  const int k = -code - 1;
+  atomicOr(&d->flags, 1u << k);
+  unsigned long long* cnt = nullptr;
+  unsigned long long* first = nullptr;
+  switch (code) {
+    case OTM_ERR_LME_NOCONV:
+      cnt = (unsigned long long*)&d->n_lme_noconv;
+      first = (unsigned long long*)&d->first_lme_noconv;
+      break;
+    case OTM_ERR_RM_NOCONV:
+      cnt = (unsigned long long*)&d->n_rm_noconv;
+      first = (unsigned long long*)&d->first_rm_noconv;
+      break;
+    case OTM_ERR_INVERTED:
+      cnt = (unsigned long long*)&d->n_inverted;
+      first = (unsigned long long*)&d->first_inverted;
+      break;
+    case OTM_ERR_NONFINITE:
+      cnt = (unsigned long long*)&d->n_nonfinite;
+      first = (unsigned long long*)&d->first_nonfinite;
+      break;
+    default:
+      return;
+  }
+  atomicAdd(cnt, 1ull);
+  atomicMin(first, (unsigned long long)index);
+}
+
+// ----------------------------------------------------------- block numbering
+// The hardware deals consecutive workgroups round-robin to the 8 XCDs, each
+// with its own L2.  Renumber so that every XCD works on one contiguous range
+// of logical blocks (neighbouring MPs share nodes, so their gathers then hit
+// the same L2).  Bijective on [0, gridDim.x).
+OTM_DEV uint32_t xcd_block() {
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  const uint32_t q = nb / 8u, r = nb % 8u, x = b % 8u;
+  return x * q + (x < r ? x : r) + b / 8u;
+}
+
+// ------------------------------------------------------------- reductions
+// Butterfly over aligned groups of G lanes.  Every lane of the group ends
+// with the same bits (a + b and b + a round identically).
+template <int G>
+OTM_DEV double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+template <int G>
+OTM_DEV float group_sum(float v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+template <int G>
+OTM_DEV double group_max(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
+  return v;
+}
+
+// ------------------------------------------------------------- 3x3 algebra
+template <typename R>
+struct M3 {
+  R a[3][3];
+};
+template <typename R>
+struct S3 {  // symmetric: xx yy zz xy yz xz
+  R v[6];
+};
+
+template <typename R>
+OTM_HD R det3(const M3<R>& A) {
+  return A.a[0][0] * (A.a[1][1] * A.a[2][2] - A.a[1][2] * A.a[2][1]) -
+         A.a[0][1] * (A.a[1][0] * A.a[2][2] - A.a[1][2] * A.a[2][0]) +
+         A.a[0][2] * (A.a[1][0] * A.a[2][1] - A.a[1][1] * A.a[2][0]);
+}
+
+// det(1 + X) - 1 = tr X + (tr^2 X - tr X^2)/2 + det X, accurate for small X.
+template <typename R>
+OTM_HD R det_one_plus_minus_one(const M3<R>& X) {
+  const R tr = X.a[0][0] + X.a[1][1] + X.a[2][2];
+  const R i2 = X.a[0][0] * X.a[1][1] + X.a[1][1] * X.a[2][2] + X.a[0][0] * X.a[2][2] -
+               X.a[0][1] * X.a[1][0] - X.a[1][2] * X.a[2][1] - X.a[0][2] * X.a[2][0];
+  return tr + i2 + det3(X);
+}
+
+// Symmetric 3x3 from its 6 components, as a full matrix.
+template <typename R>
+OTM_HD M3<R> full(const S3<R>& s) {
+  M3<R> A;
+  A.a[0][0] = s.v[0]; A.a[1][1] = s.v[1]; A.a[2][2] = s.v[2];
+  A.a[0][1] = A.a[1][0] = s.v[3];
+  A.a[1][2] = A.a[2][1] = s.v[4];
+  A.a[0][2] = A.a[2][0] = s.v[5];
+  return A;
+}
+
+// Eigen-decomposition of a symmetric 3x3 by cyclic Jacobi rotations:
+// on return d[k] are the eigenvalues and column k of V the eigenvectors.
+template <typename R>
+OTM_HD void jacobi_eig(const S3<R>& s, R d[3], R V[3][3]) {
+  R a00 = s.v[0], a11 = s.v[1], a22 = s.v[2];
+  R a01 = s.v[3], a12 = s.v[4], a02 = s.v[5];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? R(1) : R(0);
+  const R tiny = sizeof(R) == 8 ? R(1e-300) : R(1e-36);
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const R off = fabs(a01) + fabs(a12) + fabs(a02);
+    const R diag = fabs(a00) + fabs(a11) + fabs(a22);
+    if (off <= (sizeof(R) == 8 ? R(1e-18) : R(1e-9)) * diag || off < tiny) break;
+    // rotation in plane (p, q); the three planes in turn
+#pragma unroll
+    for (int plane = 0; plane < 3; ++plane) {
+      R app, aqq, apq;
+      if (plane == 0) { app = a00; aqq = a11; apq = a01; }
+      else if (plane == 1) { app = a00; aqq = a22; apq = a02; }
+      else { app = a11; aqq = a22; apq = a12; }
+      if (fabs(apq) < tiny) continue;
+      const R theta = (aqq - app) / (R(2) * apq);
+      const R t = (theta >= R(0) ? R(1) : R(-1)) / (fabs(theta) + sqrt(theta * theta + R(1)));
+      const R c = R(1) / sqrt(t * t + R(1));
+      const R sn = t * c;
+      const R np = app - t * apq, nq = aqq + t * apq;
+      if (plane == 0) {
+        const R r02 = c * a02 - sn * a12, r12 = sn * a02 + c * a12;
+        a00 = np; a11 = nq; a01 = R(0); a02 = r02; a12 = r12;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const R vp = V[k][0], vq = V[k][1];
+          V[k][0] = c * vp - sn * vq; V[k][1] = sn * vp + c * vq;
+        }
+      } else if (plane == 1) {
+        const R r01 = c * a01 - sn * a12, r21 = sn * a01 + c * a12;
+        a00 = np; a22 = nq; a02 = R(0); a01 = r01; a12 = r21;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const R vp = V[k][0], vq = V[k][2];
+          V[k][0] = c * vp - sn * vq; V[k][2] = sn * vp + c * vq;
+        }
+      } else {
+        const R r10 = c * a01 - sn * a02, r20 = sn * a01 + c * a02;
+        a11 = np; a22 = nq; a12 = R(0); a01 = r10; a02 = r20;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const R vp = V[k][1], vq = V[k][2];
+          V[k][1] = c * vp - sn * vq; V[k][2] = sn * vp + c * vq;
+        }
+      }
+    }
+  }
+  d[0] = a00; d[1] = a11; d[2] = a22;
+}
+
+// Q diag(w) Q^T as 6 components.
+template <typename R>
+OTM_HD S3<R> spectral_compose(const R V[3][3], const R w[3]) {
+  S3<R> s;
+  const int ii[6] = {0, 1, 2, 0, 1, 0}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int i = ii[c], j = jj[c];
+    s.v[c] = V[i][0] * w[0] * V[j][0] + V[i][1] * w[1] * V[j][1] + V[i][2] * w[2] * V[j][2];
+  }
+  return s;
+}
+
+// Inverse of a symmetric positive definite 3x3 given as xx yy zz xy yz xz.
+OTM_HD void sym_inv(const double J[6], double Mi[6], double& det) {
+  const double c00 = J[1] * J[2] - J[4] * J[4];
+  const double c11 = J[0] * J[2] - J[5] * J[5];
+  const double c22 = J[0] * J[1] - J[3] * J[3];
+  const double c01 = J[5] * J[4] - J[3] * J[2];
+  const double c12 = J[3] * J[5] - J[0] * J[4];
+  const double c02 = J[3] * J[4] - J[5] * J[1];
+  det = J[0] * c00 + J[3] * c01 + J[5] * c02;
+  const double id = 1.0 / det;
+  Mi[0] = c00 * id; Mi[1] = c11 * id; Mi[2] = c22 * id;
+  Mi[3] = c01 * id; Mi[4] = c12 * id; Mi[5] = c02 * id;
+}
+
+OTM_HD void sym_mul_vec(const double M[6], const double v[3], double o[3]) {
+  o[0] = M[0] * v[0] + M[3] * v[1] + M[5] * v[2];
+  o[1] = M[3] * v[0] + M[1] * v[1] + M[4] * v[2];
+  o[2] = M[5] * v[0] + M[4] * v[1] + M[2] * v[2];
+}
+
+}  // namespace otm

@@ -1,0 +1,242 @@
+"""Python front end of libotm: device buffers (torch tensors on the current
+HIP device), the caller's stream, and thin wrappers of the C entry points.
+
+All arithmetic of the method runs inside libotm's kernels; this module only
+allocates, lays out and passes pointers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Diag, Params, State, check, lib
+
+SYM = ((0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def soa(a, device, dtype=torch.float64):
+    """(n, k) host array -> contiguous [k][n] device tensor."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).T)
+    return torch.from_numpy(a).to(device=device, dtype=dtype).contiguous()
+
+
+def make_params(p):
+    """otm_params from a flat dict (the keys of the oracle's parameter dict)."""
+    q = Params()
+    q.model = int(p["model"])
+    q.wall_enabled = 1 if p.get("wall", False) else 0
+    for k in ("E", "nu", "rho0", "A", "B", "n", "C", "m", "eps_dot0", "T_r", "T_m", "Cp",
+              "chi", "Y0", "H", "beta", "r_list", "cell_size", "lme_tol", "rm_tol"):
+        setattr(q, k, float(p[k]))
+    q.lme_max_iter = int(p.get("lme_max_iter", 50))
+    q.rm_max_iter = int(p.get("rm_max_iter", 60))
+    wx = p.get("wall_x", (0.0, 0.0, 0.0))
+    wn = p.get("wall_n", (0.0, 0.0, 1.0))
+    for i in range(3):
+        q.wall_x[i] = float(wx[i])
+        q.wall_n[i] = float(wn[i])
+        q.body_force[i] = 0.0
+    q.eps_stab = 0.0
+    return q
+
+
+class Workspace:
+    def __init__(self, n_nodes, n_mp, cap, device):
+        self.nbytes = int(lib().otm_workspace_bytes(n_nodes, n_mp, cap))
+        self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self):
+        return _ptr(self.buf)
+
+
+def new_diag(device):
+    d = torch.empty(C.sizeof(Diag), dtype=torch.uint8, device=device)
+    check(lib().otm_diag_reset(_ptr(d), _stream()), "otm_diag_reset")
+    return d
+
+
+def read_diag(d):
+    out = Diag()
+    code = lib().otm_diag_read(_ptr(d), C.byref(out), _stream())
+    return code, out
+
+
+# -------------------------------------------------------------- single calls
+def build_neighbors(x_nodes, x_mp, r_list, cell_size, pair_capacity=None):
+    """Support lists of device positions x_nodes [3][nn], x_mp [3][np].
+    Returns (offsets int64 [np+1], idx int32 [P]) device tensors."""
+    dev = x_nodes.device
+    nn, nm = x_nodes.shape[1], x_mp.shape[1]
+    offsets = torch.empty(nm + 1, dtype=torch.int64, device=dev)
+    P = C.c_int64(0)
+    if pair_capacity is None:
+        ws = Workspace(nn, nm, 0, dev)
+        code = lib().otm_build_neighbors(nn, _ptr(x_nodes), nm, _ptr(x_mp), r_list, cell_size, 0,
+                                         _ptr(offsets), C.c_void_p(0), C.byref(P), ws.ptr,
+                                         ws.nbytes, _stream())
+        if code not in (_lib.OTM_OK, _lib.OTM_ERR_CAPACITY):
+            check(code, "otm_build_neighbors")
+        pair_capacity = int(P.value)
+    idx = torch.empty(max(pair_capacity, 1), dtype=torch.int32, device=dev)
+    ws = Workspace(nn, nm, pair_capacity, dev)
+    code = lib().otm_build_neighbors(nn, _ptr(x_nodes), nm, _ptr(x_mp), r_list, cell_size,
+                                     pair_capacity, _ptr(offsets), _ptr(idx), C.byref(P), ws.ptr,
+                                     ws.nbytes, _stream())
+    check(code, "otm_build_neighbors")
+    return offsets, idx[:P.value]
+
+
+def lme_shape(x_nodes, x_mp, offsets, idx, beta, tol, max_iter=50, lam=None, precision=0,
+              diag=None):
+    """LME shape functions on device lists.  Returns (lam, N, dN, diag)."""
+    dev = x_nodes.device
+    nn, nm = x_nodes.shape[1], x_mp.shape[1]
+    cap = max(int(idx.numel()), 1)
+    lam = torch.zeros(3, nm, dtype=torch.float64, device=dev) if lam is None else lam
+    N = torch.empty(cap, dtype=torch.float64, device=dev)
+    dN = torch.empty(3, cap, dtype=torch.float64 if precision == 0 else torch.float32,
+                     device=dev)
+    diag = new_diag(dev) if diag is None else diag
+    check(lib().otm_lme_shape(nn, _ptr(x_nodes), nm, _ptr(x_mp), _ptr(offsets), _ptr(idx), cap,
+                              beta, tol, max_iter, _ptr(lam), _ptr(N), _ptr(dN), precision,
+                              _ptr(diag), _stream()), "otm_lme_shape")
+    P = int(idx.numel())
+    return lam, N[:P], dN[:, :P], diag
+
+
+# -------------------------------------------------------------- simulation
+class Sim:
+    """Device state of one OTM simulation.
+
+    x_nodes (nn,3), x_mp (np,3), vol_mp, mass_mp (np,), v0_nodes (nn,3) are
+    host arrays; ``params`` is a flat dict (oracle keys, including ``dt``).
+    """
+
+    def __init__(self, x_nodes, x_mp, vol_mp, mass_mp, v0_nodes, params, precision="fp64",
+                 scatter="atomic", pair_capacity=None, capacity_margin=1.3, device="cuda"):
+        self.device = torch.device(device)
+        self.params = dict(params)
+        self.p = make_params(params)
+        self.dt = float(params["dt"])
+        self.prec = _lib.OTM_FP64 if precision == "fp64" else _lib.OTM_MIXED
+        self.mode = _lib.OTM_SCATTER_ATOMIC if scatter == "atomic" else _lib.OTM_SCATTER_SEGMENTED
+        dev = self.device
+        rdt = torch.float64 if self.prec == _lib.OTM_FP64 else torch.float32
+        nn, nm = len(x_nodes), len(x_mp)
+        self.n_nodes, self.n_mp = nn, nm
+        self.x = soa(x_nodes, dev)
+        self.du = torch.zeros(3, nn, dtype=torch.float64, device=dev)
+        self.m = torch.zeros(nn, dtype=torch.float64, device=dev)
+        self.f = torch.zeros(3, nn, dtype=torch.float64, device=dev)
+        self.xp = soa(x_mp, dev)
+        self.vol = torch.as_tensor(np.asarray(vol_mp, np.float64), device=dev).clone()
+        self.mass = torch.as_tensor(np.asarray(mass_mp, np.float64), device=dev).clone()
+        self.lam = torch.zeros(3, nm, dtype=torch.float64, device=dev)
+        self.Fd = torch.zeros(9, nm, dtype=rdt, device=dev)
+        self.bed = torch.zeros(6, nm, dtype=rdt, device=dev)
+        self.epsbar = torch.zeros(nm, dtype=torch.float64, device=dev)
+        self.T = torch.zeros(nm, dtype=torch.float64, device=dev)
+        self.sigma = torch.zeros(6, nm, dtype=rdt, device=dev)
+        self.offsets = torch.zeros(nm + 1, dtype=torch.int64, device=dev)
+        self.v0 = soa(v0_nodes, dev)
+        if pair_capacity is None:
+            P = self._count_pairs()
+            pair_capacity = int(P * capacity_margin) + 1024
+        self.cap = int(pair_capacity)
+        self.idx = torch.zeros(self.cap, dtype=torch.int32, device=dev)
+        self.N = torch.zeros(self.cap, dtype=torch.float64, device=dev)
+        self.dN = torch.zeros(3, self.cap, dtype=rdt, device=dev)
+        self.ws = Workspace(nn, nm, self.cap, dev)
+        self.diag = new_diag(dev)
+        self.st = State()
+        self._fill_state()
+        self.n = 0
+
+    def _count_pairs(self):
+        P = C.c_int64(0)
+        ws = Workspace(self.n_nodes, self.n_mp, 0, self.device)
+        code = lib().otm_build_neighbors(self.n_nodes, _ptr(self.x), self.n_mp, _ptr(self.xp),
+                                         self.p.r_list, self.p.cell_size, 0, _ptr(self.offsets),
+                                         C.c_void_p(0), C.byref(P), ws.ptr, ws.nbytes, _stream())
+        if code not in (_lib.OTM_OK, _lib.OTM_ERR_CAPACITY):
+            check(code, "otm_build_neighbors")
+        return int(P.value)
+
+    def _fill_state(self):
+        s = self.st
+        s.n_nodes, s.n_mp, s.pair_capacity, s.precision = self.n_nodes, self.n_mp, self.cap, self.prec
+        for k in ("x", "du", "m", "f", "xp", "vol", "mass", "lam", "Fd", "bed", "epsbar", "T",
+                  "sigma"):
+            setattr(s, k, _ptr(getattr(self, k)).value)
+        s.nbr_offsets = _ptr(self.offsets).value
+        s.nbr_idx = _ptr(self.idx).value
+        s.N = _ptr(self.N).value
+        s.dN = _ptr(self.dN).value
+
+    # ---------------------------------------------------------------- calls
+    def init(self):
+        check(lib().otm_init(C.byref(self.st), C.byref(self.p), self.dt, _ptr(self.v0), self.mode,
+                             self.ws.ptr, self.ws.nbytes, _ptr(self.diag), _stream()), "otm_init")
+        self.n = 0
+        return self
+
+    def step(self, rebuild=True):
+        check(lib().otm_step(C.byref(self.st), C.byref(self.p), self.dt, 1 if rebuild else 0,
+                             self.mode, self.ws.ptr, self.ws.nbytes, _ptr(self.diag), _stream()),
+              "otm_step")
+        self.n += 1
+
+    def run(self, steps, rebuild_every=1):
+        for _ in range(steps):
+            self.step(rebuild=((self.n + 1) % rebuild_every == 0))
+
+    def refresh(self, rebuild=True):
+        check(lib().otm_refresh(C.byref(self.st), C.byref(self.p), 1 if rebuild else 0, self.mode,
+                                self.ws.ptr, self.ws.nbytes, _ptr(self.diag), _stream()),
+              "otm_refresh")
+
+    def check_diag(self, raise_on_error=True):
+        code, d = read_diag(self.diag)
+        if raise_on_error and code != _lib.OTM_OK:
+            raise _lib.OtmError(code, f"device diagnostics (pairs needed {d.pairs_needed}, "
+                                      f"capacity {self.cap})")
+        return code, d
+
+    # ---------------------------------------------------------------- read back
+    def fields(self):
+        """Host copies in plain layouts: vectors (n,3), tensors (n,3,3)."""
+        torch.cuda.synchronize(self.device)
+        g = lambda t: t.detach().double().cpu().numpy()
+        out = dict(x=g(self.x).T.copy(), du=g(self.du).T.copy(), m=g(self.m), f=g(self.f).T.copy(),
+                   xp=g(self.xp).T.copy(), vol=g(self.vol), lam=g(self.lam).T.copy(),
+                   epsbar=g(self.epsbar), T=g(self.T))
+        Fd = g(self.Fd).T.reshape(-1, 3, 3)
+        out["F"] = Fd + np.eye(3)
+        out["Fd"] = Fd
+        for name in ("bed", "sigma"):
+            v = g(getattr(self, name)).T
+            M = np.zeros((v.shape[0], 3, 3))
+            for c, (i, j) in enumerate(SYM):
+                M[:, i, j] = v[:, c]
+                M[:, j, i] = v[:, c]
+            out[name] = M
+        out["be"] = out["bed"] + np.eye(3)
+        off = self.offsets.cpu().numpy()
+        P = int(off[-1])
+        out["offsets"] = off
+        out["idx"] = self.idx[:P].cpu().numpy()
+        out["N"] = g(self.N[:P])
+        out["dN"] = g(self.dN[:, :P]).T.copy()
+        return out

@@ -15,5 +15,5 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def cube():
-    from paper_2206_08772_amd import inputs
+    import otm_workloads as inputs
     return inputs.config_by_name("elastic_cube")

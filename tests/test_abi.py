@@ -1,0 +1,122 @@
+"""The C ABI library: symbols and host-side argument checks (no GPU work:
+every call below is rejected before anything is enqueued)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import otm_workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "otm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(otm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2206_08772_amd import _lib
+    return _lib
+
+
+def test_every_declared_symbol_is_exported(L):
+    lib = L.lib()
+    names = _declared()
+    assert "otm_step" in names and "otm_build_neighbors" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(L.exported_symbols())
+
+
+def test_status_strings_and_workspace_size(L):
+    lib = L.lib()
+    assert lib.otm_status_string(L.OTM_ERR_CAPACITY).startswith(b"OTM_ERR_CAPACITY")
+    a = lib.otm_workspace_bytes(1000, 4000, 100000)
+    b = lib.otm_workspace_bytes(1000, 4000, 200000)
+    assert a > 0 and a % 256 == 0 and b - a >= 8 * 100000 - 512
+    assert lib.otm_workspace_bytes(-1, 0, 0) == 0
+
+
+def _fake_state(L, prec=0):
+    s = L.State()
+    s.n_nodes, s.n_mp, s.pair_capacity, s.precision = 10, 20, 100, prec
+    for name, _ in L.State._fields_[5:]:
+        setattr(s, name, 1 << 20)      # aligned non-null stand-ins, never dereferenced
+    return s
+
+
+def _params(L, **over):
+    from paper_2206_08772_amd.sim import make_params
+    w = W.elastic_cube(n=3)
+    p = W.params_from_workload(w, **over)
+    return make_params(p)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(cell_size=0.5),            # cell edge below the search radius
+    dict(model=7),
+    dict(lme_tol=0.0),
+    dict(nu=0.5),
+])
+def test_bad_params_are_rejected(L, bad):
+    lib = L.lib()
+    st = _fake_state(L)
+    p = _params(L, **bad)
+    code = lib.otm_step(C.byref(st), C.byref(p), 1e-3, 1, 0, C.c_void_p(1 << 20), 1 << 30,
+                        C.c_void_p(1 << 20), None)
+    assert code == L.OTM_ERR_ARG
+
+
+def test_bad_state_and_workspace_are_rejected(L):
+    lib = L.lib()
+    p = _params(L)
+    st = _fake_state(L)
+    st.x = 0
+    assert lib.otm_step(C.byref(st), C.byref(p), 1e-3, 1, 0, C.c_void_p(1 << 20), 1 << 30,
+                        C.c_void_p(1 << 20), None) == L.OTM_ERR_ARG
+    st = _fake_state(L)
+    st.N = (1 << 20) + 4           # misaligned double array
+    assert lib.otm_step(C.byref(st), C.byref(p), 1e-3, 1, 0, C.c_void_p(1 << 20), 1 << 30,
+                        C.c_void_p(1 << 20), None) == L.OTM_ERR_ARG
+    st = _fake_state(L)
+    st.precision = 5
+    assert lib.otm_step(C.byref(st), C.byref(p), 1e-3, 1, 0, C.c_void_p(1 << 20), 1 << 30,
+                        C.c_void_p(1 << 20), None) == L.OTM_ERR_ARG
+    st = _fake_state(L)
+    # workspace too small
+    assert lib.otm_step(C.byref(st), C.byref(p), 1e-3, 1, 0, C.c_void_p(1 << 20), 64,
+                        C.c_void_p(1 << 20), None) == L.OTM_ERR_ARG
+    # unknown scatter mode, non-positive time step
+    assert lib.otm_step(C.byref(st), C.byref(p), 1e-3, 1, 9, C.c_void_p(1 << 20), 1 << 30,
+                        C.c_void_p(1 << 20), None) == L.OTM_ERR_ARG
+    assert lib.otm_step(C.byref(st), C.byref(p), 0.0, 1, 0, C.c_void_p(1 << 20), 1 << 30,
+                        C.c_void_p(1 << 20), None) == L.OTM_ERR_ARG
+    # pair ids are int32
+    st.pair_capacity = 1 << 31
+    assert lib.otm_step(C.byref(st), C.byref(p), 1e-3, 1, 0, C.c_void_p(1 << 20), 1 << 40,
+                        C.c_void_p(1 << 20), None) == L.OTM_ERR_ARG
+
+
+def test_search_and_lme_argument_checks(L):
+    lib = L.lib()
+    n = C.c_int64(0)
+    fake = C.c_void_p(1 << 20)
+    # cell edge smaller than the radius
+    assert lib.otm_build_neighbors(10, fake, 10, fake, 1.0, 0.5, 100, fake, fake, C.byref(n),
+                                   fake, 1 << 30, None) == L.OTM_ERR_ARG
+    # negative sizes, missing count pointer
+    assert lib.otm_build_neighbors(-1, fake, 10, fake, 1.0, 1.0, 100, fake, fake, C.byref(n),
+                                   fake, 1 << 30, None) == L.OTM_ERR_ARG
+    assert lib.otm_build_neighbors(10, fake, 10, fake, 1.0, 1.0, 100, fake, fake, None,
+                                   fake, 1 << 30, None) == L.OTM_ERR_ARG
+    # LME: bad precision, non-positive beta or tolerance
+    assert lib.otm_lme_shape(10, fake, 10, fake, fake, fake, 100, 4.0, 1e-13, 50, fake, fake,
+                             fake, 3, None, None) == L.OTM_ERR_ARG
+    assert lib.otm_lme_shape(10, fake, 10, fake, fake, fake, 100, -4.0, 1e-13, 50, fake, fake,
+                             fake, 0, None, None) == L.OTM_ERR_ARG
+    assert lib.otm_lme_shape(10, fake, 10, fake, fake, fake, 100, 4.0, 0.0, 50, fake, fake,
+                             fake, 0, None, None) == L.OTM_ERR_ARG

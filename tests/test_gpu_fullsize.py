@@ -1,0 +1,102 @@
+"""Parity at the Taylor-rod size (1.13M MPs, 202k nodes), in the launch
+configuration the benchmark times.  The oracle recomputes, from the GPU's own
+state before a step, what that step must produce: every node's update and
+force, and the lists, shape functions and material-point update of a sample
+of MPs."""
+import numpy as np
+import pytest
+
+import otm_workloads as W
+from oracle import lme as OL
+from oracle import search as OS
+from oracle import step as OST
+from tests.gpu_common import make_sim, require_gpu
+from tests.helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.fixture(scope="module")
+def rod():
+    return W.config_by_name("taylor_rod")
+
+
+def _mini_state(g, rows, p):
+    """Oracle state holding the MPs ``rows`` of a GPU snapshot (all nodes)."""
+    off, idx = g["offsets"], g["idx"]
+    K = off[rows + 1] - off[rows]
+    new_off = np.concatenate([[0], np.cumsum(K)]).astype(np.int64)
+    sel = np.concatenate([np.arange(off[r], off[r + 1]) for r in rows])
+    return OST.State(x=g["x"].copy(), du=g["du"].copy(), m=g["m"].copy(), f=g["f"].copy(),
+                     xp=g["xp"][rows].copy(), vol=g["vol"][rows].copy(), mass=None,
+                     lam=g["lam"][rows].copy(), F=g["F"][rows].copy(), be=g["be"][rows].copy(),
+                     epsbar=g["epsbar"][rows].copy(), T=g["T"][rows].copy(),
+                     sigma=g["sigma"][rows].copy(), offsets=new_off, idx=idx[sel].copy(),
+                     N=g["N"][sel].copy(), dN=g["dN"][sel].copy())
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_one_step_at_full_size(rod, precision, tol):
+    sim, p = make_sim(rod, precision, "atomic")
+    sim.init()
+    sim.run(3)                       # some plastic flow and wall contact first
+    g0 = sim.fields()
+    sim.step()
+    sim.check_diag()
+    g1 = sim.fields()
+    mass = rod.mass_mp
+    rng = np.random.default_rng(11)
+
+    # nodes: central difference + wall, every node
+    st = OST.State(x=g0["x"].copy(), du=g0["du"].copy(), m=g0["m"], f=g0["f"], xp=None, vol=None,
+                   mass=None, lam=None, F=None, be=None, epsbar=None, T=None, sigma=None,
+                   offsets=None, idx=None, N=None, dN=None)
+    OST.node_update(st, p)
+    assert rel_err(g1["x"] - rod.x_nodes, st.x - rod.x_nodes) < 1e-13
+    assert rel_err(g1["du"], st.du) < 1e-13
+    assert g1["x"][:, 2].min() >= 0.0
+
+    # MP update of a sample, from the GPU's step-n lists and shape functions
+    rows = np.sort(rng.choice(rod.n_mp, 400, replace=False))
+    # include MPs at the impact face, where the return map is active
+    face = np.nonzero(g0["xp"][:, 2] < 1.5 * rod.h)[0]
+    rows = np.unique(np.concatenate([rows, rng.choice(face, 200, replace=False)]))
+    ms = _mini_state(g0, rows, p)
+    ms.x, ms.du = g1["x"].copy(), g1["du"].copy()
+    OST.mp_update(ms, p)
+    assert ms.epsbar.max() > g0["epsbar"][rows].max()      # plastic MPs in the sample
+    scale_up = np.abs(g1["xp"][rows] - rod.x_mp[rows]).max()
+    assert np.abs(g1["xp"][rows] - ms.xp).max() <= tol * scale_up
+    assert rel_err(g1["F"][rows] - np.eye(3), ms.F - np.eye(3)) < tol
+    assert rel_err(g1["vol"][rows], ms.vol) < tol
+    assert rel_err(g1["sigma"][rows], ms.sigma) < tol
+    assert rel_err(g1["be"][rows] - np.eye(3), ms.be - np.eye(3)) < tol
+    assert rel_err(g1["epsbar"][rows], ms.epsbar) < tol
+    assert rel_err(g1["T"][rows] - p["T_r"], ms.T - p["T_r"]) < tol
+
+    # support lists of the sample: bit-exact against the definition
+    for r in rows[::3]:
+        ref = OS.neighbors_one(g1["x"], g1["xp"][r], p["r_list"])
+        assert np.array_equal(g1["idx"][g1["offsets"][r]:g1["offsets"][r + 1]], ref)
+
+    # shape functions of the sample (warm-started from the step-n multiplier)
+    for r in rows[::6]:
+        a, b = g1["offsets"][r], g1["offsets"][r + 1]
+        lam, N, dN = OL.lme_one(g1["x"][g1["idx"][a:b]], g1["xp"][r], p["beta"], p["lme_tol"],
+                                lam0=g0["lam"][r])
+        assert np.abs(g1["N"][a:b] - N).max() < 1e-12
+        assert np.abs(g1["dN"][a:b] - dN).max() < (1e-11 if precision == "fp64" else 1e-7) \
+            * np.abs(dN).max()
+
+    # lumped mass and force of every node from the GPU's new pairs and stress
+    full = OST.State(x=g1["x"], du=None, m=None, f=None, xp=g1["xp"], vol=g1["vol"], mass=mass,
+                     lam=None, F=None, be=None, epsbar=None, T=None, sigma=g1["sigma"],
+                     offsets=g1["offsets"], idx=g1["idx"], N=g1["N"], dN=g1["dN"])
+    OST.assemble(full, p)
+    assert rel_err(g1["m"], full.m) < 1e-12
+    assert rel_err(g1["f"], full.f) < (1e-12 if precision == "fp64" else 1e-6)

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from oracle import lme, search
-from paper_2206_08772_amd import inputs
+import otm_workloads as inputs
 
 
 @pytest.fixture(scope="module")

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import search
-from paper_2206_08772_amd import inputs
+import otm_workloads as inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "search_tiny.json")
 

@@ -4,12 +4,12 @@ import pytest
 
 from oracle import material, search
 from oracle import step as S
-from paper_2206_08772_amd import inputs
+import otm_workloads as inputs
 
 
 @pytest.fixture(scope="module")
 def cube_state(cube):
-    p = S.params_from_workload(cube)
+    p = inputs.params_from_workload(cube)
     st = S.init_state(cube.x_nodes, cube.x_mp, cube.vol_mp, cube.mass_mp, cube.v0_nodes, p)
     return p, st
 
@@ -71,7 +71,7 @@ def test_patch_test_uniform_deformation_is_exact(cube, model):
     """du_I = (A - 1) x_I at every node gives dF = A, x_p' = A x_p, F = A and
     v' = det(A) v exactly (linear consistency of the LME functions)."""
     w = cube
-    p = S.params_from_workload(w, model=model, E=117e9, nu=0.35, rho0=8930.0, A=90e6, B=292e6,
+    p = inputs.params_from_workload(w, model=model, E=117e9, nu=0.35, rho0=8930.0, A=90e6, B=292e6,
                                n=0.31, C=0.025, m=1.09)
     st = S.init_state(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p)
     A = np.eye(3) + 1e-3 * np.array([[1.0, 0.3, -0.2], [0.1, -0.5, 0.4], [0.25, 0.0, 0.7]])
@@ -137,7 +137,7 @@ def test_elastic_energy_is_conserved():
     without drifting).  A wrong sign of the force or the mass makes it blow
     up within a few dozen steps."""
     w = inputs.elastic_cube(n=6)
-    p = S.params_from_workload(w)
+    p = inputs.params_from_workload(w)
     st = S.init_state(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p)
     ke, pe = [], []
     for _ in range(200):
@@ -158,7 +158,7 @@ def test_elastic_energy_is_conserved():
 
 def test_rod_runs_with_plasticity_heating_and_wall():
     w = inputs.config_by_name("small_rod")
-    p = S.params_from_workload(w)
+    p = inputs.params_from_workload(w)
     st = S.init_state(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p)
     for _ in range(20):
         S.step(st, p)
