@@ -54,7 +54,8 @@ enum {
   OTM_ERR_RM_NOCONV = -4,    /* return-map Newton did not converge */
   OTM_ERR_INVERTED = -5,     /* det(dF) <= 0 at a material point */
   OTM_ERR_NONFINITE = -6,    /* non-finite stress or position */
-  OTM_ERR_HIP = -7           /* a HIP runtime call failed */
+  OTM_ERR_HIP = -7,          /* a HIP runtime call failed */
+  OTM_ERR_SUPPORT = -8       /* a support longer than the adjoint handles (48) */
 };
 
 /* arithmetic of the step */
@@ -132,7 +133,7 @@ typedef struct otm_diag {
   uint64_t first_lme_noconv;   /* smallest failing MP index (UINT64_MAX: none) */
   uint64_t first_rm_noconv;
   uint64_t first_inverted;
-  uint64_t first_nonfinite;
+  uint64_t first_nonfinite;    /* (a node I is reported as n_mp + I) */
   int64_t pairs_needed;        /* pair count of the last search */
   int64_t reserved[3];
 } otm_diag;
@@ -220,6 +221,70 @@ otm_status otm_refresh(otm_state* st, const otm_params* p, int32_t rebuild,
 otm_status otm_step(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
                     int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
                     hipStream_t s);
+
+/* One stored step of a forward trajectory (host struct of device pointers,
+ * float64 state as in otm_state with precision OTM_FP64).  Pair arrays N and
+ * dN have component stride pair_stride.  m and f are the lumped mass and
+ * force assembled for this state (the ones the next node update uses). */
+typedef struct otm_tape {
+  int64_t n_nodes, n_mp, pair_stride;
+  const double* x;
+  const double* du;
+  const double* m;
+  const double* f;
+  const double* xp;
+  const double* vol;
+  const double* lam;
+  const double* Fd;
+  const double* bed;
+  const double* epsbar;
+  const double* T;
+  const double* sigma;
+  const int64_t* nbr_offsets;
+  const int32_t* nbr_idx;
+  const double* N;
+  const double* dN;
+} otm_tape;
+
+/* Adjoint of a scalar loss with respect to one step's state (device,
+ * float64, the layouts of otm_state; N and dN per pair of that step's lists,
+ * dN with the stride of that step's tape). */
+typedef struct otm_state_bar {
+  double* x;
+  double* du;
+  double* vol;
+  double* Fd;
+  double* bed;
+  double* epsbar;
+  double* T;
+  double* sigma;
+  double* N;
+  double* dN;
+} otm_state_bar;
+
+/* Workspace bytes of otm_step_adjoint (256-aligned). */
+size_t otm_adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp);
+
+/*
+ * Reverse of one otm_step (J2 models, float64), for gradients of a loss over
+ * a rollout.  tn and tn1 are the stored states before and after the step
+ * (support lists frozen to theirs).  bar_next holds the adjoint of state
+ * n+1 on entry and is used as scratch (its x and du receive the
+ * contributions of this step before being mapped back); bar receives the
+ * adjoint of state n (every field is written).  theta_bar (device, 3
+ * doubles) accumulates dL/d(A, B, n) for OTM_J2_JC or dL/d(Y0, H, -) for
+ * OTM_J2_LINEAR.  The derivative of each stage is the exact derivative of the
+ * forward arithmetic: LME through the implicit function theorem on the
+ * consistency condition, the return map through the spectral derivative of
+ * the Hencky stress and of the exponential map and the implicit derivative
+ * of the scalar return equation; wall contact and plastic onset are
+ * differentiated on their active branch.  Supports longer than 48 nodes are
+ * reported as OTM_ERR_SUPPORT in diag.
+ */
+otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_params* p,
+                            double dt, const double* mass, otm_state_bar* bar_next,
+                            otm_state_bar* bar, double* theta_bar, void* ws, size_t ws_bytes,
+                            otm_diag* diag, hipStream_t s);
 
 /*
  * otm_step with phase markers: events[k] (host array of 7 caller-created

@@ -1,0 +1,77 @@
+"""Oracle gradients of a rollout loss by complex-step differentiation.
+
+The loss is L = 1/2 sum_I |x_I(N) - x_I^target|^2 over the node positions
+after N explicit steps (Alg. 1).  Its derivatives with respect to the
+Johnson-Cook constants A, B, n (Sec. 4.2 hardening law) and to the initial
+speed are taken by the complex-step method: a parameter is given an
+imaginary part i*h (h ~ 1e-20 of its size), the whole rollout runs in complex
+arithmetic, and dL/dtheta = Im L / h, exact up to round-off (no subtractive
+cancellation).  The holomorphic form of the oracle is used for this: tensor
+log/exp by series instead of eigen-decomposition, decisions (plastic branch,
+wall contact, Armijo test, Newton stops) taken on real parts, and extra Newton
+iterations after convergence so that the imaginary parts converge too.
+
+Support lists are frozen to those of the real (nominal) trajectory: the
+lists are piecewise constant in the parameters, so the derivative is taken
+with the lists of the nominal run, step by step.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import step as S
+
+
+def nominal_lists(x_nodes, x_mp, vol, mass, v0, p, steps):
+    """Support lists of every step of the real trajectory (index 0: t = 0)."""
+    st = S.init_state(x_nodes, x_mp, vol, mass, v0, p)
+    lists = [(st.offsets.copy(), st.idx.copy())]
+    for _ in range(steps):
+        S.step(st, p)
+        lists.append((st.offsets.copy(), st.idx.copy()))
+    return lists, st
+
+
+def rollout(x_nodes, x_mp, vol, mass, v0, p, steps, lists, complex_step=False):
+    """Final state after ``steps`` steps with the given per-step lists."""
+    st = S.init_state(np.asarray(x_nodes).real, np.asarray(x_mp).real, np.asarray(vol).real,
+                      mass, np.asarray(v0).real, p, lists=lists[0])
+    if complex_step:
+        # the t = 0 quantities again, in complex arithmetic (only v0 or the
+        # material constants carry an imaginary part)
+        p = dict(p, spectral="series", polish=3)
+        st.x = st.x.astype(complex)
+        st.xp = st.xp.astype(complex)
+        st.vol = st.vol.astype(complex)
+        st.du = p["dt"] * np.asarray(v0, complex)
+        for k in ("lam", "F", "be", "epsbar", "T", "sigma"):
+            setattr(st, k, getattr(st, k).astype(complex))
+        S.shape(st, p)
+        S.assemble(st, p)
+    for k in range(steps):
+        S.step(st, p, lists=lists[k + 1])
+    return st
+
+
+def loss(st, x_target):
+    d = st.x - x_target
+    return 0.5 * (d * d).sum()
+
+
+def complex_step_gradient(x_nodes, x_mp, vol, mass, v0, p, steps, lists, x_target,
+                          params=("A", "B", "n")):
+    """dL/dtheta for the named material constants and dL/d(speed), where the
+    initial nodal velocity is v0 = speed * v0_unit."""
+    grads = {}
+    for name in params:
+        h = 1e-20 * abs(p[name])
+        pc = dict(p)
+        pc[name] = p[name] + 1j * h
+        st = rollout(x_nodes, x_mp, vol, mass, v0, pc, steps, lists, complex_step=True)
+        grads[name] = loss(st, x_target).imag / h
+    speed = np.abs(v0).max()
+    h = 1e-20 * speed
+    v0c = np.asarray(v0, complex) * (1.0 + 1j * h / speed)
+    st = rollout(x_nodes, x_mp, vol, mass, v0c, p, steps, lists, complex_step=True)
+    grads["speed"] = loss(st, x_target).imag / h
+    return grads

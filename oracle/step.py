@@ -26,7 +26,8 @@ done at the end of the previous step (and once at t = 0), so that
 Readings: du_0 = dt v_0 at the nodes (the central difference needs one
 increment to start); the wall is rigid and frictionless: a node whose
 predicted gap g = (x* - x_bar).n is negative is projected onto the plane and
-its increment set to the projected motion.
+its increment set to the projected motion; a node that has left every
+support (zero lumped mass, zero force) keeps its increment.
 """
 from __future__ import annotations
 
@@ -87,7 +88,11 @@ def assemble(st, p):
 def node_update(st, p):
     """Central difference with lumped mass, then the rigid-wall projection."""
     dt = p["dt"]
-    du = st.du + dt * dt * st.f / st.m[:, None]
+    # a node outside every support has no lumped mass and no force: it keeps
+    # its increment (the central difference applies to nodes with mass)
+    has_mass = st.m.real > 0
+    m_safe = np.where(has_mass, st.m, 1.0)
+    du = st.du + np.where(has_mass[:, None], dt * dt * st.f / m_safe[:, None], 0.0)
     xs = st.x + du
     if p["wall"]:
         nrm = np.asarray(p["wall_n"], float)

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libotm.so")
 
 OTM_OK, OTM_ERR_ARG, OTM_ERR_CAPACITY, OTM_ERR_LME_NOCONV = 0, -1, -2, -3
 OTM_ERR_RM_NOCONV, OTM_ERR_INVERTED, OTM_ERR_NONFINITE, OTM_ERR_HIP = -4, -5, -6, -7
+OTM_ERR_SUPPORT = -8
 OTM_FP64, OTM_MIXED = 0, 1
 OTM_SCATTER_ATOMIC, OTM_SCATTER_SEGMENTED = 0, 1
 OTM_NEOHOOKE, OTM_J2_JC, OTM_J2_LINEAR = 0, 1, 2
@@ -64,6 +65,19 @@ class Diag(C.Structure):
     ]
 
 
+class Tape(C.Structure):
+    """otm_tape: one stored step of a forward trajectory."""
+    _fields_ = [("n_nodes", C.c_int64), ("n_mp", C.c_int64), ("pair_stride", C.c_int64)] + \
+        [(k, C.c_void_p) for k in ("x", "du", "m", "f", "xp", "vol", "lam", "Fd", "bed",
+                                  "epsbar", "T", "sigma", "nbr_offsets", "nbr_idx", "N", "dN")]
+
+
+class StateBar(C.Structure):
+    """otm_state_bar: adjoint of one step's state."""
+    _fields_ = [(k, C.c_void_p) for k in ("x", "du", "vol", "Fd", "bed", "epsbar", "T", "sigma",
+                                          "N", "dN")]
+
+
 _LIB = None
 
 _SIGS = {
@@ -90,8 +104,13 @@ _SIGS = {
                                       C.c_void_p, C.c_void_p]),
 }
 
-# optional entry points (present once the adjoint is built)
-_OPTIONAL = {}
+_OPTIONAL = {
+    "otm_adjoint_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int64]),
+    "otm_step_adjoint": (C.c_int32, [C.POINTER(Tape), C.POINTER(Tape), C.POINTER(Params),
+                                     C.c_double, C.c_void_p, C.POINTER(StateBar),
+                                     C.POINTER(StateBar), C.c_void_p, C.c_void_p, C.c_size_t,
+                                     C.c_void_p, C.c_void_p]),
+}
 
 
 def lib():

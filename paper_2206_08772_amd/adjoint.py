@@ -1,0 +1,156 @@
+"""Checkpointed reverse-mode gradients of OTM rollouts (float64, J2 models).
+
+``OTMRollout`` is a ``torch.autograd.Function``: its forward runs N explicit
+steps of libotm and keeps a copy of the state every ``k`` steps; its backward
+walks the segments in reverse, re-runs each segment from its checkpoint while
+keeping every step's state (the tape), then calls ``otm_step_adjoint`` step
+by step.  Device buffers are torch tensors; all arithmetic is in libotm.
+
+Gradients: with respect to the hardening constants (A, B, n of the
+Johnson-Cook law, or Y0, H for linear hardening) and to the scale of the
+initial nodal velocity field (v0 = speed * unit field, du_0 = dt v0).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import StateBar, Tape, check, lib
+from .sim import Sim, _ptr, _stream
+
+STATE_FIELDS = ("x", "du", "m", "f", "xp", "vol", "lam", "Fd", "bed", "epsbar", "T", "sigma",
+                "offsets", "idx", "N", "dN")
+
+
+def snapshot(sim):
+    """Device copy of a simulation's state (one tape entry / checkpoint)."""
+    return {k: getattr(sim, k).clone() for k in STATE_FIELDS}
+
+
+def restore(sim, snap):
+    for k in STATE_FIELDS:
+        getattr(sim, k).copy_(snap[k])
+
+
+def tape_struct(snap, n_nodes, n_mp, cap):
+    t = Tape()
+    t.n_nodes, t.n_mp, t.pair_stride = n_nodes, n_mp, cap
+    for k in ("x", "du", "m", "f", "xp", "vol", "lam", "Fd", "bed", "epsbar", "T", "sigma", "N",
+              "dN"):
+        setattr(t, k, _ptr(snap[k]).value)
+    t.nbr_offsets = _ptr(snap["offsets"]).value
+    t.nbr_idx = _ptr(snap["idx"]).value
+    return t
+
+
+class Bars:
+    """Adjoint buffers of one state (float64, the state's layouts)."""
+
+    def __init__(self, n_nodes, n_mp, cap, device):
+        z = lambda *s: torch.zeros(*s, dtype=torch.float64, device=device)
+        self.x, self.du = z(3, n_nodes), z(3, n_nodes)
+        self.vol, self.Fd, self.bed = z(n_mp), z(9, n_mp), z(6, n_mp)
+        self.epsbar, self.T, self.sigma = z(n_mp), z(n_mp), z(6, n_mp)
+        self.N, self.dN = z(cap), z(3, cap)
+
+    def zero_(self):
+        for k in ("x", "du", "vol", "Fd", "bed", "epsbar", "T", "sigma", "N", "dN"):
+            getattr(self, k).zero_()
+        return self
+
+    def struct(self):
+        b = StateBar()
+        for k in ("x", "du", "vol", "Fd", "bed", "epsbar", "T", "sigma", "N", "dN"):
+            setattr(b, k, _ptr(getattr(self, k)).value)
+        return b
+
+
+def rollout_forward(sim, steps, every, rebuild_every=1):
+    """Run ``steps`` steps from the initialised ``sim``, keeping a checkpoint
+    every ``every`` steps (and at 0).  Returns the checkpoint dict."""
+    ckpt = {0: snapshot(sim)}
+    for n in range(1, steps + 1):
+        sim.step(rebuild=(n % rebuild_every == 0))
+        if n % every == 0 and n < steps:
+            ckpt[n] = snapshot(sim)
+    return ckpt
+
+
+def rollout_backward(sim, ckpt, steps, every, xbar_final, rebuild_every=1):
+    """Adjoint sweep.  ``xbar_final`` is dL/dx at the last step ([3][n_nodes]).
+    Returns (theta_bar (3,), bars of state 0)."""
+    L = lib()
+    dev = sim.device
+    nn, nm, cap = sim.n_nodes, sim.n_mp, sim.cap
+    ws_bytes = int(L.otm_adjoint_workspace_bytes(nn, nm))
+    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+    theta = torch.zeros(3, dtype=torch.float64, device=dev)
+    mass = sim.mass
+    nxt, cur = Bars(nn, nm, cap, dev), Bars(nn, nm, cap, dev)
+    nxt.x.copy_(xbar_final)
+    starts = sorted(ckpt)
+    for s0 in reversed(starts):
+        s1 = min(s0 + every, steps)
+        restore(sim, ckpt[s0])
+        tape = [snapshot(sim)]
+        for n in range(s0 + 1, s1 + 1):
+            sim.step(rebuild=(n % rebuild_every == 0))
+            tape.append(snapshot(sim))
+        for j in range(s1 - s0 - 1, -1, -1):
+            t0 = tape_struct(tape[j], nn, nm, cap)
+            t1 = tape_struct(tape[j + 1], nn, nm, cap)
+            bn, bc = nxt.struct(), cur.struct()
+            check(L.otm_step_adjoint(C.byref(t0), C.byref(t1), C.byref(sim.p), sim.dt,
+                                     _ptr(mass), C.byref(bn), C.byref(bc), _ptr(theta), _ptr(ws),
+                                     ws_bytes, _ptr(sim.diag), _stream()), "otm_step_adjoint")
+            nxt, cur = cur, nxt
+        del tape
+    sim.check_diag()
+    return theta, nxt
+
+
+class OTMRollout(torch.autograd.Function):
+    """x_final = OTMRollout.apply(theta, speed, problem).
+
+    theta: (3,) float64 tensor of hardening constants (A, B, n for
+    Johnson-Cook); speed: scalar float64 tensor scaling ``problem['v0_unit']``.
+    ``problem`` is a dict with the workload arrays (x_nodes, x_mp, vol_mp,
+    mass_mp, v0_unit), ``params`` (flat dict, including dt), ``steps``,
+    ``every`` (checkpoint interval) and optional ``rebuild_every``.
+    Returns the final node positions (n_nodes, 3) on the device.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, speed, problem):
+        p = dict(problem["params"])
+        names = ("A", "B", "n") if p["model"] == _lib.OTM_J2_JC else ("Y0", "H", "_unused")
+        th = theta.detach().double().cpu().numpy()
+        for k, v in zip(names, th):
+            if k != "_unused":
+                p[k] = float(v)
+        v0 = float(speed) * np.asarray(problem["v0_unit"])
+        sim = Sim(problem["x_nodes"], problem["x_mp"], problem["vol_mp"], problem["mass_mp"], v0,
+                  p, precision="fp64", scatter=problem.get("scatter", "atomic"),
+                  device=problem.get("device", "cuda"))
+        sim.init()
+        ckpt = rollout_forward(sim, problem["steps"], problem["every"],
+                               problem.get("rebuild_every", 1))
+        sim.check_diag()
+        ctx.sim, ctx.ckpt, ctx.problem = sim, ckpt, problem
+        ctx.theta_device, ctx.speed_device = theta.device, speed.device
+        return sim.x.t().contiguous().clone()
+
+    @staticmethod
+    def backward(ctx, grad_x):
+        sim, problem = ctx.sim, ctx.problem
+        xbar = grad_x.to(dtype=torch.float64).t().contiguous()
+        theta_bar, bars0 = rollout_backward(sim, ctx.ckpt, problem["steps"], problem["every"],
+                                            xbar, problem.get("rebuild_every", 1))
+        unit = torch.as_tensor(np.ascontiguousarray(np.asarray(problem["v0_unit"]).T),
+                               dtype=torch.float64, device=sim.device)
+        speed_bar = sim.dt * (bars0.du * unit).sum()
+        ctx.sim = ctx.ckpt = None
+        return (theta_bar.to(ctx.theta_device), speed_bar.reshape(()).to(ctx.speed_device), None)

@@ -1,0 +1,858 @@
+// Adjoint (reverse-mode derivative) of one explicit step, float64.
+//
+// Given the adjoint of the state after step n (bar_next) and the stored
+// forward states n and n+1 (tapes), it produces the adjoint of state n and
+// adds the step's contribution to the gradient with respect to the hardening
+// constants.  Support lists are those of the stored trajectory (frozen).  The
+// step's data flow, reversed:
+//
+//   K1  shape functions of state n+1 (LME, Sec. 2.3): N_I = softmax(f_I),
+//       f_I = -beta |d_I|^2 + lambda . d_I, grad N_I = -N_I J^{-1} d_I, with
+//       lambda(d) implicit through sum N_I d_I = 0.  From the adjoints of N and
+//       grad N per pair it forms the adjoint of each offset d_I = x_p - x_I:
+//       x_p gets the sum, node I the negative (pre-summed in LDS, then
+//       float64 atomics).
+//   K3  MP update: x_p' = sum N_I x_I', dF = 1 + sum du_I' (x) grad N_I,
+//       F' = dF F, v' = det(dF) v and the J2 return map (Sec. 4.1/4.2) with
+//       Hencky strain: the spectral derivative of the isotropic tensor
+//       functions b_tr -> tau, b^e' (divided differences, stable for equal
+//       eigenvalues), the scalar chain through q_tr, and the implicit
+//       derivative of the return equation for dEpsbar, which also gives the
+//       parameter gradient.  Node adjoints of x' and du' are pre-summed in LDS.
+//   K5  node update (central difference + wall projection).
+//   K6  lumped mass and force of state n (nodal mass / residual equations).
+#include "constitutive.h"
+#include "launch.h"
+#include "otm_common.h"
+
+namespace otm {
+
+// ------------------------------------------------------------------ helpers
+// Workgroup-level sum of NV node values per node id in an LDS hash table,
+// flushed to global memory with one float64 atomic per node and value.
+template <int NV, int BITS>
+struct NodeSums {
+  static constexpr int kSlots = 1 << BITS;
+  int32_t keys[kSlots];
+  double vals[NV][kSlots];
+};
+
+template <int NV, int BITS>
+OTM_DEV void sums_clear(NodeSums<NV, BITS>& t) {
+  for (int s = threadIdx.x; s < NodeSums<NV, BITS>::kSlots; s += blockDim.x) {
+    t.keys[s] = -1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) t.vals[v][s] = 0.0;
+  }
+}
+
+// dst[v] is the v-th destination array ([n] each); values go to dst[v][I].
+template <int NV, int BITS>
+OTM_DEV void sums_add(NodeSums<NV, BITS>& t, int32_t I, const double c[NV],
+                      double* const dst[NV]) {
+  constexpr int kSlots = NodeSums<NV, BITS>::kSlots;
+  uint32_t h = ((uint32_t)I * 2654435761u) >> (32 - BITS);
+  for (int probe = 0; probe < 32; ++probe) {
+    const int32_t prev = atomicCAS(&t.keys[h], -1, I);
+    if (prev == -1 || prev == I) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) atomicAdd(&t.vals[v][h], c[v]);
+      return;
+    }
+    h = (h + 1) & (kSlots - 1);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) atomicAdd(&dst[v][I], c[v]);  // crowded table
+}
+
+template <int NV, int BITS>
+OTM_DEV void sums_flush(NodeSums<NV, BITS>& t, double* const dst[NV]) {
+  for (int s = threadIdx.x; s < NodeSums<NV, BITS>::kSlots; s += blockDim.x) {
+    const int32_t I = t.keys[s];
+    if (I < 0) continue;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) atomicAdd(&dst[v][I], t.vals[v][s]);
+  }
+}
+
+OTM_HD void mat3_mul(const double A[3][3], const double B[3][3], double C[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[i][j] = A[i][0] * B[0][j] + A[i][1] * B[1][j] + A[i][2] * B[2][j];
+}
+// cof(A) = det(A) A^{-T}
+OTM_HD void cofactor3(const double A[3][3], double C[3][3]) {
+  C[0][0] = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  C[0][1] = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  C[0][2] = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  C[1][0] = A[0][2] * A[2][1] - A[0][1] * A[2][2];
+  C[1][1] = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+  C[1][2] = A[0][1] * A[2][0] - A[0][0] * A[2][1];
+  C[2][0] = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+  C[2][1] = A[0][2] * A[1][0] - A[0][0] * A[1][2];
+  C[2][2] = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+}
+OTM_HD double det3m(const double A[3][3]) {
+  return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+         A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+         A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+}
+
+constexpr int kVi[6] = {0, 1, 2, 0, 1, 0}, kVj[6] = {0, 1, 2, 1, 2, 2};
+
+// Adjoint of the 6 stored components of a symmetric tensor -> the symmetric
+// full-matrix adjoint (dL = sum_ij Sb_ij dS_ij), and back.
+OTM_HD void voigt_bar_to_full(const double v[6], double S[3][3]) {
+  for (int c = 0; c < 6; ++c) {
+    const double w = c < 3 ? v[c] : 0.5 * v[c];
+    S[kVi[c]][kVj[c]] = w;
+    S[kVj[c]][kVi[c]] = w;
+  }
+}
+OTM_HD void full_bar_to_voigt(const double S[3][3], double v[6]) {
+  for (int c = 0; c < 6; ++c)
+    v[c] = c < 3 ? S[c][c] : S[kVi[c]][kVj[c]] + S[kVj[c]][kVi[c]];
+}
+
+// u / expm1(u) and expm1(a u) / expm1(u), accurate near u = 0.
+OTM_HD double ratio_u_expm1(double u) {
+  return fabs(u) < 1e-8 ? 1.0 - 0.5 * u : u / expm1(u);
+}
+OTM_HD double ratio_expm1(double a, double u) {
+  return fabs(u) < 1e-8 ? a * (1.0 + 0.5 * (a - 1.0) * u) : expm1(a * u) / expm1(u);
+}
+
+// Partial derivatives of the flow stress at (eb + x, x/dt, T*).
+struct FlowPartials {
+  double s_eb, s_T, s_th[3];
+};
+OTM_DEV FlowPartials flow_partials(const Mat<double>& M, double eb, double x, double Ts) {
+  FlowPartials P{0.0, 0.0, {0.0, 0.0, 0.0}};
+  if (M.model == OTM_J2_LINEAR) {
+    P.s_eb = M.H;
+    P.s_th[0] = 1.0;       // d/dY0
+    P.s_th[1] = eb + x;    // d/dH
+    return P;
+  }
+  const double e = eb + x;
+  double en = 0.0, hard = M.A, dhard = 0.0, lne = 0.0;
+  if (e > 0.0) {
+    en = pow(e, M.n);
+    hard = M.A + M.B * en;
+    dhard = M.B * M.n * en / e;
+    lne = log(e);
+  }
+  const double ratio = x / M.rate0dt;
+  const double rate = ratio > 1.0 ? 1.0 + M.C * log(ratio) : 1.0;
+  double therm = 1.0, dtherm = 0.0;
+  if (Ts > 0.0) {
+    const double tm = pow(Ts, M.m);
+    therm = 1.0 - tm;
+    dtherm = -M.m * tm / Ts;
+  }
+  P.s_eb = dhard * rate * therm;
+  P.s_T = hard * rate * dtherm;
+  P.s_th[0] = rate * therm;                 // d/dA
+  P.s_th[1] = en * rate * therm;            // d/dB
+  P.s_th[2] = M.B * en * lne * rate * therm;  // d/dn
+  return P;
+}
+
+// ---------------------------------------------------------------- K1: LME
+constexpr int kAdjG = 16;       // lanes per MP
+constexpr int kAdjPPL = 3;      // pairs per lane held in registers
+constexpr int kAdjLmeRounds = 8;  // MPs per workgroup = 16 * rounds
+
+struct AdjLmeArgs {
+  int64_t n_nodes, n_mp, stride;
+  const double* x;       // nodes of state n+1 [3][n_nodes]
+  const double* xp;      // [3][n_mp]
+  const double* lam;     // [3][n_mp]
+  const int64_t* off;
+  const int32_t* idx;
+  const double* Nb;      // adjoint of N per pair
+  const double* dNb;     // adjoint of grad N per pair [3][stride]
+  double beta;
+  double* xpb;           // out: adjoint of x_p from the shape functions [3][n_mp]
+  double* xb;            // in/out: adjoint of node positions [3][n_nodes]
+  otm_diag* diag;
+};
+
+__global__ __launch_bounds__(256) void k_adj_lme(AdjLmeArgs a) {
+  constexpr int G = kAdjG, PPL = kAdjPPL;
+  __shared__ NodeSums<3, 10> tab;
+  sums_clear(tab);
+  __syncthreads();
+  double* const dst[3] = {a.xb, a.xb + a.n_nodes, a.xb + 2 * a.n_nodes};
+  const int lane = threadIdx.x % G;
+  for (int round = 0; round < kAdjLmeRounds; ++round) {
+    const int64_t p = ((int64_t)xcd_block() * kAdjLmeRounds + round) * (256 / G) + threadIdx.x / G;
+    if (p >= a.n_mp) continue;
+    const int64_t o = a.off[p];
+    const int K = (int)(a.off[p + 1] - o);
+    if (K == 0 || K > G * PPL) {
+      if (lane == 0) {
+        a.xpb[p] = a.xpb[a.n_mp + p] = a.xpb[2 * a.n_mp + p] = 0.0;
+        if (K > 0) diag_fail(a.diag, OTM_ERR_SUPPORT, (uint64_t)p);
+      }
+      continue;
+    }
+    const double px = a.xp[p], py = a.xp[a.n_mp + p], pz = a.xp[2 * a.n_mp + p];
+    const double lam[3] = {a.lam[p], a.lam[a.n_mp + p], a.lam[2 * a.n_mp + p]};
+    double d[PPL][3], e[PPL], Nb[PPL], Gb[PPL][3];
+    int32_t node[PPL];
+    bool use[PPL];
+    double fm = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      const int q = k * G + lane;
+      use[k] = q < K;
+      const int64_t qq = o + (use[k] ? q : 0);
+      node[k] = a.idx[qq];
+      const int32_t I = node[k];
+      d[k][0] = px - a.x[I];
+      d[k][1] = py - a.x[a.n_nodes + I];
+      d[k][2] = pz - a.x[2 * a.n_nodes + I];
+      Nb[k] = a.Nb[qq];
+      Gb[k][0] = a.dNb[qq];
+      Gb[k][1] = a.dNb[a.stride + qq];
+      Gb[k][2] = a.dNb[2 * a.stride + qq];
+      const double prior = -a.beta * ((d[k][0] * d[k][0] + d[k][1] * d[k][1]) + d[k][2] * d[k][2]);
+      e[k] = prior + (lam[0] * d[k][0] + lam[1] * d[k][1] + lam[2] * d[k][2]);
+      if (use[k]) fm = fmax(fm, e[k]);
+    }
+    fm = group_max<G>(fm);
+    // forward quantities at the stored multiplier
+    double Z = 0, r[3] = {0, 0, 0}, S[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      e[k] = use[k] ? exp(e[k] - fm) : 0.0;
+      Z += e[k];
+      for (int i = 0; i < 3; ++i) r[i] += e[k] * d[k][i];
+      for (int c = 0; c < 6; ++c) S[c] += e[k] * d[k][kVi[c]] * d[k][kVj[c]];
+    }
+    Z = group_sum<G>(Z);
+    for (int i = 0; i < 3; ++i) r[i] = group_sum<G>(r[i]);
+    for (int c = 0; c < 6; ++c) S[c] = group_sum<G>(S[c]);
+    const double iz = 1.0 / Z;
+    for (int i = 0; i < 3; ++i) r[i] *= iz;
+    double J[6], Mi[6], det;
+    for (int c = 0; c < 6; ++c) J[c] = S[c] * iz - r[kVi[c]] * r[kVj[c]];
+    sym_inv(J, Mi, det);
+    double Nq[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) Nq[k] = e[k] * iz;
+
+    // grad N_I = -N_I M d_I
+    double db[PPL][3], Mb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      double Md[3], MG[3];
+      sym_mul_vec(Mi, d[k], Md);
+      sym_mul_vec(Mi, Gb[k], MG);
+      Nb[k] -= Gb[k][0] * Md[0] + Gb[k][1] * Md[1] + Gb[k][2] * Md[2];
+      for (int i = 0; i < 3; ++i) db[k][i] = -Nq[k] * MG[i];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Mb[i][j] -= Nq[k] * Gb[k][i] * d[k][j];
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Mb[i][j] = group_sum<G>(Mb[i][j]);
+    // M = J^{-1}:  Jb = -M Mb M
+    double Mf[3][3], T1[3][3], Jb[3][3];
+    for (int c = 0; c < 6; ++c) { Mf[kVi[c]][kVj[c]] = Mi[c]; Mf[kVj[c]][kVi[c]] = Mi[c]; }
+    mat3_mul(Mf, Mb, T1);
+    mat3_mul(T1, Mf, Jb);
+    double Js[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Js[i][j] = -(Jb[i][j] + Jb[j][i]);  // adjoint of sym part
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Jb[i][j] = -Jb[i][j];
+    // J = sum N d d^T - r r^T,  r = sum N d
+    double rb[3];
+    for (int i = 0; i < 3; ++i) rb[i] = -(Js[i][0] * r[0] + Js[i][1] * r[1] + Js[i][2] * r[2]);
+    double s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      double Jd[3], dJd = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        Jd[i] = Js[i][0] * d[k][0] + Js[i][1] * d[k][1] + Js[i][2] * d[k][2];
+        for (int j = 0; j < 3; ++j) dJd += d[k][i] * Jb[i][j] * d[k][j];
+      }
+      Nb[k] += dJd + rb[0] * d[k][0] + rb[1] * d[k][1] + rb[2] * d[k][2];
+      for (int i = 0; i < 3; ++i) db[k][i] += Nq[k] * (Jd[i] + rb[i]);
+      s1 += use[k] ? Nq[k] * Nb[k] : 0.0;
+    }
+    s1 = group_sum<G>(s1);
+    // N = softmax(f), f = -beta |d|^2 + lambda . d
+    double lb[3] = {0, 0, 0}, gk[PPL][3];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      const double fb = use[k] ? Nq[k] * (Nb[k] - s1) : 0.0;
+      for (int i = 0; i < 3; ++i) {
+        gk[k][i] = -2.0 * a.beta * d[k][i] + lam[i];
+        db[k][i] += fb * gk[k][i];
+        lb[i] += fb * d[k][i];
+      }
+    }
+    for (int i = 0; i < 3; ++i) lb[i] = group_sum<G>(lb[i]);
+    // lambda(d) from r(lambda, d) = 0: d_bar -= (dr/dd)^T J^{-1} lambda_bar
+    double w[3];
+    sym_mul_vec(Mi, lb, w);
+    double xpb[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      const double dw = (d[k][0] - r[0]) * w[0] + (d[k][1] - r[1]) * w[1] + (d[k][2] - r[2]) * w[2];
+      for (int i = 0; i < 3; ++i) {
+        db[k][i] -= Nq[k] * (w[i] + dw * gk[k][i]);
+        if (use[k]) xpb[i] += db[k][i];
+      }
+    }
+    for (int i = 0; i < 3; ++i) xpb[i] = group_sum<G>(xpb[i]);
+    if (lane == 0) {
+      a.xpb[p] = xpb[0];
+      a.xpb[a.n_mp + p] = xpb[1];
+      a.xpb[2 * a.n_mp + p] = xpb[2];
+    }
+    // d = x_p - x_I: node I gets -d_bar
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      if (!use[k]) continue;
+      const double c[3] = {-db[k][0], -db[k][1], -db[k][2]};
+      sums_add(tab, node[k], c, dst);
+    }
+  }
+  __syncthreads();
+  sums_flush(tab, dst);
+}
+
+// ------------------------------------------------ K3: MP update (J2 model)
+constexpr int kAdjMpBlock = 128;
+constexpr int kAdjGather = 8;
+
+struct AdjMpArgs {
+  int64_t n_nodes, n_mp, stride;  // stride: pair arrays of state n
+  // state n (tape)
+  const int64_t* off;
+  const int32_t* idx;
+  const double* N;
+  const double* dN;
+  const double* vol;
+  const double* Fd;
+  const double* bed;
+  const double* epsbar;
+  const double* T;
+  // nodes of state n+1
+  const double* x1;
+  const double* du1;
+  // adjoints of state n+1 (in)
+  const double* xpb1;   // from K1
+  const double* volb1;
+  const double* Fdb1;
+  const double* bedb1;
+  const double* epsb1;
+  const double* Tb1;
+  const double* sigb1;
+  // adjoints of state n (out)
+  double* volb;
+  double* Fdb;
+  double* bedb;
+  double* epsb;
+  double* Tb;
+  double* Nb;      // per pair of state n (written)
+  double* dNb;     // [3][stride] (written)
+  double* xb1;     // node adjoints of state n+1 (accumulated)
+  double* dub1;
+  double* theta_part;  // [gridDim][3]
+  Mat<double> M;
+  double dt;
+  otm_diag* diag;
+};
+
+// Adjoint of the return map at one MP.  dF, F_n, b^e_n - 1, epsbar_n, T_n:
+// forward inputs; *_b1: adjoints of its outputs.  Adds to dFb and returns the
+// adjoints of the inputs.
+OTM_DEV void return_map_adjoint(const Mat<double>& M, const double dF[3][3],
+                                const double Fn[3][3], const double bd[6], double ebn,
+                                double Tn, const double sigb[6], const double bedb1[6],
+                                double epsb1, double Tb1, const double Fb1[3][3],
+                                double dFb[3][3], double Fnb[3][3], double bedb[6],
+                                double& ebnb, double& Tnb, double thb[3], bool& ok) {
+  // ---- forward recomputation (the same arithmetic as the MP pass)
+  M3<double> h;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) h.a[i][j] = dF[i][j] - (i == j ? 1.0 : 0.0);
+  S3<double> bds;
+  for (int c = 0; c < 6; ++c) bds.v[c] = bd[c];
+  const M3<double> B = full(bds);
+  M3<double> HB;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      HB.a[i][j] = B.a[i][j] + h.a[i][0] * B.a[0][j] + h.a[i][1] * B.a[1][j] + h.a[i][2] * B.a[2][j];
+  S3<double> dtr;
+  for (int c = 0; c < 6; ++c) {
+    const int i = kVi[c], j = kVj[c];
+    const double hbh = HB.a[i][j] + HB.a[i][0] * h.a[j][0] + HB.a[i][1] * h.a[j][1] + HB.a[i][2] * h.a[j][2];
+    dtr.v[c] = h.a[i][j] + h.a[j][i] +
+               (h.a[i][0] * h.a[j][0] + h.a[i][1] * h.a[j][1] + h.a[i][2] * h.a[j][2]) + hbh;
+  }
+  double d[3], V[3][3];
+  jacobi_eig(dtr, d, V);
+  double e[3];
+  for (int a = 0; a < 3; ++a) e[a] = 0.5 * log1p(d[a]);
+  const double tr = e[0] + e[1] + e[2];
+  double dev[3];
+  for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / 3.0;
+  const double s2 = dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2];
+  const double q = 2.0 * M.mu * sqrt(1.5 * s2);
+  double Ts = 0.0, tunc = 0.0;
+  if (M.model == OTM_J2_JC) {
+    tunc = (Tn - M.Tr) / (M.Tm - M.Tr);
+    Ts = tunc < 0.0 ? 0.0 : (tunc > 1.0 ? 1.0 : tunc);
+  }
+  double sy0, dsy0;
+  flow_stress(M, ebn, 0.0, Ts, sy0, dsy0);
+  const bool plastic = q > sy0;
+  double deps = 0.0, c = 0.0;
+  ok = true;
+  if (plastic) {
+    deps = solve_return(M, q, ebn, Ts, sy0, ok);
+    c = 3.0 * M.mu * deps / q;
+  }
+  double eps[3], tau[3], bm1[3];
+  for (int a = 0; a < 3; ++a) {
+    eps[a] = e[a] - c * dev[a];
+    tau[a] = M.K * tr + 2.0 * M.mu * (1.0 - c) * dev[a];
+    bm1[a] = expm1(2.0 * eps[a]);
+  }
+  double Fp[3][3];
+  mat3_mul(dF, Fn, Fp);
+  const double Jp = det3m(Fp);
+
+  // ---- adjoint: sigma = tau / J', b^e' = 1 + V diag(bm1) V^T
+  double Sb[3][3], Bb[3][3];
+  voigt_bar_to_full(sigb, Sb);
+  voigt_bar_to_full(bedb1, Bb);
+  double Jpb = 0.0;
+  double taub[3][3];
+  {
+    // sigma_ij = sum_a V_ia tau_a V_ja / J'
+    double sig_dot = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double sij = (V[i][0] * tau[0] * V[j][0] + V[i][1] * tau[1] * V[j][1] +
+                            V[i][2] * tau[2] * V[j][2]) / Jp;
+        sig_dot += Sb[i][j] * sij;
+        taub[i][j] = Sb[i][j] / Jp;
+      }
+    Jpb = -sig_dot / Jp;
+  }
+  // eigen-basis components of the output adjoints
+  double Tt[3][3], Bt[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double st = 0.0, sb = 0.0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          st += V[i][a] * taub[i][j] * V[j][b];
+          sb += V[i][a] * Bb[i][j] * V[j][b];
+        }
+      Tt[a][b] = st;
+      Bt[a][b] = sb;
+    }
+  // scalar chain through the principal values
+  double epsb[3], devb[3];
+  const double rhoCp = M.rhoCp;
+  double cb = 0.0, depsb = epsb1, qb = 0.0, trb = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    epsb[a] = Bt[a][a] * 2.0 * (bm1[a] + 1.0);
+    trb += M.K * Tt[a][a];
+    devb[a] = 2.0 * M.mu * (1.0 - c) * Tt[a][a] - c * epsb[a];
+    cb += -2.0 * M.mu * dev[a] * Tt[a][a] - dev[a] * epsb[a];
+  }
+  ebnb = epsb1;
+  Tnb = Tb1;
+  if (M.model == OTM_J2_JC) {
+    // T' = T_n + chi (1 - c) q deps / (rho0 Cp)
+    cb += -M.chi * q * deps / rhoCp * Tb1;
+    depsb += M.chi * (1.0 - c) * q / rhoCp * Tb1;
+    qb += M.chi * (1.0 - c) * deps / rhoCp * Tb1;
+  }
+  thb[0] = thb[1] = thb[2] = 0.0;
+  if (plastic) {
+    // c = 3 mu deps / q
+    depsb += cb * 3.0 * M.mu / q;
+    qb -= cb * c / q;
+    // deps(q, epsbar_n, T*, theta) from q - 3 mu x - sigma_Y(ebn + x, x/dt, T*) = 0
+    double sy, dsy;
+    flow_stress(M, ebn, deps, Ts, sy, dsy);
+    const double gx = -3.0 * M.mu - dsy;
+    const FlowPartials P = flow_partials(M, ebn, deps, Ts);
+    qb += depsb * (-1.0 / gx);
+    ebnb += depsb * P.s_eb / gx;
+    if (M.model == OTM_J2_JC && tunc > 0.0 && tunc < 1.0)
+      Tnb += depsb * P.s_T / gx / (M.Tm - M.Tr);
+    for (int k = 0; k < 3; ++k) thb[k] = depsb * P.s_th[k] / gx;
+  }
+  // q = 2 mu sqrt(3/2 sum dev^2)
+  if (q > 0.0)
+    for (int a = 0; a < 3; ++a) devb[a] += qb * 6.0 * M.mu * M.mu * dev[a] / q;
+  const double devb_sum = devb[0] + devb[1] + devb[2];
+  double db[3];
+  for (int a = 0; a < 3; ++a) {
+    const double eb = epsb[a] + trb + devb[a] - devb_sum / 3.0;
+    db[a] = eb * 0.5 / (1.0 + d[a]);
+  }
+  // full adjoint of b_tr - 1 in the eigen-basis: diagonal from the scalar
+  // chain, off-diagonal from divided differences of tau_a and bm1_a
+  double Dt[3][3];
+  for (int a = 0; a < 3; ++a) Dt[a][a] = db[a];
+  for (int a = 0; a < 3; ++a)
+    for (int b = a + 1; b < 3; ++b) {
+      const double u = 2.0 * (e[a] - e[b]);
+      const double rt = M.mu * (1.0 - c) * ratio_u_expm1(u) / (1.0 + d[b]);
+      const double rbm = (bm1[b] + 1.0) * ratio_expm1(1.0 - c, u) / (1.0 + d[b]);
+      const double v = Tt[a][b] * rt + Bt[a][b] * rbm;
+      Dt[a][b] = Dt[b][a] = v;
+    }
+  double Db[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) s += V[i][a] * Dt[a][b] * V[j][b];
+      Db[i][j] = s;
+    }
+  // b_tr = dF b^e_n dF^T
+  double be[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) be[i][j] = B.a[i][j] + (i == j ? 1.0 : 0.0);
+  double DbF[3][3], DbFbe[3][3], FtDb[3][3], BeB[3][3];
+  mat3_mul(Db, dF, DbF);
+  mat3_mul(DbF, be, DbFbe);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) dFb[i][j] += 2.0 * DbFbe[i][j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) FtDb[i][j] = dF[0][i] * Db[0][j] + dF[1][i] * Db[1][j] + dF[2][i] * Db[2][j];
+  mat3_mul(FtDb, dF, BeB);
+  full_bar_to_voigt(BeB, bedb);
+  // J' = det F', F' = dF F_n
+  double cofp[3][3], Fpb[3][3];
+  cofactor3(Fp, cofp);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Fpb[i][j] = Fb1[i][j] + Jpb * cofp[i][j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      dFb[i][j] += Fpb[i][0] * Fn[j][0] + Fpb[i][1] * Fn[j][1] + Fpb[i][2] * Fn[j][2];
+      Fnb[i][j] = dF[0][i] * Fpb[0][j] + dF[1][i] * Fpb[1][j] + dF[2][i] * Fpb[2][j];
+    }
+}
+
+__global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
+  __shared__ double sums[9][kAdjMpBlock];   // dF - 1, then the adjoint of dF
+  __shared__ NodeSums<6, 10> tab;
+  __shared__ double thred[3][kAdjMpBlock];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)xcd_block() * kAdjMpBlock;
+  const int lane = tid % kAdjGather;
+  constexpr int groups = kAdjMpBlock / kAdjGather;
+  sums_clear(tab);
+  // phase 1: H = dF - 1 = sum du'_I (x) grad N_I
+  for (int r = 0; r < kAdjMpBlock / groups; ++r) {
+    const int local = r * groups + tid / kAdjGather;
+    const int64_t p = base + local;
+    double h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (p < a.n_mp) {
+      for (int64_t q = a.off[p] + lane; q < a.off[p + 1]; q += kAdjGather) {
+        const int32_t I = a.idx[q];
+        const double g[3] = {a.dN[q], a.dN[a.stride + q], a.dN[2 * a.stride + q]};
+        const double u[3] = {a.du1[I], a.du1[a.n_nodes + I], a.du1[2 * a.n_nodes + I]};
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) h[3 * i + j] += u[i] * g[j];
+      }
+    }
+    for (int c = 0; c < 9; ++c) h[c] = group_sum<kAdjGather>(h[c]);
+    if (lane == 0)
+      for (int c = 0; c < 9; ++c) sums[c][local] = h[c];
+  }
+  __syncthreads();
+  // phase 2: one lane per MP
+  double th[3] = {0, 0, 0};
+  {
+    const int64_t p = base + tid;
+    if (p < a.n_mp) {
+      const int64_t n = a.n_mp;
+      double dF[3][3], Fn[3][3], Fb1[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          dF[i][j] = sums[3 * i + j][tid] + (i == j ? 1.0 : 0.0);
+          Fn[i][j] = a.Fd[(3 * i + j) * n + p] + (i == j ? 1.0 : 0.0);
+          Fb1[i][j] = a.Fdb1[(3 * i + j) * n + p];
+        }
+      double bd[6], sigb[6], bedb1[6];
+      for (int c = 0; c < 6; ++c) {
+        bd[c] = a.bed[c * n + p];
+        sigb[c] = a.sigb1[c * n + p];
+        bedb1[c] = a.bedb1[c * n + p];
+      }
+      double dFb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fnb[3][3], bedb[6], ebnb, Tnb;
+      bool ok;
+      return_map_adjoint(a.M, dF, Fn, bd, a.epsbar[p], a.T[p], sigb, bedb1, a.epsb1[p], a.Tb1[p],
+                         Fb1, dFb, Fnb, bedb, ebnb, Tnb, th, ok);
+      if (!ok) diag_fail(a.diag, OTM_ERR_RM_NOCONV, (uint64_t)p);
+      // v' = det(dF) v
+      double cof[3][3];
+      cofactor3(dF, cof);
+      const double detdF = det3m(dF);
+      const double vb1 = a.volb1[p];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) dFb[i][j] += vb1 * a.vol[p] * cof[i][j];
+      a.volb[p] = vb1 * detdF;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) a.Fdb[(3 * i + j) * n + p] = Fnb[i][j];
+      for (int c = 0; c < 6; ++c) a.bedb[c * n + p] = bedb[c];
+      a.epsb[p] = ebnb;
+      a.Tb[p] = Tnb;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) sums[3 * i + j][tid] = dFb[i][j];
+    }
+  }
+  for (int k = 0; k < 3; ++k) thred[k][tid] = th[k];
+  __syncthreads();
+  // parameter gradient: one partial per workgroup
+  for (int o = kAdjMpBlock / 2; o > 0; o >>= 1) {
+    if (tid < o)
+      for (int k = 0; k < 3; ++k) thred[k][tid] += thred[k][tid + o];
+    __syncthreads();
+  }
+  if (tid == 0)
+    for (int k = 0; k < 3; ++k) a.theta_part[blockIdx.x * 3 + k] = thred[k][0];
+  // phase 3: per pair, x_p' = sum N_I x_I' and dF = 1 + sum du_I' (x) grad N_I
+  double* const dst[6] = {a.xb1, a.xb1 + a.n_nodes, a.xb1 + 2 * a.n_nodes,
+                          a.dub1, a.dub1 + a.n_nodes, a.dub1 + 2 * a.n_nodes};
+  for (int r = 0; r < kAdjMpBlock / groups; ++r) {
+    const int local = r * groups + tid / kAdjGather;
+    const int64_t p = base + local;
+    if (p >= a.n_mp) continue;
+    const double xpb[3] = {a.xpb1[p], a.xpb1[a.n_mp + p], a.xpb1[2 * a.n_mp + p]};
+    double Fb[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Fb[i][j] = sums[3 * i + j][local];
+    for (int64_t q = a.off[p] + lane; q < a.off[p + 1]; q += kAdjGather) {
+      const int32_t I = a.idx[q];
+      const double w = a.N[q];
+      const double g[3] = {a.dN[q], a.dN[a.stride + q], a.dN[2 * a.stride + q]};
+      const double u[3] = {a.du1[I], a.du1[a.n_nodes + I], a.du1[2 * a.n_nodes + I]};
+      const double xI[3] = {a.x1[I], a.x1[a.n_nodes + I], a.x1[2 * a.n_nodes + I]};
+      a.Nb[q] = xI[0] * xpb[0] + xI[1] * xpb[1] + xI[2] * xpb[2];
+      for (int j = 0; j < 3; ++j)
+        a.dNb[j * a.stride + q] = Fb[0][j] * u[0] + Fb[1][j] * u[1] + Fb[2][j] * u[2];
+      double c[6];
+      for (int i = 0; i < 3; ++i) {
+        c[i] = w * xpb[i];
+        c[3 + i] = Fb[i][0] * g[0] + Fb[i][1] * g[1] + Fb[i][2] * g[2];
+      }
+      sums_add(tab, I, c, dst);
+    }
+  }
+  __syncthreads();
+  sums_flush(tab, dst);
+}
+
+// ----------------------------------------------------------- K5: nodes
+struct AdjNodeArgs {
+  int64_t n;
+  const double* x;    // state n
+  const double* du;
+  const double* m;
+  const double* f;
+  const double* xb1;  // adjoint of x_{n+1}, du_{n+1}
+  const double* dub1;
+  double* xb;         // out: adjoint of x_n, du_n
+  double* dub;
+  double* fb;         // out: adjoint of f_n, m_n
+  double* mb;
+  double dt2;
+  int wall;
+  double wx[3], wn[3];
+};
+
+__global__ __launch_bounds__(256) void k_adj_node(AdjNodeArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t n = a.n;
+  const double mi = a.m[i];
+  double fv[3], pred[3], xs[3], xb1[3], dub1[3];
+  const bool has_mass = mi > 0.0;
+  for (int c = 0; c < 3; ++c) {
+    fv[c] = a.f[c * n + i];
+    pred[c] = a.du[c * n + i] + (has_mass ? a.dt2 * fv[c] / mi : 0.0);
+    xs[c] = a.x[c * n + i] + pred[c];
+    xb1[c] = a.xb1[c * n + i];
+    dub1[c] = a.dub1[c * n + i];
+  }
+  double xb[3], pb[3];  // adjoints of x_n and of the predicted increment
+  bool hit = false;
+  if (a.wall) {
+    const double g = (xs[0] - a.wx[0]) * a.wn[0] + (xs[1] - a.wx[1]) * a.wn[1] + (xs[2] - a.wx[2]) * a.wn[2];
+    hit = g < 0.0;
+  }
+  if (!hit) {
+    // du' = pred, x' = x + du'
+    for (int c = 0; c < 3; ++c) {
+      xb[c] = xb1[c];
+      pb[c] = dub1[c] + xb1[c];
+    }
+  } else {
+    // x' = P x* + (x_w . n) n with P = 1 - n n^T, x* = x + pred, du' = x' - x
+    double t[3];
+    for (int c = 0; c < 3; ++c) t[c] = xb1[c] + dub1[c];
+    const double tn = t[0] * a.wn[0] + t[1] * a.wn[1] + t[2] * a.wn[2];
+    double xsb[3];
+    for (int c = 0; c < 3; ++c) xsb[c] = t[c] - tn * a.wn[c];
+    for (int c = 0; c < 3; ++c) {
+      xb[c] = xsb[c] - dub1[c];
+      pb[c] = xsb[c];
+    }
+  }
+  double fm = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    a.xb[c * n + i] = xb[c];
+    a.dub[c * n + i] = pb[c];
+    a.fb[c * n + i] = has_mass ? a.dt2 / mi * pb[c] : 0.0;
+    fm += fv[c] * pb[c];
+  }
+  a.mb[i] = has_mass ? -a.dt2 * fm / (mi * mi) : 0.0;
+}
+
+// ------------------------------------------------------- K6: assembly
+struct AdjAsmArgs {
+  int64_t n_nodes, n_mp, stride;
+  const int64_t* off;
+  const int32_t* idx;
+  const double* N;
+  const double* dN;
+  const double* vol;
+  const double* mass;
+  const double* sigma;
+  const double* fb;
+  const double* mb;
+  double* Nb;      // += per pair
+  double* dNb;     // +=
+  double* sigb;    // written
+  double* volb;    // +=
+};
+
+constexpr int kAdjAsmLanes = 8;
+__global__ __launch_bounds__(256) void k_adj_assembly(AdjAsmArgs a) {
+  const int64_t p = (int64_t)xcd_block() * (256 / kAdjAsmLanes) + threadIdx.x / kAdjAsmLanes;
+  const int lane = threadIdx.x % kAdjAsmLanes;
+  if (p >= a.n_mp) return;
+  const int64_t n = a.n_mp;
+  const double v = a.vol[p], mp = a.mass[p];
+  double s[6];
+  for (int c = 0; c < 6; ++c) s[c] = a.sigma[c * n + p];
+  double sb[6] = {0, 0, 0, 0, 0, 0}, vb = 0.0;
+  for (int64_t q = a.off[p] + lane; q < a.off[p + 1]; q += kAdjAsmLanes) {
+    const int32_t I = a.idx[q];
+    const double g[3] = {a.dN[q], a.dN[a.stride + q], a.dN[2 * a.stride + q]};
+    const double f[3] = {a.fb[I], a.fb[a.n_nodes + I], a.fb[2 * a.n_nodes + I]};
+    // m_I += N m_p
+    a.Nb[q] += a.mb[I] * mp;
+    // f_I = -v sigma g
+    const double sf[3] = {s[0] * f[0] + s[3] * f[1] + s[5] * f[2],
+                          s[3] * f[0] + s[1] * f[1] + s[4] * f[2],
+                          s[5] * f[0] + s[4] * f[1] + s[2] * f[2]};
+    for (int j = 0; j < 3; ++j) a.dNb[j * a.stride + q] -= v * sf[j];
+    vb -= sf[0] * g[0] + sf[1] * g[1] + sf[2] * g[2];
+    sb[0] -= v * f[0] * g[0];
+    sb[1] -= v * f[1] * g[1];
+    sb[2] -= v * f[2] * g[2];
+    sb[3] -= v * (f[0] * g[1] + f[1] * g[0]);
+    sb[4] -= v * (f[1] * g[2] + f[2] * g[1]);
+    sb[5] -= v * (f[0] * g[2] + f[2] * g[0]);
+  }
+  for (int c = 0; c < 6; ++c) sb[c] = group_sum<kAdjAsmLanes>(sb[c]);
+  vb = group_sum<kAdjAsmLanes>(vb);
+  if (lane == 0) {
+    for (int c = 0; c < 6; ++c) a.sigb[c * n + p] = sb[c];
+    a.volb[p] += vb;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adj_theta(const double* part, int64_t nb,
+                                                   double* theta_bar) {
+  __shared__ double red[3][256];
+  double s[3] = {0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nb; b += 256)
+    for (int k = 0; k < 3; ++k) s[k] += part[b * 3 + k];
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) theta_bar[k] += red[k][0];
+}
+
+// ------------------------------------------------------------ host side
+size_t adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp) {
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const int64_t nb = (n_mp + kAdjMpBlock - 1) / kAdjMpBlock + 1;
+  return al(sizeof(double) * 3 * (size_t)n_mp) + al(sizeof(double) * 4 * (size_t)n_nodes) +
+         al(sizeof(double) * 3 * (size_t)nb);
+}
+
+void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_params& p,
+                         double dt, const double* mass, otm_state_bar& b1, otm_state_bar& b0,
+                         double* theta_bar, void* ws, otm_diag* diag, hipStream_t s) {
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const int64_t nn = t0.n_nodes, nm = t0.n_mp;
+  char* c = (char*)ws;
+  double* xpb = (double*)c;
+  c += al(sizeof(double) * 3 * (size_t)nm);
+  double* fb = (double*)c;
+  double* mb = fb + 3 * nn;
+  c += al(sizeof(double) * 4 * (size_t)nn);
+  double* theta_part = (double*)c;
+
+  if (nm > 0) {
+    AdjLmeArgs la{nn, nm, t1.pair_stride, t1.x, t1.xp, t1.lam, t1.nbr_offsets, t1.nbr_idx,
+                  b1.N, b1.dN, p.beta, xpb, b1.x, diag};
+    const int per = (256 / kAdjG) * kAdjLmeRounds;
+    k_adj_lme<<<(unsigned)((nm + per - 1) / per), 256, 0, s>>>(la);
+    AdjMpArgs ma;
+    ma.n_nodes = nn; ma.n_mp = nm; ma.stride = t0.pair_stride;
+    ma.off = t0.nbr_offsets; ma.idx = t0.nbr_idx; ma.N = t0.N; ma.dN = t0.dN;
+    ma.vol = t0.vol; ma.Fd = t0.Fd; ma.bed = t0.bed; ma.epsbar = t0.epsbar; ma.T = t0.T;
+    ma.x1 = t1.x; ma.du1 = t1.du;
+    ma.xpb1 = xpb; ma.volb1 = b1.vol; ma.Fdb1 = b1.Fd; ma.bedb1 = b1.bed; ma.epsb1 = b1.epsbar;
+    ma.Tb1 = b1.T; ma.sigb1 = b1.sigma;
+    ma.volb = b0.vol; ma.Fdb = b0.Fd; ma.bedb = b0.bed; ma.epsb = b0.epsbar; ma.Tb = b0.T;
+    ma.Nb = b0.N; ma.dNb = b0.dN; ma.xb1 = b1.x; ma.dub1 = b1.du;
+    ma.theta_part = theta_part;
+    ma.M = make_mat<double>(p, dt);
+    ma.dt = dt;
+    ma.diag = diag;
+    const unsigned nbm = (unsigned)((nm + kAdjMpBlock - 1) / kAdjMpBlock);
+    k_adj_mp<<<nbm, kAdjMpBlock, 0, s>>>(ma);
+    k_adj_theta<<<1, 256, 0, s>>>(theta_part, nbm, theta_bar);
+  }
+  if (nn > 0) {
+    AdjNodeArgs na;
+    na.n = nn; na.x = t0.x; na.du = t0.du; na.m = t0.m; na.f = t0.f;
+    na.xb1 = b1.x; na.dub1 = b1.du; na.xb = b0.x; na.dub = b0.du; na.fb = fb; na.mb = mb;
+    na.dt2 = dt * dt;
+    na.wall = p.wall_enabled;
+    for (int k = 0; k < 3; ++k) { na.wx[k] = p.wall_x[k]; na.wn[k] = p.wall_n[k]; }
+    k_adj_node<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(na);
+  }
+  if (nm > 0) {
+    AdjAsmArgs aa{nn, nm, t0.pair_stride, t0.nbr_offsets, t0.nbr_idx, t0.N, t0.dN, t0.vol,
+                  mass, t0.sigma, fb, mb, b0.N, b0.dN, b0.sigma, b0.vol};
+    k_adj_assembly<<<(unsigned)((nm + (256 / kAdjAsmLanes) - 1) / (256 / kAdjAsmLanes)), 256, 0,
+                     s>>>(aa);
+  }
+}
+
+}  // namespace otm

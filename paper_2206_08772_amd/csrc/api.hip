@@ -156,6 +156,7 @@ const char* otm_status_string(otm_status s) {
     case OTM_ERR_INVERTED: return "OTM_ERR_INVERTED: det(dF) <= 0 at a material point";
     case OTM_ERR_NONFINITE: return "OTM_ERR_NONFINITE: non-finite stress or position";
     case OTM_ERR_HIP: return "OTM_ERR_HIP: HIP runtime error";
+    case OTM_ERR_SUPPORT: return "OTM_ERR_SUPPORT: support longer than the adjoint handles";
     default: return "unknown otm_status";
   }
 }
@@ -176,7 +177,7 @@ otm_status otm_diag_read(const otm_diag* diag, otm_diag* host_out, hipStream_t s
   if (hipMemcpyAsync(host_out, diag, sizeof(otm_diag), hipMemcpyDeviceToHost, s) != hipSuccess)
     return OTM_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return OTM_ERR_HIP;
-  for (int k = 0; k < 7; ++k)
+  for (int k = 0; k < 8; ++k)
     if (host_out->flags & (1u << k)) return (otm_status)(-(k + 1));
   return OTM_OK;
 }
@@ -272,7 +273,7 @@ static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32
   if (check_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &w) != OTM_OK)
     return OTM_ERR_ARG;
   mark(ev, 0, s);
-  launch_node_update(*st, *p, dt, scatter_mode == OTM_SCATTER_ATOMIC, w.nodes, s);
+  launch_node_update(*st, *p, dt, scatter_mode == OTM_SCATTER_ATOMIC, w.nodes, diag, s);
   mark(ev, 1, s);
   launch_mp_update(*st, *p, dt, w.nodes, diag, s);
   mark(ev, 2, s);
@@ -291,6 +292,46 @@ otm_status otm_step_profiled(otm_state* st, const otm_params* p, double dt, int3
                              hipEvent_t* events, hipStream_t s) {
   if (events == nullptr) return OTM_ERR_ARG;
   return step_impl(st, p, dt, rebuild, scatter_mode, ws, ws_bytes, diag, events, s);
+}
+
+size_t otm_adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp) {
+  if (n_nodes < 0 || n_mp < 0) return 0;
+  return adjoint_workspace_bytes(n_nodes, n_mp);
+}
+
+static bool tape_ok(const otm_tape* t) {
+  if (t == nullptr || t->n_nodes < 0 || t->n_mp < 0 || t->pair_stride < 0) return false;
+  const void* p8[] = {t->x, t->du, t->m, t->f, t->xp, t->vol, t->lam, t->Fd, t->bed,
+                      t->epsbar, t->T, t->sigma, t->nbr_offsets, t->N, t->dN};
+  for (const void* q : p8)
+    if (!dev_ok(q, 8)) return false;
+  return dev_ok(t->nbr_idx, 4);
+}
+
+static bool bar_ok(const otm_state_bar* b) {
+  if (b == nullptr) return false;
+  const void* p8[] = {b->x, b->du, b->vol, b->Fd, b->bed, b->epsbar, b->T, b->sigma, b->N, b->dN};
+  for (const void* q : p8)
+    if (!dev_ok(q, 8)) return false;
+  return true;
+}
+
+otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_params* p,
+                            double dt, const double* mass, otm_state_bar* bar_next,
+                            otm_state_bar* bar, double* theta_bar, void* ws, size_t ws_bytes,
+                            otm_diag* diag, hipStream_t s) {
+  otm_status e;
+  if ((e = check_params(p)) != OTM_OK) return e;
+  if (p->model == OTM_NEOHOOKE) return OTM_ERR_ARG;  // adjoint covers the J2 models
+  if (!tape_ok(tn) || !tape_ok(tn1) || !bar_ok(bar_next) || !bar_ok(bar)) return OTM_ERR_ARG;
+  if (tn->n_nodes != tn1->n_nodes || tn->n_mp != tn1->n_mp) return OTM_ERR_ARG;
+  if (!(dt > 0) || !dev_ok(mass, 8) || !dev_ok(theta_bar, 8) || !dev_ok(diag, 8))
+    return OTM_ERR_ARG;
+  if (ws == nullptr || !aligned(ws, 256) ||
+      ws_bytes < adjoint_workspace_bytes(tn->n_nodes, tn->n_mp))
+    return OTM_ERR_ARG;
+  launch_step_adjoint(*tn, *tn1, *p, dt, mass, *bar_next, *bar, theta_bar, ws, diag, s);
+  return hip_status();
 }
 
 }  // extern "C"

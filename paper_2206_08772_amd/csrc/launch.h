@@ -66,7 +66,7 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
 // Nodes and material points.
 // Node records: packed[2 I] = (x, y, z, 0), packed[2 I + 1] = (du, 0).
 void launch_node_update(const otm_state& st, const otm_params& p, double dt, bool zero_mf,
-                        double4* packed, hipStream_t s);
+                        double4* packed, otm_diag* diag, hipStream_t s);
 void launch_pack_nodes(const otm_state& st, double4* packed, hipStream_t s);
 void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
                       const double4* packed, otm_diag* diag, hipStream_t s);
@@ -83,5 +83,11 @@ void launch_scatter_segmented(const otm_state& st, const Workspace& w, hipStream
 void launch_assemble_atomic(const otm_state& st, hipStream_t s);
 
 void launch_diag_reset(otm_diag* d, hipStream_t s);
+
+// Adjoint of one step.
+size_t adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp);
+void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_params& p,
+                         double dt, const double* mass, otm_state_bar& b1, otm_state_bar& b0,
+                         double* theta_bar, void* ws, otm_diag* diag, hipStream_t s);
 
 }  // namespace otm

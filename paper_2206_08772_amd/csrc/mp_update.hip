@@ -13,6 +13,7 @@
 // shape functions fetch a node with one or two loads instead of six.
 // Tensors near the identity are carried as deviations (F - 1, b^e - 1, dF - 1)
 // so that the float32 form of the mixed-precision mode keeps its accuracy.
+#include "constitutive.h"
 #include "launch.h"
 #include "otm_common.h"
 
@@ -26,7 +27,8 @@ __global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restri
                                                      int wall, double wx0, double wx1,
                                                      double wx2, double wn0, double wn1,
                                                      double wn2, int zero_mf,
-                                                     double4* __restrict__ packed) {
+                                                     double4* __restrict__ packed,
+                                                     int64_t n_mp, otm_diag* diag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double mi = m[i];
@@ -34,7 +36,8 @@ __global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restri
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     xo[c] = x[c * n + i];
-    u[c] = du[c * n + i] + dt2 * f[c * n + i] / mi;
+    // a node outside every support (no mass, no force) keeps its increment
+    u[c] = du[c * n + i] + (mi > 0.0 ? dt2 * f[c * n + i] / mi : 0.0);
     xs[c] = xo[c] + u[c];
   }
   if (wall) {
@@ -50,6 +53,8 @@ __global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restri
     x[c * n + i] = xs[c];
     du[c * n + i] = u[c];
   }
+  if (!(isfinite(xs[0]) && isfinite(xs[1]) && isfinite(xs[2])))
+    diag_fail(diag, OTM_ERR_NONFINITE, (uint64_t)(n_mp + i));
   if (zero_mf) {
     m[i] = 0.0;
     f[i] = 0.0; f[n + i] = 0.0; f[2 * n + i] = 0.0;
@@ -74,85 +79,13 @@ void launch_pack_nodes(const otm_state& st, double4* packed, hipStream_t s) {
 }
 
 void launch_node_update(const otm_state& st, const otm_params& p, double dt, bool zero_mf,
-                        double4* packed, hipStream_t s) {
+                        double4* packed, otm_diag* diag, hipStream_t s) {
   const int64_t n = st.n_nodes;
   if (n <= 0) return;
   k_node_update<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
       n, st.x, st.du, st.m, st.f, dt * dt, p.wall_enabled, p.wall_x[0], p.wall_x[1],
-      p.wall_x[2], p.wall_n[0], p.wall_n[1], p.wall_n[2], zero_mf ? 1 : 0, packed);
-}
-
-// ----------------------------------------------------------- scalar math
-OTM_DEV double m_log1p(double v) { return log1p(v); }
-OTM_DEV float m_log1p(float v) { return log1pf(v); }
-OTM_DEV double m_expm1(double v) { return expm1(v); }
-OTM_DEV float m_expm1(float v) { return expm1f(v); }
-OTM_DEV double m_log(double v) { return log(v); }
-OTM_DEV float m_log(float v) { return logf(v); }
-OTM_DEV double m_pow(double a, double b) { return pow(a, b); }
-OTM_DEV float m_pow(float a, float b) { return powf(a, b); }
-OTM_DEV double m_sqrt(double v) { return sqrt(v); }
-OTM_DEV float m_sqrt(float v) { return sqrtf(v); }
-
-// Material constants in the working precision.
-template <typename R>
-struct Mat {
-  int model;
-  R K, mu, lamL;
-  R A, B, n, C, m, rate0dt, Tr, Tm, rhoCp, chi, Y0, H;
-  R tol;
-  int max_iter;
-};
-
-template <typename R>
-OTM_DEV void flow_stress(const Mat<R>& M, R eb, R x, R Ts, R& sy, R& dsy) {
-  if (M.model == OTM_J2_LINEAR) {
-    sy = M.Y0 + M.H * (eb + x);
-    dsy = M.H;
-    return;
-  }
-  const R e = eb + x;
-  R hard = M.A, dhard = R(INFINITY);
-  if (e > R(0)) {
-    const R en = m_pow(e, M.n);
-    hard = M.A + M.B * en;
-    dhard = M.B * M.n * en / e;
-  }
-  const R ratio = x / M.rate0dt;
-  R rate = R(1), drate = R(0);
-  if (ratio > R(1)) {
-    rate = R(1) + M.C * m_log(ratio);
-    drate = M.C / x;
-  }
-  const R therm = Ts > R(0) ? R(1) - m_pow(Ts, M.m) : R(1);
-  sy = hard * rate * therm;
-  dsy = (dhard * rate + hard * drate) * therm;
-}
-
-// Root of q - 3 mu x - sigma_Y(eb + x, x/dt, T*) on (0, (q - sigma_Y0)/(3 mu)]:
-// Newton from the right end, bracket kept on the sign, bisection when the
-// Newton iterate leaves the bracket.  Stops when the residual is at the
-// rounding level (|g| <= tol q; the only test that can end the iteration for
-// MPs that barely yield) or the step or bracket is below tol of the iterate.
-template <typename R>
-OTM_DEV R solve_return(const Mat<R>& M, R q, R eb, R Ts, R sy0, bool& ok) {
-  R x = (q - sy0) / (R(3) * M.mu);
-  R lo = R(0), hi = x;
-  ok = false;
-  for (int it = 0; it < M.max_iter; ++it) {
-    R sy, dsy;
-    flow_stress(M, eb, x, Ts, sy, dsy);
-    const R g = q - R(3) * M.mu * x - sy;
-    if (fabs(g) <= M.tol * q) { ok = true; break; }
-    const R gp = -R(3) * M.mu - dsy;
-    if (g > R(0)) lo = x; else hi = x;
-    R xn = x - g / gp;
-    if (!(xn > lo && xn < hi)) xn = R(0.5) * (lo + hi);
-    const bool small = fabs(xn - x) <= M.tol * fabs(xn) || (hi - lo) <= M.tol * hi;
-    x = xn;
-    if (small) { ok = true; break; }
-  }
-  return x;
+      p.wall_x[2], p.wall_n[0], p.wall_n[1], p.wall_n[2], zero_mf ? 1 : 0, packed, st.n_mp,
+      diag);
 }
 
 // ----------------------------------------------------- material-point pass
@@ -335,27 +268,6 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     finite = finite && isfinite((double)sig.v[k]);
   }
   if (!finite) diag_fail(diag, OTM_ERR_NONFINITE, (uint64_t)p);
-}
-
-template <typename R>
-static Mat<R> make_mat(const otm_params& p, double dt) {
-  Mat<R> M;
-  const double lamL = p.E * p.nu / ((1 + p.nu) * (1 - 2 * p.nu));
-  const double mu = p.E / (2 * (1 + p.nu));
-  M.model = p.model;
-  M.K = (R)(lamL + 2.0 * mu / 3.0);
-  M.mu = (R)mu;
-  M.lamL = (R)lamL;
-  M.A = (R)p.A; M.B = (R)p.B; M.n = (R)p.n; M.C = (R)p.C; M.m = (R)p.m;
-  M.rate0dt = (R)(dt * p.eps_dot0);
-  M.Tr = (R)p.T_r; M.Tm = (R)p.T_m;
-  M.rhoCp = (R)(p.rho0 * p.Cp);
-  M.chi = (R)p.chi;
-  M.Y0 = (R)p.Y0; M.H = (R)p.H;
-  const double eps = sizeof(R) == 8 ? 2.2e-16 : 1.2e-7;
-  M.tol = (R)(p.rm_tol > 4 * eps ? p.rm_tol : 4 * eps);
-  M.max_iter = p.rm_max_iter;
-  return M;
 }
 
 void launch_mp_update(const otm_state& st, const otm_params& p, double dt,

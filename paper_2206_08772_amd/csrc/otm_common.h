@@ -15,7 +15,8 @@ namespace otm {
 constexpr int kWave = 64;
 
 // ----------------------------------------------------------------- failures
-// Flag bit k corresponds to status -(k+1).
+// Flag bit k corresponds to status -(k+1); counts and first indices are kept
+// for the MP-level failures.
 OTM_DEV void diag_fail(otm_diag* d, otm_status code, uint64_t index) {
   if (d == nullptr) return;
   const int k = -code - 1;

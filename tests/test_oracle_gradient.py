@@ -1,0 +1,51 @@
+"""Pin of the oracle's complex-step gradient: central finite differences of
+the real oracle on the same frozen lists (relative step 1e-6; agreement to
+1e-4, the accuracy of the differences: measured 1e-5 for B)."""
+import numpy as np
+import pytest
+
+import otm_workloads as W
+from oracle import gradient as OG
+
+
+@pytest.fixture(scope="module")
+def setup():
+    w = W.taylor_rod(h=0.8e-3, seed=5, radius=2.4e-3, length=6.4e-3, steps=8, name="tiny_rod")
+    p = W.params_from_workload(w)
+    steps = 8
+    lists, st = OG.nominal_lists(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, steps)
+    rng = np.random.default_rng(0)
+    target = st.x + 1e-6 * rng.standard_normal(st.x.shape)
+    return w, p, steps, lists, target, st
+
+
+def test_complex_rollout_primal_matches_real(setup):
+    w, p, steps, lists, target, st = setup
+    stc = OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, steps, lists,
+                     complex_step=True)
+    assert st.epsbar.max() > 0                      # plastic flow in the run
+    u = st.x - w.x_nodes
+    assert np.abs(stc.x.real - st.x).max() < 1e-12 * np.abs(u).max()
+    assert np.abs(stc.x.imag).max() == 0.0
+
+
+def test_complex_step_matches_central_differences(setup):
+    w, p, steps, lists, target, st = setup
+    g = OG.complex_step_gradient(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, steps,
+                                 lists, target, params=("A", "B", "n"))
+    for name in ("A", "B", "n"):
+        e = 1e-6 * abs(p[name])
+        lp = OG.loss(OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes,
+                                dict(p, **{name: p[name] + e}), steps, lists), target)
+        lm = OG.loss(OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes,
+                                dict(p, **{name: p[name] - e}), steps, lists), target)
+        fd = (lp - lm) / (2 * e)
+        assert abs(g[name] - fd) <= 1e-4 * abs(fd), (name, g[name], fd)
+    s = np.abs(w.v0_nodes).max()
+    e = 1e-6 * s
+    lp = OG.loss(OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes * (1 + e / s), p,
+                            steps, lists), target)
+    lm = OG.loss(OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes * (1 - e / s), p,
+                            steps, lists), target)
+    fd = (lp - lm) / (2 * e)
+    assert abs(g["speed"] - fd) <= 1e-4 * abs(fd), (g["speed"], fd)
