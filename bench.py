@@ -186,6 +186,42 @@ def roofline_entry(nbytes, ms):
                 frac=round(gbs / HBM_PEAK_GBS, 4))
 
 
+# ------------------------------------------------------------ adjoint ratio
+def adjoint_ratio(every=20):
+    """Gradient of a rollout loss on the adjoint-rod workload (268k MPs, 200
+    float64 steps): wall time of the backward sweep (segment replay from
+    checkpoints every ``every`` steps + otm_step_adjoint) over the wall time
+    of the plain forward rollout of the same steps."""
+    import torch
+    import otm_workloads as W
+    from paper_2206_08772_amd.adjoint import rollout_backward, rollout_forward
+    from paper_2206_08772_amd.sim import Sim
+    w = W.config_by_name("adjoint_rod")
+    p = W.params_from_workload(w)
+    steps = w.steps
+    sim = Sim(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p)
+    sim.init()
+    sim.run(3)                          # warm-up (kernels loaded, caches)
+    sim.init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    target = sim.x.clone() * (1.0 + 1e-6)
+    sim.init()
+    ckpt = rollout_forward(sim, steps, every)
+    xbar = sim.x - target
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    theta_bar, _ = rollout_backward(sim, ckpt, steps, every, xbar)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    return dict(ratio=round(t_bwd / t_fwd, 3), forward_s=round(t_fwd, 4),
+                backward_s=round(t_bwd, 4), workload=f"{w.name}: {w.n_mp} MPs, {steps} steps, "
+                f"checkpoint every {every}", theta_bar_finite=bool(torch.isfinite(theta_bar).all()))
+
+
 # ------------------------------------------------------------ CPU baseline
 def cpu_baseline(seconds_budget=30.0):
     """The oracle, as it is, on a bounded slab of the same rod (same h,
@@ -223,6 +259,7 @@ def main():
     ap.add_argument("--variants", default="mixed,segmented",
                     help="extra timed variants: mixed, segmented (comma separated, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -290,6 +327,10 @@ def main():
         "variants": variants,
         "adjoint_forward_ratio": None,
     }
+    if not args.no_adjoint:
+        adj = adjoint_ratio()
+        line["adjoint_forward_ratio"] = adj["ratio"]
+        line["adjoint"] = adj
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
