@@ -260,6 +260,9 @@ def main():
                     help="extra timed variants: mixed, segmented (comma separated, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (a reference kernel "
+                         "of known traffic for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -270,6 +273,13 @@ def main():
     import otm_workloads as W
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    if args.calibration_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w = W.config_by_name(args.workload)
 
     main_run = run_variant(w, "fp64", "atomic", args.steps, args.warmup)

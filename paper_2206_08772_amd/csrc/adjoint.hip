@@ -136,16 +136,16 @@ OTM_DEV FlowPartials flow_partials(const Mat<double>& M, double eb, double x, do
   const double e = eb + x;
   double en = 0.0, hard = M.A, dhard = 0.0, lne = 0.0;
   if (e > 0.0) {
-    en = pow(e, M.n);
+    lne = log(e);
+    en = exp(M.n * lne);  // e^n, as in the forward flow law
     hard = M.A + M.B * en;
     dhard = M.B * M.n * en / e;
-    lne = log(e);
   }
   const double ratio = x / M.rate0dt;
   const double rate = ratio > 1.0 ? 1.0 + M.C * log(ratio) : 1.0;
   double therm = 1.0, dtherm = 0.0;
   if (Ts > 0.0) {
-    const double tm = pow(Ts, M.m);
+    const double tm = m_pow(Ts, M.m);
     therm = 1.0 - tm;
     dtherm = -M.m * tm / Ts;
   }
@@ -367,183 +367,225 @@ struct AdjMpArgs {
   otm_diag* diag;
 };
 
-// Adjoint of the return map at one MP.  dF, F_n, b^e_n - 1, epsbar_n, T_n:
-// forward inputs; *_b1: adjoints of its outputs.  Adds to dFb and returns the
-// adjoints of the inputs.
-OTM_DEV void return_map_adjoint(const Mat<double>& M, const double dF[3][3],
-                                const double Fn[3][3], const double bd[6], double ebn,
-                                double Tn, const double sigb[6], const double bedb1[6],
-                                double epsb1, double Tb1, const double Fb1[3][3],
-                                double dFb[3][3], double Fnb[3][3], double bedb[6],
-                                double& ebnb, double& Tnb, double thb[3], bool& ok) {
-  // ---- forward recomputation (the same arithmetic as the MP pass)
-  M3<double> h;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) h.a[i][j] = dF[i][j] - (i == j ? 1.0 : 0.0);
-  S3<double> bds;
-  for (int c = 0; c < 6; ++c) bds.v[c] = bd[c];
-  const M3<double> B = full(bds);
-  M3<double> HB;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      HB.a[i][j] = B.a[i][j] + h.a[i][0] * B.a[0][j] + h.a[i][1] * B.a[1][j] + h.a[i][2] * B.a[2][j];
-  S3<double> dtr;
-  for (int c = 0; c < 6; ++c) {
-    const int i = kVi[c], j = kVj[c];
-    const double hbh = HB.a[i][j] + HB.a[i][0] * h.a[j][0] + HB.a[i][1] * h.a[j][1] + HB.a[i][2] * h.a[j][2];
-    dtr.v[c] = h.a[i][j] + h.a[j][i] +
-               (h.a[i][0] * h.a[j][0] + h.a[i][1] * h.a[j][1] + h.a[i][2] * h.a[j][2]) + hbh;
+// Adjoint of the MP update at MP p after the gather: dF = 1 + H of the step.
+// Writes the adjoints of F_n, b^e_n, epsbar_n, T_n and v_n, adds the
+// parameter-gradient terms to th and returns the adjoint of dF in dFb.
+//
+// The work runs in stages (forward recomputation; sigma and b^e'; scalar
+// chain; the eigen-basis adjoint back to dF and b^e_n; F' = dF F_n), each
+// loading its inputs where it starts and storing its outputs where they are
+// final, with scheduling barriers between them, so that the live set stays
+// within the 256 architectural VGPRs.  Spilling to AGPRs here is not safe:
+// the compiler has been seen to place such spill copies ahead of the exec
+// restore at the end of a divergent branch, leaving stale values in the lanes
+// that skipped the branch.
+OTM_DEV void mp_adjoint(const AdjMpArgs& a, int64_t p, const double dF[3][3], double dFb[3][3],
+                        double thb[3], bool& ok) {
+  const Mat<double>& M = a.M;
+  const int64_t n = a.n_mp;
+  // ---- stage 1: forward recomputation (the same arithmetic as the MP pass)
+  double d[3], V[3][3], e[3], dev[3], tr, q, Ts = 0.0, tunc = 0.0, deps = 0.0, c = 0.0;
+  bool plastic;
+  const double ebn = a.epsbar[p], Tn = a.T[p];
+  {
+    M3<double> h;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) h.a[i][j] = dF[i][j] - (i == j ? 1.0 : 0.0);
+    S3<double> bds;
+    for (int k = 0; k < 6; ++k) bds.v[k] = a.bed[k * n + p];
+    const M3<double> B = full(bds);
+    M3<double> HB;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        HB.a[i][j] = B.a[i][j] + h.a[i][0] * B.a[0][j] + h.a[i][1] * B.a[1][j] + h.a[i][2] * B.a[2][j];
+    S3<double> dtr;
+    for (int k = 0; k < 6; ++k) {
+      const int i = kVi[k], j = kVj[k];
+      const double hbh = HB.a[i][j] + HB.a[i][0] * h.a[j][0] + HB.a[i][1] * h.a[j][1] + HB.a[i][2] * h.a[j][2];
+      dtr.v[k] = h.a[i][j] + h.a[j][i] +
+                 (h.a[i][0] * h.a[j][0] + h.a[i][1] * h.a[j][1] + h.a[i][2] * h.a[j][2]) + hbh;
+    }
+    jacobi_eig(dtr, d, V);
   }
-  double d[3], V[3][3];
-  jacobi_eig(dtr, d, V);
-  double e[3];
-  for (int a = 0; a < 3; ++a) e[a] = 0.5 * log1p(d[a]);
-  const double tr = e[0] + e[1] + e[2];
-  double dev[3];
-  for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / 3.0;
-  const double s2 = dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2];
-  const double q = 2.0 * M.mu * sqrt(1.5 * s2);
-  double Ts = 0.0, tunc = 0.0;
+  for (int k = 0; k < 3; ++k) e[k] = 0.5 * log1p(d[k]);
+  tr = e[0] + e[1] + e[2];
+  for (int k = 0; k < 3; ++k) dev[k] = e[k] - tr / 3.0;
+  q = 2.0 * M.mu * sqrt(1.5 * (dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]));
   if (M.model == OTM_J2_JC) {
     tunc = (Tn - M.Tr) / (M.Tm - M.Tr);
     Ts = tunc < 0.0 ? 0.0 : (tunc > 1.0 ? 1.0 : tunc);
   }
-  double sy0, dsy0;
-  flow_stress(M, ebn, 0.0, Ts, sy0, dsy0);
-  const bool plastic = q > sy0;
-  double deps = 0.0, c = 0.0;
-  ok = true;
-  if (plastic) {
-    deps = solve_return(M, q, ebn, Ts, sy0, ok);
-    c = 3.0 * M.mu * deps / q;
-  }
-  double eps[3], tau[3], bm1[3];
-  for (int a = 0; a < 3; ++a) {
-    eps[a] = e[a] - c * dev[a];
-    tau[a] = M.K * tr + 2.0 * M.mu * (1.0 - c) * dev[a];
-    bm1[a] = expm1(2.0 * eps[a]);
-  }
-  double Fp[3][3];
-  mat3_mul(dF, Fn, Fp);
-  const double Jp = det3m(Fp);
-
-  // ---- adjoint: sigma = tau / J', b^e' = 1 + V diag(bm1) V^T
-  double Sb[3][3], Bb[3][3];
-  voigt_bar_to_full(sigb, Sb);
-  voigt_bar_to_full(bedb1, Bb);
-  double Jpb = 0.0;
-  double taub[3][3];
   {
-    // sigma_ij = sum_a V_ia tau_a V_ja / J'
-    double sig_dot = 0.0;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        const double sij = (V[i][0] * tau[0] * V[j][0] + V[i][1] * tau[1] * V[j][1] +
-                            V[i][2] * tau[2] * V[j][2]) / Jp;
-        sig_dot += Sb[i][j] * sij;
-        taub[i][j] = Sb[i][j] / Jp;
-      }
-    Jpb = -sig_dot / Jp;
-  }
-  // eigen-basis components of the output adjoints
-  double Tt[3][3], Bt[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
-      double st = 0.0, sb = 0.0;
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          st += V[i][a] * taub[i][j] * V[j][b];
-          sb += V[i][a] * Bb[i][j] * V[j][b];
-        }
-      Tt[a][b] = st;
-      Bt[a][b] = sb;
+    double sy0, dsy0;
+    flow_stress(M, ebn, 0.0, Ts, sy0, dsy0);
+    plastic = q > sy0;
+    ok = true;
+    if (plastic) {
+      deps = solve_return(M, q, ebn, Ts, sy0, ok);
+      c = 3.0 * M.mu * deps / q;
     }
-  // scalar chain through the principal values
-  double epsb[3], devb[3];
-  const double rhoCp = M.rhoCp;
-  double cb = 0.0, depsb = epsb1, qb = 0.0, trb = 0.0;
-  for (int a = 0; a < 3; ++a) {
-    epsb[a] = Bt[a][a] * 2.0 * (bm1[a] + 1.0);
-    trb += M.K * Tt[a][a];
-    devb[a] = 2.0 * M.mu * (1.0 - c) * Tt[a][a] - c * epsb[a];
-    cb += -2.0 * M.mu * dev[a] * Tt[a][a] - dev[a] * epsb[a];
   }
-  ebnb = epsb1;
-  Tnb = Tb1;
-  if (M.model == OTM_J2_JC) {
-    // T' = T_n + chi (1 - c) q deps / (rho0 Cp)
-    cb += -M.chi * q * deps / rhoCp * Tb1;
-    depsb += M.chi * (1.0 - c) * q / rhoCp * Tb1;
-    qb += M.chi * (1.0 - c) * deps / rhoCp * Tb1;
+  double tau[3], bm1[3];
+  for (int k = 0; k < 3; ++k) {
+    tau[k] = M.K * tr + 2.0 * M.mu * (1.0 - c) * dev[k];
+    bm1[k] = expm1(2.0 * (e[k] - c * dev[k]));
   }
-  thb[0] = thb[1] = thb[2] = 0.0;
+  // derivative of the return equation in x and the flow-law partials at the
+  // solution (plastic MPs), and the divided differences of tau_a and bm1_a
+  // for the off-diagonal eigen-basis terms: all scalars, computed here while
+  // few values are live
+  double gx = 1.0;
+  FlowPartials P{0.0, 0.0, {0.0, 0.0, 0.0}};
   if (plastic) {
-    // c = 3 mu deps / q
-    depsb += cb * 3.0 * M.mu / q;
-    qb -= cb * c / q;
-    // deps(q, epsbar_n, T*, theta) from q - 3 mu x - sigma_Y(ebn + x, x/dt, T*) = 0
     double sy, dsy;
     flow_stress(M, ebn, deps, Ts, sy, dsy);
-    const double gx = -3.0 * M.mu - dsy;
-    const FlowPartials P = flow_partials(M, ebn, deps, Ts);
-    qb += depsb * (-1.0 / gx);
-    ebnb += depsb * P.s_eb / gx;
-    if (M.model == OTM_J2_JC && tunc > 0.0 && tunc < 1.0)
-      Tnb += depsb * P.s_T / gx / (M.Tm - M.Tr);
-    for (int k = 0; k < 3; ++k) thb[k] = depsb * P.s_th[k] / gx;
+    gx = -3.0 * M.mu - dsy;
+    P = flow_partials(M, ebn, deps, Ts);
   }
-  // q = 2 mu sqrt(3/2 sum dev^2)
-  if (q > 0.0)
-    for (int a = 0; a < 3; ++a) devb[a] += qb * 6.0 * M.mu * M.mu * dev[a] / q;
-  const double devb_sum = devb[0] + devb[1] + devb[2];
-  double db[3];
-  for (int a = 0; a < 3; ++a) {
-    const double eb = epsb[a] + trb + devb[a] - devb_sum / 3.0;
-    db[a] = eb * 0.5 / (1.0 + d[a]);
+  double rt[3], rbm[3];  // pairs (0,1), (1,2), (0,2)
+  for (int k = 3; k < 6; ++k) {
+    const int aa = kVi[k], bb = kVj[k];
+    const double u = 2.0 * (e[aa] - e[bb]);
+    rt[k - 3] = M.mu * (1.0 - c) * ratio_u_expm1(u) / (1.0 + d[bb]);
+    rbm[k - 3] = (bm1[bb] + 1.0) * ratio_expm1(1.0 - c, u) / (1.0 + d[bb]);
   }
-  // full adjoint of b_tr - 1 in the eigen-basis: diagonal from the scalar
-  // chain, off-diagonal from divided differences of tau_a and bm1_a
-  double Dt[3][3];
-  for (int a = 0; a < 3; ++a) Dt[a][a] = db[a];
-  for (int a = 0; a < 3; ++a)
-    for (int b = a + 1; b < 3; ++b) {
-      const double u = 2.0 * (e[a] - e[b]);
-      const double rt = M.mu * (1.0 - c) * ratio_u_expm1(u) / (1.0 + d[b]);
-      const double rbm = (bm1[b] + 1.0) * ratio_expm1(1.0 - c, u) / (1.0 + d[b]);
-      const double v = Tt[a][b] * rt + Bt[a][b] * rbm;
-      Dt[a][b] = Dt[b][a] = v;
+  double Jp;
+  {
+    double Fn[3][3], Fp[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Fn[i][j] = a.Fd[(3 * i + j) * n + p] + (i == j ? 1.0 : 0.0);
+    mat3_mul(dF, Fn, Fp);
+    Jp = det3m(Fp);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // ---- stage 2: sigma = V diag(tau) V^T / J', b^e' = 1 + V diag(bm1) V^T;
+  // output adjoints in the eigen-basis (symmetric: xx yy zz xy yz xz)
+  double Tt[6], Bt[6], Jpb;
+  {
+    double vb[6], Sb[3][3], Bb[3][3];
+    for (int k = 0; k < 6; ++k) vb[k] = a.sigb1[k * n + p];
+    voigt_bar_to_full(vb, Sb);
+    for (int k = 0; k < 6; ++k) vb[k] = a.bedb1[k * n + p];
+    voigt_bar_to_full(vb, Bb);
+    // Tt = V^T (Sb / J') V and Bt = V^T Bb V; sigma : Sb = sum_a tau_a Tt_aa
+    const double iJ = 1.0 / Jp;
+    for (int bb = 0; bb < 3; ++bb) {
+      double ws[3], wb[3];
+      for (int i = 0; i < 3; ++i) {
+        ws[i] = (Sb[i][0] * V[0][bb] + Sb[i][1] * V[1][bb] + Sb[i][2] * V[2][bb]) * iJ;
+        wb[i] = Bb[i][0] * V[0][bb] + Bb[i][1] * V[1][bb] + Bb[i][2] * V[2][bb];
+      }
+      for (int aa = 0; aa <= bb; ++aa) {
+        const int k = aa == bb ? aa : (aa == 0 ? (bb == 1 ? 3 : 5) : 4);
+        Tt[k] = V[0][aa] * ws[0] + V[1][aa] * ws[1] + V[2][aa] * ws[2];
+        Bt[k] = V[0][aa] * wb[0] + V[1][aa] * wb[1] + V[2][aa] * wb[2];
+      }
     }
+    Jpb = -(tau[0] * Tt[0] + tau[1] * Tt[1] + tau[2] * Tt[2]) * iJ;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // ---- stage 3: scalar chain through the principal values
+  double Dt[6];
+  {
+    const double epsb1 = a.epsb1[p], Tb1 = a.Tb1[p];
+    double epsb[3], devb[3];
+    double cb = 0.0, depsb = epsb1, qb = 0.0, trb = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      epsb[k] = Bt[k] * 2.0 * (bm1[k] + 1.0);
+      trb += M.K * Tt[k];
+      devb[k] = 2.0 * M.mu * (1.0 - c) * Tt[k] - c * epsb[k];
+      cb += -2.0 * M.mu * dev[k] * Tt[k] - dev[k] * epsb[k];
+    }
+    double ebnb = epsb1, Tnb = Tb1;
+    if (M.model == OTM_J2_JC) {
+      // T' = T_n + chi (1 - c) q deps / (rho0 Cp)
+      cb += -M.chi * q * deps / M.rhoCp * Tb1;
+      depsb += M.chi * (1.0 - c) * q / M.rhoCp * Tb1;
+      qb += M.chi * (1.0 - c) * deps / M.rhoCp * Tb1;
+    }
+    thb[0] = thb[1] = thb[2] = 0.0;
+    if (plastic) {
+      // c = 3 mu deps / q
+      depsb += cb * 3.0 * M.mu / q;
+      qb -= cb * c / q;
+      // deps(q, epsbar_n, T*, theta) from q - 3 mu x - sigma_Y(ebn + x, x/dt, T*) = 0
+      qb += depsb * (-1.0 / gx);
+      ebnb += depsb * P.s_eb / gx;
+      if (M.model == OTM_J2_JC && tunc > 0.0 && tunc < 1.0)
+        Tnb += depsb * P.s_T / gx / (M.Tm - M.Tr);
+      for (int k = 0; k < 3; ++k) thb[k] = depsb * P.s_th[k] / gx;
+    }
+    a.epsb[p] = ebnb;
+    a.Tb[p] = Tnb;
+    // q = 2 mu sqrt(3/2 sum dev^2)
+    if (q > 0.0)
+      for (int k = 0; k < 3; ++k) devb[k] += qb * 6.0 * M.mu * M.mu * dev[k] / q;
+    const double devb_sum = devb[0] + devb[1] + devb[2];
+    // full adjoint of b_tr - 1 in the eigen-basis: diagonal from the scalar
+    // chain, off-diagonal from divided differences of tau_a and bm1_a
+    for (int k = 0; k < 3; ++k) {
+      const double eb = epsb[k] + trb + devb[k] - devb_sum / 3.0;
+      Dt[k] = eb * 0.5 / (1.0 + d[k]);
+    }
+    for (int k = 3; k < 6; ++k) Dt[k] = Tt[k] * rt[k - 3] + Bt[k] * rbm[k - 3];
+  }
+  // back to the lab frame: Db = V Dt V^T
   double Db[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      double s = 0.0;
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) s += V[i][a] * Dt[a][b] * V[j][b];
-      Db[i][j] = s;
+  {
+    double Df[3][3];
+    for (int k = 0; k < 6; ++k) Df[kVi[k]][kVj[k]] = Df[kVj[k]][kVi[k]] = Dt[k];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int aa = 0; aa < 3; ++aa)
+          for (int bb = 0; bb < 3; ++bb) s += V[i][aa] * Df[aa][bb] * V[j][bb];
+        Db[i][j] = s;
+      }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // ---- stage 4: b_tr = dF b^e_n dF^T
+  {
+    double be[3][3];
+    {
+      double bd[6];
+      for (int k = 0; k < 6; ++k) bd[k] = a.bed[k * n + p];
+      for (int k = 0; k < 6; ++k)
+        be[kVi[k]][kVj[k]] = be[kVj[k]][kVi[k]] = bd[k] + (k < 3 ? 1.0 : 0.0);
     }
-  // b_tr = dF b^e_n dF^T
-  double be[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) be[i][j] = B.a[i][j] + (i == j ? 1.0 : 0.0);
-  double DbF[3][3], DbFbe[3][3], FtDb[3][3], BeB[3][3];
-  mat3_mul(Db, dF, DbF);
-  mat3_mul(DbF, be, DbFbe);
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) dFb[i][j] += 2.0 * DbFbe[i][j];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) FtDb[i][j] = dF[0][i] * Db[0][j] + dF[1][i] * Db[1][j] + dF[2][i] * Db[2][j];
-  mat3_mul(FtDb, dF, BeB);
-  full_bar_to_voigt(BeB, bedb);
-  // J' = det F', F' = dF F_n
-  double cofp[3][3], Fpb[3][3];
-  cofactor3(Fp, cofp);
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) Fpb[i][j] = Fb1[i][j] + Jpb * cofp[i][j];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      dFb[i][j] += Fpb[i][0] * Fn[j][0] + Fpb[i][1] * Fn[j][1] + Fpb[i][2] * Fn[j][2];
-      Fnb[i][j] = dF[0][i] * Fpb[0][j] + dF[1][i] * Fpb[1][j] + dF[2][i] * Fpb[2][j];
-    }
+    double DbF[3][3], DbFbe[3][3];
+    mat3_mul(Db, dF, DbF);
+    mat3_mul(DbF, be, DbFbe);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) dFb[i][j] = 2.0 * DbFbe[i][j];
+  }
+  {
+    double FtDb[3][3], BeB[3][3], bedb[6];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) FtDb[i][j] = dF[0][i] * Db[0][j] + dF[1][i] * Db[1][j] + dF[2][i] * Db[2][j];
+    mat3_mul(FtDb, dF, BeB);
+    full_bar_to_voigt(BeB, bedb);
+    for (int k = 0; k < 6; ++k) a.bedb[k * n + p] = bedb[k];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // ---- stage 5: J' = det F', F' = dF F_n
+  {
+    double Fn[3][3], Fp[3][3], cofp[3][3], Fpb[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Fn[i][j] = a.Fd[(3 * i + j) * n + p] + (i == j ? 1.0 : 0.0);
+    mat3_mul(dF, Fn, Fp);
+    cofactor3(Fp, cofp);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Fpb[i][j] = a.Fdb1[(3 * i + j) * n + p] + Jpb * cofp[i][j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        dFb[i][j] += Fpb[i][0] * Fn[j][0] + Fpb[i][1] * Fn[j][1] + Fpb[i][2] * Fn[j][2];
+        a.Fdb[(3 * i + j) * n + p] = dF[0][i] * Fpb[0][j] + dF[1][i] * Fpb[1][j] + dF[2][i] * Fpb[2][j];
+      }
+  }
 }
 
 __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
@@ -579,24 +621,12 @@ __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
   {
     const int64_t p = base + tid;
     if (p < a.n_mp) {
-      const int64_t n = a.n_mp;
-      double dF[3][3], Fn[3][3], Fb1[3][3];
+      double dF[3][3];
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          dF[i][j] = sums[3 * i + j][tid] + (i == j ? 1.0 : 0.0);
-          Fn[i][j] = a.Fd[(3 * i + j) * n + p] + (i == j ? 1.0 : 0.0);
-          Fb1[i][j] = a.Fdb1[(3 * i + j) * n + p];
-        }
-      double bd[6], sigb[6], bedb1[6];
-      for (int c = 0; c < 6; ++c) {
-        bd[c] = a.bed[c * n + p];
-        sigb[c] = a.sigb1[c * n + p];
-        bedb1[c] = a.bedb1[c * n + p];
-      }
-      double dFb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fnb[3][3], bedb[6], ebnb, Tnb;
+        for (int j = 0; j < 3; ++j) dF[i][j] = sums[3 * i + j][tid] + (i == j ? 1.0 : 0.0);
+      double dFb[3][3];
       bool ok;
-      return_map_adjoint(a.M, dF, Fn, bd, a.epsbar[p], a.T[p], sigb, bedb1, a.epsb1[p], a.Tb1[p],
-                         Fb1, dFb, Fnb, bedb, ebnb, Tnb, th, ok);
+      mp_adjoint(a, p, dF, dFb, th, ok);
       if (!ok) diag_fail(a.diag, OTM_ERR_RM_NOCONV, (uint64_t)p);
       // v' = det(dF) v
       double cof[3][3];
@@ -606,11 +636,6 @@ __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) dFb[i][j] += vb1 * a.vol[p] * cof[i][j];
       a.volb[p] = vb1 * detdF;
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) a.Fdb[(3 * i + j) * n + p] = Fnb[i][j];
-      for (int c = 0; c < 6; ++c) a.bedb[c * n + p] = bedb[c];
-      a.epsb[p] = ebnb;
-      a.Tb[p] = Tnb;
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) sums[3 * i + j][tid] = dFb[i][j];
     }

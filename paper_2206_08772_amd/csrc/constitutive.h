@@ -15,7 +15,12 @@ OTM_DEV double m_expm1(double v) { return expm1(v); }
 OTM_DEV float m_expm1(float v) { return expm1f(v); }
 OTM_DEV double m_log(double v) { return log(v); }
 OTM_DEV float m_log(float v) { return logf(v); }
-OTM_DEV double m_pow(double a, double b) { return pow(a, b); }
+// a^b for a > 0 (every caller guards it) as exp(b log a): the relative error
+// is about (2 + |b log a|) ulp, far below the float64 tolerance for the
+// strains and homologous temperatures of the flow law, and it needs far fewer
+// registers than the library pow, whose extended-precision log would set the
+// register peak of the material-point pass.
+OTM_DEV double m_pow(double a, double b) { return exp(b * log(a)); }
 OTM_DEV float m_pow(float a, float b) { return powf(a, b); }
 OTM_DEV double m_sqrt(double v) { return sqrt(v); }
 OTM_DEV float m_sqrt(float v) { return sqrtf(v); }
@@ -30,8 +35,16 @@ struct Mat {
   int max_iter;
 };
 
+// Thermal softening factor 1 - T*^m of the Johnson-Cook law (1 below T_r).
 template <typename R>
-OTM_DEV void flow_stress(const Mat<R>& M, R eb, R x, R Ts, R& sy, R& dsy) {
+OTM_DEV R thermal_factor(const Mat<R>& M, R Ts) {
+  return Ts > R(0) ? R(1) - m_pow(Ts, M.m) : R(1);
+}
+
+// sigma_Y(eb + x, x / dt, T*) and its derivative in x, with the thermal
+// factor of T* given (it does not change during a return-map solve).
+template <typename R>
+OTM_DEV void flow_stress_t(const Mat<R>& M, R eb, R x, R therm, R& sy, R& dsy) {
   if (M.model == OTM_J2_LINEAR) {
     sy = M.Y0 + M.H * (eb + x);
     dsy = M.H;
@@ -50,9 +63,13 @@ OTM_DEV void flow_stress(const Mat<R>& M, R eb, R x, R Ts, R& sy, R& dsy) {
     rate = R(1) + M.C * m_log(ratio);
     drate = M.C / x;
   }
-  const R therm = Ts > R(0) ? R(1) - m_pow(Ts, M.m) : R(1);
   sy = hard * rate * therm;
   dsy = (dhard * rate + hard * drate) * therm;
+}
+
+template <typename R>
+OTM_DEV void flow_stress(const Mat<R>& M, R eb, R x, R Ts, R& sy, R& dsy) {
+  flow_stress_t(M, eb, x, thermal_factor(M, Ts), sy, dsy);
 }
 
 // Root of q - 3 mu x - sigma_Y(eb + x, x/dt, T*) on (0, (q - sigma_Y0)/(3 mu)]:
@@ -62,12 +79,13 @@ OTM_DEV void flow_stress(const Mat<R>& M, R eb, R x, R Ts, R& sy, R& dsy) {
 // MPs that barely yield) or the step or bracket is below tol of the iterate.
 template <typename R>
 OTM_DEV R solve_return(const Mat<R>& M, R q, R eb, R Ts, R sy0, bool& ok) {
+  const R therm = thermal_factor(M, Ts);
   R x = (q - sy0) / (R(3) * M.mu);
   R lo = R(0), hi = x;
   ok = false;
   for (int it = 0; it < M.max_iter; ++it) {
     R sy, dsy;
-    flow_stress(M, eb, x, Ts, sy, dsy);
+    flow_stress_t(M, eb, x, therm, sy, dsy);
     const R g = q - R(3) * M.mu * x - sy;
     if (fabs(g) <= M.tol * q) { ok = true; break; }
     const R gp = -R(3) * M.mu - dsy;

@@ -1,12 +1,15 @@
 // Local max-ent shape functions (Sec. 2.3) by a per-material-point damped
 // Newton solve for the Lagrange multiplier, in float64.
 //
-// A group of G lanes works on one MP; each lane keeps up to PPL of the MP's
-// pairs in registers (offset d = x_p - x_I and the prior -beta |d|^2), so one
-// Newton evaluation costs one exp per pair and 10 group reductions
-// (Z, r, S = sum e d d^T) by butterfly shuffles.  The 3x3 solve is repeated
-// in every lane of the group, so the group never diverges.  MPs with longer
-// supports than G*PPL take the same iteration with pairs re-read from memory.
+// A group of G = 4 lanes works on one MP; each lane keeps up to PPL = 10 of
+// the MP's pairs in registers (offset d = x_p - x_I and the prior
+// -beta |d|^2), so one Newton evaluation costs one exp per pair and 10 group
+// reductions (Z, r, S = sum e d d^T) of two DPP stages each.  The 3x3 solve
+// is repeated in every lane of the group, so the group never diverges.  Few
+// lanes per MP keep the per-MP work (reductions, solve, line search) from
+// being repeated across many lanes, which is what bounds this kernel: it is
+// float64 ALU work, not memory traffic.  MPs with more than 40 pairs take the
+// same iteration with pairs re-read from memory.
 //
 // Newton reading (the paper gives none): start from the previous multiplier;
 // step -J^{-1} r with J = sum N d d^T - r r^T; Armijo backtracking on log Z
@@ -153,7 +156,7 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
   // ek holds the exponentials of the last evaluation; every line search
   // ends with an accepted trial, so they always belong to the current lambda
   double ek[CACHED ? PPL : 1];
-  Eval ev, et_ev;
+  Eval ev;
   lme_eval<G, PPL, CACHED>(pr, lane, K, off, px, py, pz, ns, idx, beta, lam, ev, ek);
   bool converged = false;
   for (int it = 0;; ++it) {
@@ -167,19 +170,20 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
     double delta[3];
     sym_mul_vec(Mi, ev.r, delta);
     delta[0] = -delta[0]; delta[1] = -delta[1]; delta[2] = -delta[2];
+    // only log Z and the slope of the base point are needed from here on, so
+    // the trials are evaluated into ev (the accepted one stays there)
     const double slope = ev.r[0] * delta[0] + ev.r[1] * delta[1] + ev.r[2] * delta[2];
-    double t = 1.0, lt[3];
+    const double lz0 = ev.logZ;
+    const double l0[3] = {lam[0], lam[1], lam[2]};
+    double t = 1.0;
     for (int h = 0; h < 31; ++h) {
-      lt[0] = lam[0] + t * delta[0];
-      lt[1] = lam[1] + t * delta[1];
-      lt[2] = lam[2] + t * delta[2];
-      lme_eval<G, PPL, CACHED>(pr, lane, K, off, px, py, pz, ns, idx, beta, lt, et_ev, ek);
-      if (et_ev.logZ <= ev.logZ + 1e-4 * t * slope + 1e-12 * (1.0 + fabs(ev.logZ)) || h == 30)
-        break;
+      lam[0] = l0[0] + t * delta[0];
+      lam[1] = l0[1] + t * delta[1];
+      lam[2] = l0[2] + t * delta[2];
+      lme_eval<G, PPL, CACHED>(pr, lane, K, off, px, py, pz, ns, idx, beta, lam, ev, ek);
+      if (ev.logZ <= lz0 + 1e-4 * t * slope + 1e-12 * (1.0 + fabs(lz0)) || h == 30) break;
       t *= 0.5;
     }
-    lam[0] = lt[0]; lam[1] = lt[1]; lam[2] = lt[2];
-    ev = et_ev;
   }
   if (lane == 0) {
     lam_io[p] = lam[0]; lam_io[n_mp + p] = lam[1]; lam_io[2 * n_mp + p] = lam[2];
@@ -242,7 +246,7 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
                 int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s) {
   if (n_mp <= 0) return;
   const NodeSrc ns{x_nodes, packed, n_nodes};
-  constexpr int G = 16, PPL = 3;
+  constexpr int G = 4, PPL = 10;
   const unsigned nb = (unsigned)((n_mp + (256 / G) - 1) / (256 / G));
   if (precision == OTM_FP64)
     k_lme<G, PPL, double><<<nb, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx,

@@ -90,7 +90,8 @@ void launch_node_update(const otm_state& st, const otm_params& p, double dt, boo
 
 // ----------------------------------------------------- material-point pass
 constexpr int kMpBlock = 256;
-constexpr int kGather = 8;  // lanes per MP in the gather phase
+constexpr int kGather = 8;             // lanes per MP in the gather phase
+constexpr int kSlots = 32 / kGather;   // pairs per lane loaded branch-free
 
 template <typename R>
 __global__ __launch_bounds__(kMpBlock) void k_mp_update(
@@ -100,21 +101,27 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     double* __restrict__ xp, double* __restrict__ vol, R* __restrict__ Fd, R* __restrict__ bed,
     double* __restrict__ epsbar, double* __restrict__ T, R* __restrict__ sigma, Mat<R> M,
     otm_diag* diag) {
-  __shared__ double sums[12][kMpBlock];
+  // phase 1: the 12 gathered sums of each MP; phase 2: the MP's eigenvectors,
+  // logarithmic strains and J parked over the return-map solve (each lane
+  // only touches its own column)
+  __shared__ double sums[13][kMpBlock];
+  __shared__ int64_t row[kMpBlock + 1];
   const int64_t base = (int64_t)xcd_block() * kMpBlock;
   const int tid = threadIdx.x;
   const bool lists_ok = offsets[n_mp] <= cap;
   const bool have_nodes = n_nodes > 0 && cap > 0;
+  // the block's row offsets, read once (rows past the end are empty)
+  for (int i = tid; i <= kMpBlock; i += kMpBlock) row[i] = offsets[min(base + i, n_mp)];
+  __syncthreads();
 
-  // phase 1: gather with 8 lanes per MP
+  // phase 1: gather with kGather lanes per MP
   {
     const int lane = tid % kGather;
-    for (int r = 0; r < kMpBlock / (kMpBlock / kGather); ++r) {
+    for (int r = 0; r < kGather; ++r) {
       const int local = r * (kMpBlock / kGather) + tid / kGather;
-      const int64_t p = base + local;
       double a[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      if (p < n_mp && lists_ok && have_nodes) {
-        const int64_t o0 = offsets[p], o1 = offsets[p + 1];
+      if (lists_ok && have_nodes) {
+        const int64_t o0 = row[local], o1 = row[local + 1];
         // branch-free loads (pair 0 stands in past the row end, weight 0), so
         // the compiler can keep all of them in flight together
         auto add_pair = [&](int64_t q, bool use) {
@@ -133,11 +140,11 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
           a[9] += uv.z * g0; a[10] += uv.z * g1; a[11] += uv.z * g2;
         };
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kSlots; ++k) {
           const int64_t q = o0 + k * kGather + lane;
           add_pair(q, q < o1);
         }
-        for (int64_t q = o0 + 4 * kGather + lane; q < o1; q += kGather) add_pair(q, true);
+        for (int64_t q = o0 + kSlots * kGather + lane; q < o1; q += kGather) add_pair(q, true);
       }
 #pragma unroll
       for (int c = 0; c < 12; ++c) a[c] = group_sum<kGather>(a[c]);
@@ -158,6 +165,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
 #pragma unroll
     for (int j = 0; j < 3; ++j) H.a[i][j] = sums[3 + 3 * i + j][tid];
   const double xnew[3] = {sums[0][tid], sums[1][tid], sums[2][tid]};
+  bool finite = isfinite(xnew[0]) && isfinite(xnew[1]) && isfinite(xnew[2]);
   const double detdF = 1.0 + det_one_plus_minus_one(H);
   if (!(detdF > 0.0)) diag_fail(diag, OTM_ERR_INVERTED, (uint64_t)p);
   vol[p] = detdF * vol[p];
@@ -184,7 +192,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
 #pragma unroll
     for (int j = 0; j < 3; ++j) Fd[(3 * i + j) * n_mp + p] = fn.a[i][j];
   const R Jm1 = det_one_plus_minus_one(fn);
-  const R J = R(1) + Jm1;
+  R J = R(1) + Jm1;
 
   S3<R> sig;
   if (M.model == OTM_NEOHOOKE) {
@@ -226,7 +234,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     R e[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) e[a] = R(0.5) * m_log1p(d[a]);
-    const R tr = e[0] + e[1] + e[2];
+    R tr = e[0] + e[1] + e[2];
     R dev[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / R(3);
@@ -241,10 +249,29 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     flow_stress(M, (R)ebn, R(0), Ts, sy0, dsy0);
     R deps = R(0), c = R(0);
     if (q_tr > sy0) {
+      // the solve is the register peak of the kernel: park what it does not
+      // use in LDS and read it back afterwards
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) sums[3 * i + j][tid] = (double)V[i][j];
+        sums[9 + i][tid] = (double)e[i];
+      }
+      sums[12][tid] = (double)J;
       bool ok;
       deps = solve_return(M, q_tr, (R)ebn, Ts, sy0, ok);
       if (!ok) diag_fail(diag, OTM_ERR_RM_NOCONV, (uint64_t)p);
       c = R(3) * M.mu * deps / q_tr;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) V[i][j] = (R)sums[3 * i + j][tid];
+        e[i] = (R)sums[9 + i][tid];
+      }
+      J = (R)sums[12][tid];
+      tr = e[0] + e[1] + e[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / R(3);
     }
     R bnew[3], tau[3];
 #pragma unroll
@@ -261,7 +288,6 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     if (M.model == OTM_J2_JC)
       T[p] = Tn + (double)(M.chi * (R(1) - c) * q_tr * deps / M.rhoCp);
   }
-  bool finite = isfinite(xnew[0]) && isfinite(xnew[1]) && isfinite(xnew[2]);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     sigma[k * n_mp + p] = sig.v[k];

@@ -59,25 +59,32 @@ OTM_DEV uint32_t xcd_block() {
 }
 
 // ------------------------------------------------------------- reductions
-// Butterfly over aligned groups of G lanes.  Every lane of the group ends
-// with the same bits (a + b and b + a round identically).
-template <int G>
-OTM_DEV double group_sum(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+// All-reduce over aligned groups of G <= 16 lanes with DPP row moves (no LDS
+// round trip): row_ror:8 folds the two halves of a 16-lane row, then
+// row_half_mirror, quad_perm [2,3,0,1] and quad_perm [1,0,3,2] finish the
+// 8-lane groups.  Each stage adds a value to one that holds the same set of
+// terms, so every lane of the group ends with the same bits (a + b and b + a
+// round identically).
+template <int CTRL, typename T>
+OTM_DEV T dpp_move(T v) {
+  return __builtin_amdgcn_update_dpp(T(0), v, CTRL, 0xF, 0xF, false);
+}
+template <int G, typename T, typename Op>
+OTM_DEV T group_reduce(T v, Op op) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
+  if constexpr (G >= 16) v = op(v, dpp_move<0x128>(v));  // row_ror:8
+  if constexpr (G >= 8) v = op(v, dpp_move<0x141>(v));   // row_half_mirror
+  if constexpr (G >= 4) v = op(v, dpp_move<0x4E>(v));    // quad_perm [2,3,0,1]
+  if constexpr (G >= 2) v = op(v, dpp_move<0xB1>(v));    // quad_perm [1,0,3,2]
   return v;
 }
-template <int G>
-OTM_DEV float group_sum(float v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-  return v;
+template <int G, typename T>
+OTM_DEV T group_sum(T v) {
+  return group_reduce<G>(v, [](T a, T b) { return a + b; });
 }
 template <int G>
 OTM_DEV double group_max(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
-  return v;
+  return group_reduce<G>(v, [](double a, double b) { return fmax(a, b); });
 }
 
 // ------------------------------------------------------------- 3x3 algebra

@@ -120,3 +120,24 @@ def test_search_and_lme_argument_checks(L):
                              fake, 0, None, None) == L.OTM_ERR_ARG
     assert lib.otm_lme_shape(10, fake, 10, fake, fake, fake, 100, 4.0, 0.0, 50, fake, fake,
                              fake, 0, None, None) == L.OTM_ERR_ARG
+
+
+def test_kernel_resource_parser():
+    """The build refuses kernels that spill; the parser reads the compiler's
+    kernel-resource-usage remarks (text in the form hipcc prints)."""
+    from paper_2206_08772_amd.build import kernel_resources
+    txt = "\n".join([
+        "a.hip:1:1: remark: Function Name: k_one [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     VGPRs: 120 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     AGPRs: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     VGPRs Spill: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark: Function Name: k_two [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     VGPRs: 256 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     AGPRs: 58 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     ScratchSize [bytes/lane]: 16 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     VGPRs Spill: 4 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    r = kernel_resources(txt)
+    assert r["k_one"] == {"VGPRs": 120, "AGPRs": 0, "ScratchSize": 0, "VGPRs Spill": 0}
+    assert r["k_two"] == {"VGPRs": 256, "AGPRs": 58, "ScratchSize": 16, "VGPRs Spill": 4}
