@@ -3,7 +3,7 @@
 // F, volume and the constitutive update.
 //
 // Material-point pass, one workgroup per 256 MPs:
-//   phase 1 (gather): groups of 8 lanes walk one MP's pairs with unit stride,
+//   phase 1 (gather): groups of 16 lanes walk one MP's pairs with unit stride,
 //     accumulate x_p = sum N_I x_I and H = dF - 1 = sum du_I (x) grad N_I,
 //     reduce by shuffles and park the 12 sums in LDS;
 //   phase 2 (update): one lane per MP reads its sums back and runs the
@@ -90,7 +90,7 @@ void launch_node_update(const otm_state& st, const otm_params& p, double dt, boo
 
 // ----------------------------------------------------- material-point pass
 constexpr int kMpBlock = 256;
-constexpr int kGather = 8;             // lanes per MP in the gather phase
+constexpr int kGather = 16;            // lanes per MP in the gather phase
 constexpr int kSlots = 32 / kGather;   // pairs per lane loaded branch-free
 
 template <typename R>
@@ -114,37 +114,68 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   for (int i = tid; i <= kMpBlock; i += kMpBlock) row[i] = offsets[min(base + i, n_mp)];
   __syncthreads();
 
-  // phase 1: gather with kGather lanes per MP
-  {
+  // phase 1: gather with kGather lanes per MP, software-pipelined: a round
+  // issues its node gathers (whose ids arrived in the previous round), then
+  // the pair data of the next round, then does its arithmetic, so each round
+  // waits for one memory latency instead of two.  Slots past the row end load
+  // pair 0 / node 0 and get weight 0, so all loads are branch-free.
+  if (lists_ok && have_nodes) {
     const int lane = tid % kGather;
+    // raw loads of one round (slot k of the row, or pair 0 past its end)
+    int32_t iv[kSlots];
+    double wv[kSlots], d0[kSlots], d1[kSlots], d2[kSlots];
+    bool use[kSlots];
+    auto load_pairs = [&](int r) {
+      const int local = r * (kMpBlock / kGather) + tid / kGather;
+      const int64_t o0 = row[local], o1 = row[local + 1];
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int64_t q = o0 + k * kGather + lane;
+        use[k] = q < o1;
+        // unconditional loads (qq is always a valid pair slot); the selects
+        // come where the values are used, one round later
+        const int64_t qq = use[k] ? q : 0;
+        iv[k] = idx[qq];
+        wv[k] = N[qq];
+        d0[k] = (double)dN[qq];
+        d1[k] = (double)dN[cap + qq];
+        d2[k] = (double)dN[2 * cap + qq];
+      }
+    };
+    load_pairs(0);
     for (int r = 0; r < kGather; ++r) {
       const int local = r * (kMpBlock / kGather) + tid / kGather;
-      double a[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      if (lists_ok && have_nodes) {
-        const int64_t o0 = row[local], o1 = row[local + 1];
-        // branch-free loads (pair 0 stands in past the row end, weight 0), so
-        // the compiler can keep all of them in flight together
-        auto add_pair = [&](int64_t q, bool use) {
-          const int64_t qq = use ? q : 0;
-          const int32_t I = use ? idx[qq] : 0;  // node 0 stands in (its values get weight 0)
-          const double w = use ? N[qq] : 0.0;
-          const double g0 = use ? (double)dN[qq] : 0.0;
-          const double g1 = use ? (double)dN[cap + qq] : 0.0;
-          const double g2 = use ? (double)dN[2 * cap + qq] : 0.0;
-          const double4 xv = nodes[2 * (int64_t)I], uv = nodes[2 * (int64_t)I + 1];
-          a[0] += w * xv.x;
-          a[1] += w * xv.y;
-          a[2] += w * xv.z;
-          a[3] += uv.x * g0; a[4] += uv.x * g1; a[5] += uv.x * g2;
-          a[6] += uv.y * g0; a[7] += uv.y * g1; a[8] += uv.y * g2;
-          a[9] += uv.z * g0; a[10] += uv.z * g1; a[11] += uv.z * g2;
-        };
+      double4 xv[kSlots], uv[kSlots];
+      double wc[kSlots], gc[kSlots][3];
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-          const int64_t q = o0 + k * kGather + lane;
-          add_pair(q, q < o1);
-        }
-        for (int64_t q = o0 + kSlots * kGather + lane; q < o1; q += kGather) add_pair(q, true);
+      for (int k = 0; k < kSlots; ++k) {
+        const int32_t I = use[k] ? iv[k] : 0;  // node 0 stands in (idx[0] is unset without pairs)
+        xv[k] = nodes[2 * (int64_t)I];
+        uv[k] = nodes[2 * (int64_t)I + 1];
+        wc[k] = use[k] ? wv[k] : 0.0;
+        gc[k][0] = use[k] ? d0[k] : 0.0;
+        gc[k][1] = use[k] ? d1[k] : 0.0;
+        gc[k][2] = use[k] ? d2[k] : 0.0;
+      }
+      // unconditional (the last round reloads its own rows) so that the
+      // waits below need not cover a path without these loads
+      load_pairs(r + 1 < kGather ? r + 1 : r);
+      double a[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      auto add = [&](double wt, double h0, double h1, double h2, const double4& x4,
+                     const double4& u4) {
+        a[0] += wt * x4.x; a[1] += wt * x4.y; a[2] += wt * x4.z;
+        a[3] += u4.x * h0; a[4] += u4.x * h1; a[5] += u4.x * h2;
+        a[6] += u4.y * h0; a[7] += u4.y * h1; a[8] += u4.y * h2;
+        a[9] += u4.z * h0; a[10] += u4.z * h1; a[11] += u4.z * h2;
+      };
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) add(wc[k], gc[k][0], gc[k][1], gc[k][2], xv[k], uv[k]);
+      // pairs past kSlots * kGather (long rows), read directly
+      const int64_t o0 = row[local], o1 = row[local + 1];
+      for (int64_t q = o0 + kSlots * kGather + lane; q < o1; q += kGather) {
+        const int32_t J = idx[q];
+        add(N[q], (double)dN[q], (double)dN[cap + q], (double)dN[2 * cap + q],
+            nodes[2 * (int64_t)J], nodes[2 * (int64_t)J + 1]);
       }
 #pragma unroll
       for (int c = 0; c < 12; ++c) a[c] = group_sum<kGather>(a[c]);
@@ -153,6 +184,8 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
         for (int c = 0; c < 12; ++c) sums[c][local] = a[c];
       }
     }
+  } else {
+    for (int i = tid; i < 12 * kMpBlock; i += kMpBlock) sums[i / kMpBlock][i % kMpBlock] = 0.0;
   }
   __syncthreads();
 
