@@ -32,13 +32,16 @@ struct Workspace {
   int32_t* node_cell;    // [n_nodes]
   double4* sorted;       // [n_nodes]: x, y, z, node id
   int64_t* scan_aux;     // scan partial sums (int64 view)
-  int32_t* block_max;    // [n_mp / 64 + 1] largest support per search workgroup
+  int32_t* block_max;    // [n_mp / 64 + 1] largest support per compaction workgroup
   int64_t* tr_start;     // [n_nodes + 1] influence-list offsets
   int32_t* tr_cursor;    // [n_nodes]
   int32_t* tr_pairs;     // [pair_capacity] pair ids sorted by node, then pair
   int32_t* pair_mp;      // [pair_capacity] MP of each pair
-  int32_t* stage;        // [kRowCapacity][n_mp] sorted rows of the one-pass search
+  int32_t* stage;        // [n_mp][kRowCapacity] sorted rows of the one-pass search
   double4* nodes;        // [2 n_nodes] packed node records
+  int32_t* mp_cell_start;  // [cap_cells + 1] MPs binned on the search grid
+  int32_t* mp_cell;        // [n_mp]
+  double4* mp_sorted;      // [n_mp]: x, y, z, MP id
 };
 
 // Lays the workspace out over [base, base + bytes).  Returns the bytes needed

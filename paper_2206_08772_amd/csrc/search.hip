@@ -233,8 +233,32 @@ OTM_DEV int cell_coord(double x, double lo, double inv_cell, int dim) {
   return c;
 }
 
-__global__ void k_bin_count(const double* x, int64_t n, const Grid* g, int32_t* node_cell,
-                            int32_t* cell_start) {
+// Points of one wave that fall in the same cell share one atomic: the lanes
+// of each distinct cell id are found by ballot, the lowest of them adds the
+// group's size, and each lane takes its rank inside the group.  Spatially
+// ordered points (lattice nodes, MPs in hex order) put few cells in a wave.
+// Returns the value the atomic returned for the lane's group plus the lane's
+// rank in it.
+OTM_DEV int32_t grouped_atomic_add(int32_t* counters, int32_t cid) {
+  int32_t out = 0;
+  uint64_t todo = __ballot(true);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int32_t lc = __builtin_amdgcn_readlane(cid, leader);
+    const uint64_t same = __ballot(cid == lc);
+    int32_t base = 0;
+    if ((int)__lane_id() == leader) base = atomicAdd(&counters[lc], (int32_t)__popcll(same));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if (cid == lc)
+      out = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
+                       (uint32_t)(same >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+    todo &= ~same;
+  }
+  return out;
+}
+
+__global__ __launch_bounds__(256) void k_bin_count(const double* x, int64_t n, const Grid* g,
+                                                   int32_t* node_cell, int32_t* cell_start) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double inv = 1.0 / g->cell;
@@ -243,15 +267,17 @@ __global__ void k_bin_count(const double* x, int64_t n, const Grid* g, int32_t* 
   const int cz = cell_coord(x[2 * n + i], g->lo[2], inv, g->dims[2]);
   const int32_t cid = (cz * g->dims[1] + cy) * g->dims[0] + cx;
   node_cell[i] = cid;
-  atomicAdd(&cell_start[cid + 1], 1);
+  grouped_atomic_add(cell_start + 1, cid);
 }
 
-__global__ void k_bin_fill(const double* x, int64_t n, const int32_t* node_cell,
-                           const int32_t* cell_start, int32_t* cursor, double4* sorted) {
+__global__ __launch_bounds__(256) void k_bin_fill(const double* x, int64_t n,
+                                                  const int32_t* node_cell,
+                                                  const int32_t* cell_start, int32_t* cursor,
+                                                  double4* sorted) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t cid = node_cell[i];
-  const int32_t pos = cell_start[cid] + atomicAdd(&cursor[cid], 1);
+  const int32_t pos = cell_start[cid] + grouped_atomic_add(cursor, cid);
   sorted[pos] = make_double4(x[i], x[n + i], x[2 * n + i], (double)i);
 }
 
@@ -288,121 +314,256 @@ OTM_DEV void for_each_neighbor(double px, double py, double pz, double r2, const
   }
 }
 
-// One pass over the 27 cells per MP.  A group of 8 lanes shares one MP: the
-// lanes test consecutive node records of each row of cells together (so a
-// load instruction touches few cache lines), hits are appended to the MP's
-// list in LDS by a ballot prefix count, and the list is then put in
-// ascending id order by a rank sort (ids are distinct).  The count goes to
-// offsets[p+1] and the sorted row to the block's staging area, rows of
-// kRowCap ids per MP, contiguous per workgroup.  Longer rows are only
-// counted here and re-found by the compaction kernel.
-constexpr int kScanThreads = 256;
-constexpr int kScanLanes = 8;
-constexpr int kScanMPs = 64;   // MPs per workgroup (two rounds of 32 groups)
-constexpr int kScanUnroll = 4;
+// Row ranges of the 27 cells around cell (cx, cy, cz): the 9 (z, y) rows of
+// three cells each are contiguous in the binned array.  Rows outside the
+// grid are empty.  pre[k] is the number of candidates before row k.
+OTM_DEV void cell_rows(const Grid& g, const int32_t* __restrict__ cell_start, int cx, int cy,
+                       int cz, int32_t rs[9], int32_t pre[10]) {
+  const int x0 = cx > 0 ? cx - 1 : 0;
+  const int x1 = cx + 1 < g.dims[0] ? cx + 1 : g.dims[0] - 1;
+  int32_t re[9];
+  // branch-free: every load is issued (clamped rows), then masked
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int z = cz - 1 + k / 3, y = cy - 1 + k % 3;
+    const bool in = z >= 0 && z < g.dims[2] && y >= 0 && y < g.dims[1];
+    const int zc = z < 0 ? 0 : (z >= g.dims[2] ? g.dims[2] - 1 : z);
+    const int yc = y < 0 ? 0 : (y >= g.dims[1] ? g.dims[1] - 1 : y);
+    const int rw = (zc * g.dims[1] + yc) * g.dims[0];
+    const int32_t a = cell_start[rw + x0], b = cell_start[rw + x1 + 1];
+    rs[k] = in ? a : 0;
+    re[k] = in ? b : 0;
+  }
+  pre[0] = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) pre[k + 1] = pre[k] + (re[k] - rs[k]);
+}
+
+// Position in the binned array of candidate c (0 <= c < pre[9]).
+OTM_DEV int32_t cand_pos(int32_t c, const int32_t rs[9], const int32_t pre[10]) {
+  int32_t shift = rs[0] - pre[0];
+#pragma unroll
+  for (int k = 1; k < 9; ++k) shift = c >= pre[k] ? rs[k] - pre[k] : shift;
+  return c + shift;
+}
+
+OTM_DEV void wave_sync() {
+  // the wave's lanes read each other's LDS writes after this point
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+OTM_DEV double lane_value(double v, int t) {  // v of lane t (t uniform)
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, t);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), t);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Cell-centric pass: one wave per grid cell.  All MPs of a cell have the same
+// 27 candidate cells, so the wave loads the candidates once, puts them in
+// ascending node id order (rank sort of the ids in LDS; ids are distinct)
+// and keeps them in registers, lane l holding candidates l, l + 64, ...  Each
+// MP of the cell (binned like the nodes) is then tested against them: a
+// ballot of the hits, taken in candidate order, is already the MP's sorted
+// row, written to its staging row at the hit's prefix count.  The count goes
+// to offsets[p + 1]; rows longer than kRowCap are only counted (the
+// compaction re-finds them).  A cell with more than kCand candidates takes
+// each MP separately: hits are appended to LDS by ballot and rank-sorted.
+//
+// The cell index is wave-uniform, so a cell's header (MP range, candidate
+// rows) comes from scalar loads, and the next cell's header is requested
+// before the current cell is processed.  Each XCD strides over its own
+// contiguous eighth of the cells (neighbouring cells share that XCD's L2).
+constexpr int kCellWaves = 4;
+constexpr unsigned kCellBlocks = 8 * 512;
+constexpr int kCand = 320;
+constexpr int kCandChunks = kCand / kWave;
 constexpr int kRowCap = kRowCapacity;
 
-__global__ __launch_bounds__(kScanThreads) void k_nbr_scan(
-    const double* __restrict__ xp, int64_t n_mp, double r2, const Grid* __restrict__ gp,
-    const int32_t* __restrict__ cell_start, const double4* __restrict__ sorted,
-    int64_t* __restrict__ offsets, int32_t* __restrict__ stage, int32_t* __restrict__ block_max) {
-  __shared__ int32_t found[kScanThreads / kScanLanes][kRowCap];
-  __shared__ int32_t red[kScanThreads];
-  int32_t nmax = 0;
-  const int tid = threadIdx.x, grp = tid / kScanLanes, lane = tid % kScanLanes;
-  const int wave_grp = (tid % kWave) / kScanLanes;  // group index inside the wave
-  const int64_t blk = xcd_block();
-  if (blk == 0 && tid == 0) offsets[0] = 0;
-  const Grid g = *gp;
-  for (int r = 0; r < kScanMPs / (kScanThreads / kScanLanes); ++r) {
-    const int local = r * (kScanThreads / kScanLanes) + grp;
-    const int64_t p = blk * kScanMPs + local;
-    const bool valid = p < n_mp;
-    int32_t n = 0;
-    if (valid) {
-      const double px = xp[p], py = xp[n_mp + p], pz = xp[2 * n_mp + p];
-      // the 9 row ranges, loaded together; candidates are then taken as one
-      // flat list, kScanUnroll chunks of 8 per iteration with independent loads
-      int32_t rs[9], pre[10];
-      {
-        const double inv = 1.0 / g.cell;
-        const int cx = cell_coord(px, g.lo[0], inv, g.dims[0]);
-        const int cy = cell_coord(py, g.lo[1], inv, g.dims[1]);
-        const int cz = cell_coord(pz, g.lo[2], inv, g.dims[2]);
-        const int x0 = cx > 0 ? cx - 1 : 0;
-        const int x1 = cx + 1 < g.dims[0] ? cx + 1 : g.dims[0] - 1;
-        int32_t re[9];
-        // branch-free: every load is issued (clamped rows), then masked
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          const int z = cz - 1 + k / 3, y = cy - 1 + k % 3;
-          const bool in = z >= 0 && z < g.dims[2] && y >= 0 && y < g.dims[1];
-          const int zc = z < 0 ? 0 : (z >= g.dims[2] ? g.dims[2] - 1 : z);
-          const int yc = y < 0 ? 0 : (y >= g.dims[1] ? g.dims[1] - 1 : y);
-          const int rw = (zc * g.dims[1] + yc) * g.dims[0];
-          const int32_t a = cell_start[rw + x0], b = cell_start[rw + x1 + 1];
-          rs[k] = in ? a : 0;
-          re[k] = in ? b : 0;
-        }
-        pre[0] = 0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) pre[k + 1] = pre[k] + (re[k] - rs[k]);
-      }
-      const int32_t total = pre[9];
-      for (int32_t b = 0; b < total; b += kScanLanes * kScanUnroll) {
-        double4 nd[kScanUnroll];
-        bool in[kScanUnroll];
-#pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
-          const int32_t c = b + u * kScanLanes + lane;
-          in[u] = c < total;
-          int32_t shift = rs[0] - pre[0];
-#pragma unroll
-          for (int k = 1; k < 9; ++k) shift = c >= pre[k] ? rs[k] - pre[k] : shift;
-          nd[u] = sorted[in[u] ? c + shift : 0];  // record 0 stands in past the end
-        }
-#pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
-          const bool hit = in[u] && sqdist(px, py, pz, nd[u].x, nd[u].y, nd[u].z) <= r2;
-          const uint64_t m = __ballot(hit);
-          const uint32_t gm = (uint32_t)(m >> (wave_grp * kScanLanes)) & 0xffu;
-          const int pos = n + __popc(gm & ((1u << lane) - 1u));
-          if (hit && pos < kRowCap) found[grp][pos] = (int32_t)nd[u].w;
-          n += __popc(gm);
-        }
-      }
-    }
-    // the group's lanes read each other's LDS writes below
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (valid) {
-      if (lane == 0) offsets[p + 1] = n;
-      nmax = n > nmax ? n : nmax;
-      if (n <= kRowCap) {
-        int32_t* row = stage + (blk * kScanMPs + local) * kRowCap;
-        for (int e = lane; e < n; e += kScanLanes) {
-          const int32_t v = found[grp][e];
-          int rank = 0;
-          for (int j = 0; j < n; ++j) rank += found[grp][j] < v;
-          row[rank] = v;
-        }
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  // largest support of the workgroup (reduced once more by k_search_done;
-  // one atomic per MP on a single counter would serialise the whole pass)
-  red[tid] = nmax;
-  __syncthreads();
-  for (int o = kScanThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) red[tid] = red[tid] > red[tid + o] ? red[tid] : red[tid + o];
-    __syncthreads();
-  }
-  if (tid == 0) block_max[blk] = red[0];
+struct CellHdr {
+  int32_t m0, m1;
+  int32_t rs[9], pre[10];
+};
+
+OTM_DEV CellHdr cell_header(int64_t c, const Grid& g, const int32_t* __restrict__ cell_start,
+                            const int32_t* __restrict__ mp_cell_start) {
+  CellHdr h;
+  h.m0 = mp_cell_start[c];
+  h.m1 = mp_cell_start[c + 1];
+  const int32_t ci = (int32_t)c;  // cell counts stay below 2^31
+  const int cx = ci % g.dims[0];
+  const int cy = (ci / g.dims[0]) % g.dims[1];
+  const int cz = ci / (g.dims[0] * g.dims[1]);
+  cell_rows(g, cell_start, cx, cy, cz, h.rs, h.pre);
+  return h;
 }
+
+struct CellLds {  // candidate coordinates and ids, structure of arrays
+  double x[kCand], y[kCand], z[kCand];
+  int32_t ids[kCand];
+};
+
+OTM_DEV void cell_scan_one(const CellHdr& h, double r2, const double4* __restrict__ sorted,
+                           const double4* __restrict__ mp_sorted, int64_t* __restrict__ offsets,
+                           int32_t* __restrict__ stage, CellLds& L, int lane) {
+  const int32_t m0 = h.m0, m1 = h.m1;
+  if (m0 == m1) return;
+  const int32_t T = h.pre[9];
+  if (T <= kCand) {
+    const int nch = (T + kWave - 1) / kWave;  // uniform
+    double4 v[kCandChunks];
+    // the first 64 MPs of the cell, requested with the candidates
+    const int mc0 = m1 - m0 < kWave ? (int)(m1 - m0) : kWave;
+    double4 mine = mp_sorted[m0 + (lane < mc0 ? lane : mc0 - 1)];
+    if (T > 0) {
+      // ids padded with INT32_MAX to a multiple of 16 (never smaller than an id)
+      const int32_t T16 = (T + 15) & ~15;
+      int32_t id[kCandChunks];
+#pragma unroll
+      for (int k = 0; k < kCandChunks; ++k) {
+        if (k < nch) {
+          const int32_t j = k * kWave + lane;
+          v[k] = sorted[cand_pos(j < T ? j : 0, h.rs, h.pre)];
+          id[k] = j < T ? (int32_t)v[k].w : INT32_MAX;
+          if (j < T16) L.ids[j] = id[k];
+        }
+      }
+      wave_sync();
+      // rank = number of smaller ids, 16 ids per step from four 16-byte LDS
+      // reads (broadcast: every lane reads the same words); each candidate
+      // is then stored at its rank and read back in rank order
+      int32_t r[kCandChunks];
+#pragma unroll
+      for (int k = 0; k < kCandChunks; ++k) r[k] = 0;
+      for (int32_t t = 0; t < T16; t += 16) {
+        int4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = *(const int4*)&L.ids[t + 4 * u];
+#pragma unroll
+        for (int k = 0; k < kCandChunks; ++k) {
+          if (k < nch) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              r[k] += (q[u].x < id[k]) + (q[u].y < id[k]) + (q[u].z < id[k]) + (q[u].w < id[k]);
+          }
+        }
+      }
+      wave_sync();  // every rank is known before the ids are overwritten
+#pragma unroll
+      for (int k = 0; k < kCandChunks; ++k) {
+        const int32_t j = k * kWave + lane;
+        if (k < nch && j < T) {
+          L.x[r[k]] = v[k].x; L.y[r[k]] = v[k].y; L.z[r[k]] = v[k].z;
+          L.ids[r[k]] = id[k];
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int k = 0; k < kCandChunks; ++k) {
+        const int32_t j = k * kWave + lane;
+        if (k < nch) {
+          const int32_t jj = j < T ? j : 0;
+          v[k] = make_double4(L.x[jj], L.y[jj], L.z[jj], (double)L.ids[jj]);
+        }
+      }
+      wave_sync();  // the LDS arrays are free again for the next cell
+    }
+    // per chunk: lanes holding a real candidate, and the candidate ids
+    bool valid[kCandChunks];
+    int32_t cid[kCandChunks];
+#pragma unroll
+    for (int k = 0; k < kCandChunks; ++k) {
+      valid[k] = k * kWave + lane < T;
+      cid[k] = (int32_t)v[k].w;
+    }
+    for (int32_t mb = m0; mb < m1; mb += kWave) {
+      const int mc = m1 - mb < kWave ? (int)(m1 - mb) : kWave;
+      if (mb != m0) mine = mp_sorted[mb + (lane < mc ? lane : mc - 1)];
+      const int32_t pl = (int32_t)mine.w;  // this lane's MP
+      for (int t = 0; t < mc; ++t) {
+        const double px = lane_value(mine.x, t), py = lane_value(mine.y, t);
+        const double pz = lane_value(mine.z, t);
+        const int32_t p = __builtin_amdgcn_readlane(pl, t);
+        int32_t* row = stage + (int64_t)p * kRowCap;
+        uint32_t n = 0;
+#pragma unroll
+        for (int k = 0; k < kCandChunks; ++k) {
+          if (k < nch) {
+            // every lane computes the distance (stand-ins are masked), so no
+            // branch around it
+            const bool hit = (sqdist(px, py, pz, v[k].x, v[k].y, v[k].z) <= r2) & valid[k];
+            const uint64_t m = __ballot(hit);
+            const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, n));
+            if (hit & (pos < (uint32_t)kRowCap)) row[pos] = cid[k];
+            n += (uint32_t)__popcll(m);
+          }
+        }
+        if (lane == 0) offsets[p + 1] = n;
+      }
+    }
+  } else {
+    // dense neighbourhood: one MP at a time, candidates read from memory
+    for (int32_t m = m0; m < m1; ++m) {
+      const double4 mp = mp_sorted[m];
+      const int64_t p = (int64_t)mp.w;
+      int32_t n = 0;
+      for (int32_t b = 0; b < T; b += kWave) {
+        const int32_t j = b + lane;
+        const double4 nd = sorted[cand_pos(j < T ? j : 0, h.rs, h.pre)];
+        const bool hit = j < T && sqdist(mp.x, mp.y, mp.z, nd.x, nd.y, nd.z) <= r2;
+        const uint64_t msk = __ballot(hit);
+        const int pos = n + (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(msk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)msk, 0u));
+        if (hit && pos < kCand) L.ids[pos] = (int32_t)nd.w;
+        n += __popcll(msk);
+      }
+      wave_sync();
+      if (n <= kRowCap) {
+        int32_t* row = stage + p * kRowCap;
+        if (lane < n) {
+          const int32_t id = L.ids[lane];
+          int rk = 0;
+          for (int t = 0; t < n; ++t) rk += L.ids[t] < id;
+          row[rk] = id;
+        }
+      }
+      if (lane == 0) offsets[p + 1] = n;
+      wave_sync();
+    }
+  }
+}
+
+__global__ __launch_bounds__(kCellWaves * kWave) void k_cell_scan(
+    double r2, const Grid* __restrict__ gp, int64_t cap_cells,
+    const int32_t* __restrict__ cell_start, const double4* __restrict__ sorted,
+    const int32_t* __restrict__ mp_cell_start, const double4* __restrict__ mp_sorted,
+    int64_t* __restrict__ offsets, int32_t* __restrict__ stage) {
+  __shared__ CellLds lds[kCellWaves];
+  // wave index as a uniform value, so the cell loop runs on scalar registers
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x % kWave);
+  if (blockIdx.x == 0 && threadIdx.x == 0) offsets[0] = 0;
+  const Grid g = *gp;
+  const int64_t n_cells = g.n_cells < cap_cells ? g.n_cells : cap_cells;
+  const int64_t per_xcd = (n_cells + 7) / 8;
+  const int64_t c_lo = (int64_t)(blockIdx.x % 8u) * per_xcd;
+  const int64_t c_hi = c_lo + per_xcd < n_cells ? c_lo + per_xcd : n_cells;
+  const int64_t stride = (int64_t)(gridDim.x / 8u) * kCellWaves;
+  int64_t c = c_lo + (int64_t)(blockIdx.x / 8u) * kCellWaves + w;
+  if (c >= c_hi) return;
+  CellHdr h = cell_header(c, g, cell_start, mp_cell_start);
+  for (; c < c_hi; c += stride) {
+    const int64_t cn = c + stride < c_hi ? c + stride : c;
+    const CellHdr hn = cell_header(cn, g, cell_start, mp_cell_start);  // next cell, early
+    cell_scan_one(h, r2, sorted, mp_sorted, offsets, stage, lds[w], lane);
+    h = hn;
+  }
+}
+
+constexpr int kScanMPs = 64;  // MPs per compaction workgroup
 
 // Copies each workgroup's staged rows into its contiguous CSR segment with
 // unit-stride stores; rows longer than kRowCap are found again and sorted
@@ -411,16 +572,31 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
     const double* __restrict__ xp, int64_t n_mp, double r2, const Grid* __restrict__ gp,
     const int32_t* __restrict__ cell_start, const double4* __restrict__ sorted,
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ stage, int64_t capacity,
-    int32_t* __restrict__ idx) {
+    int32_t* __restrict__ idx, int32_t* __restrict__ block_max) {
   __shared__ int32_t rows[kScanMPs * kRowCap];
   __shared__ int64_t off[kScanMPs + 1];
   const int tid = threadIdx.x;
   const int64_t blk = xcd_block();
   const int64_t p0 = blk * kScanMPs;
   if (p0 >= n_mp) return;
-  if (offsets[n_mp] > capacity) return;  // lists do not fit: counts only
   const int nloc = (int)(n_mp - p0 < kScanMPs ? n_mp - p0 : kScanMPs);
   for (int i = tid; i <= nloc; i += 256) off[i] = offsets[p0 + i];
+  __syncthreads();
+  // largest support of the workgroup (reduced once more by k_search_done;
+  // one atomic per MP on a single counter would serialise the pass)
+  if (tid < kWave) {
+    int32_t m = 0;
+    for (int i = tid; i < nloc; i += kWave) {
+      const int32_t K = (int32_t)(off[i + 1] - off[i]);
+      m = K > m ? K : m;
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      const int32_t u = __shfl_xor(m, o);
+      m = u > m ? u : m;
+    }
+    if (tid == 0) block_max[blk] = m;
+  }
+  if (offsets[n_mp] > capacity) return;  // lists do not fit: counts only
   for (int i = tid; i < nloc * kRowCap; i += 256) rows[i] = stage[p0 * kRowCap + i];
   __syncthreads();
   const int64_t base = off[0];
@@ -492,13 +668,23 @@ void launch_search(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const d
                                    w.sorted);
   const double r2 = r_list * r_list;
   if (n_mp > 0) {
-    const unsigned nbs = (unsigned)((n_mp + kScanMPs - 1) / kScanMPs);
-    k_nbr_scan<<<nbs, kScanThreads, 0, s>>>(x_mp, n_mp, r2, w.grid, w.cell_start, w.sorted,
-                                            nbr_offsets, w.stage, w.block_max);
+    // MPs binned on the same grid (cell_cursor is free again)
+    fill_i32(w.mp_cell_start, w.cap_cells + 1, 0, s);
+    fill_i32(w.cell_cursor, w.cap_cells, 0, s);
+    const unsigned nbm = (unsigned)((n_mp + 255) / 256);
+    k_bin_count<<<nbm, 256, 0, s>>>(x_mp, n_mp, w.grid, w.mp_cell, w.mp_cell_start);
+    scan_inclusive(w.mp_cell_start + 1, w.cap_cells, w.scan_aux, s);
+    k_bin_fill<<<nbm, 256, 0, s>>>(x_mp, n_mp, w.mp_cell, w.mp_cell_start, w.cell_cursor,
+                                   w.mp_sorted);
+    // a fixed grid (a multiple of the 8 XCDs) strides over the cells
+    k_cell_scan<<<kCellBlocks, kCellWaves * kWave, 0, s>>>(r2, w.grid, w.cap_cells, w.cell_start,
+                                                   w.sorted, w.mp_cell_start, w.mp_sorted,
+                                                   nbr_offsets, w.stage);
     scan_inclusive(nbr_offsets + 1, n_mp, w.scan_aux, s);
-    k_nbr_compact<<<nbs, 256, 0, s>>>(
-        x_mp, n_mp, r2, w.grid, w.cell_start, w.sorted, nbr_offsets, w.stage, pair_capacity,
-        nbr_idx);
+    const unsigned nbs = (unsigned)((n_mp + kScanMPs - 1) / kScanMPs);
+    k_nbr_compact<<<nbs, 256, 0, s>>>(x_mp, n_mp, r2, w.grid, w.cell_start, w.sorted,
+                                      nbr_offsets, w.stage, pair_capacity, nbr_idx,
+                                      w.block_max);
   } else {
     k_set_first_offset<<<1, 1, 0, s>>>(nbr_offsets);
   }
