@@ -79,8 +79,9 @@ def node_bytes(n_nodes):
 
 
 def src_digest():
+    """Digest of the sources the MP-pass kernel is compiled from."""
     h = hashlib.sha256()
-    for f in ("mp_update.hip", "otm_common.h"):
+    for f in ("mp_update.hip", "constitutive.h", "otm_common.h", "launch.h"):
         h.update(open(os.path.join(ROOT, "paper_2206_08772_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
