@@ -357,10 +357,7 @@ struct AdjMpArgs {
   double* bedb;
   double* epsb;
   double* Tb;
-  double* Nb;      // per pair of state n (written)
-  double* dNb;     // [3][stride] (written)
-  double* xb1;     // node adjoints of state n+1 (accumulated)
-  double* dub1;
+  double* dfb;     // adjoint of dF per MP [9][n_mp] (written, workspace)
   double* theta_part;  // [gridDim][3]
   Mat<double> M;
   double dt;
@@ -589,14 +586,12 @@ OTM_DEV void mp_adjoint(const AdjMpArgs& a, int64_t p, const double dF[3][3], do
 }
 
 __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
-  __shared__ double sums[9][kAdjMpBlock];   // dF - 1, then the adjoint of dF
-  __shared__ NodeSums<6, 10> tab;
+  __shared__ double sums[9][kAdjMpBlock];   // dF - 1 of the workgroup's MPs
   __shared__ double thred[3][kAdjMpBlock];
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)xcd_block() * kAdjMpBlock;
   const int lane = tid % kAdjGather;
   constexpr int groups = kAdjMpBlock / kAdjGather;
-  sums_clear(tab);
   // phase 1: H = dF - 1 = sum du'_I (x) grad N_I
   for (int r = 0; r < kAdjMpBlock / groups; ++r) {
     const int local = r * groups + tid / kAdjGather;
@@ -637,7 +632,7 @@ __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
         for (int j = 0; j < 3; ++j) dFb[i][j] += vb1 * a.vol[p] * cof[i][j];
       a.volb[p] = vb1 * detdF;
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) sums[3 * i + j][tid] = dFb[i][j];
+        for (int j = 0; j < 3; ++j) a.dfb[(3 * i + j) * a.n_mp + p] = dFb[i][j];
     }
   }
   for (int k = 0; k < 3; ++k) thred[k][tid] = th[k];
@@ -650,26 +645,48 @@ __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
   }
   if (tid == 0)
     for (int k = 0; k < 3; ++k) a.theta_part[blockIdx.x * 3 + k] = thred[k][0];
-  // phase 3: per pair, x_p' = sum N_I x_I' and dF = 1 + sum du_I' (x) grad N_I
+}
+
+// ------------------------------------------- K3b: MP update, node adjoints
+// Per pair of state n: x_p' = sum N_I x_I' gives x_I' the term N_I x_p'_bar and
+// dF = 1 + sum du_I' (x) grad N_I gives du_I' the term dF_bar grad N_I, both
+// pre-summed per node in LDS (256 consecutive MPs per workgroup share most of
+// their nodes) and then added with one float64 atomic per node and value.
+constexpr int kAdjScatMPs = 256;
+constexpr int kAdjScatLanes = 8;
+
+struct AdjScatArgs {
+  int64_t n_nodes, n_mp, stride;
+  const int64_t* off;
+  const int32_t* idx;
+  const double* N;
+  const double* dN;
+  const double* xpb1;  // adjoint of x_p' [3][n_mp]
+  const double* dfb;   // adjoint of dF [9][n_mp]
+  double* xb1;         // node adjoints of state n+1 (accumulated)
+  double* dub1;
+};
+
+__global__ __launch_bounds__(256) void k_adj_mp_scatter(AdjScatArgs a) {
+  __shared__ NodeSums<6, 10> tab;
+  sums_clear(tab);
+  __syncthreads();
   double* const dst[6] = {a.xb1, a.xb1 + a.n_nodes, a.xb1 + 2 * a.n_nodes,
                           a.dub1, a.dub1 + a.n_nodes, a.dub1 + 2 * a.n_nodes};
-  for (int r = 0; r < kAdjMpBlock / groups; ++r) {
-    const int local = r * groups + tid / kAdjGather;
-    const int64_t p = base + local;
+  const int64_t base = (int64_t)xcd_block() * kAdjScatMPs;
+  const int lane = threadIdx.x % kAdjScatLanes;
+  for (int r = 0; r < kAdjScatMPs / (256 / kAdjScatLanes); ++r) {
+    const int64_t p = base + r * (256 / kAdjScatLanes) + threadIdx.x / kAdjScatLanes;
     if (p >= a.n_mp) continue;
-    const double xpb[3] = {a.xpb1[p], a.xpb1[a.n_mp + p], a.xpb1[2 * a.n_mp + p]};
+    const int64_t n = a.n_mp;
+    const double xpb[3] = {a.xpb1[p], a.xpb1[n + p], a.xpb1[2 * n + p]};
     double Fb[3][3];
     for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) Fb[i][j] = sums[3 * i + j][local];
-    for (int64_t q = a.off[p] + lane; q < a.off[p + 1]; q += kAdjGather) {
+      for (int j = 0; j < 3; ++j) Fb[i][j] = a.dfb[(3 * i + j) * n + p];
+    for (int64_t q = a.off[p] + lane; q < a.off[p + 1]; q += kAdjScatLanes) {
       const int32_t I = a.idx[q];
       const double w = a.N[q];
       const double g[3] = {a.dN[q], a.dN[a.stride + q], a.dN[2 * a.stride + q]};
-      const double u[3] = {a.du1[I], a.du1[a.n_nodes + I], a.du1[2 * a.n_nodes + I]};
-      const double xI[3] = {a.x1[I], a.x1[a.n_nodes + I], a.x1[2 * a.n_nodes + I]};
-      a.Nb[q] = xI[0] * xpb[0] + xI[1] * xpb[1] + xI[2] * xpb[2];
-      for (int j = 0; j < 3; ++j)
-        a.dNb[j * a.stride + q] = Fb[0][j] * u[0] + Fb[1][j] * u[1] + Fb[2][j] * u[2];
       double c[6];
       for (int i = 0; i < 3; ++i) {
         c[i] = w * xpb[i];
@@ -753,40 +770,53 @@ struct AdjAsmArgs {
   int64_t n_nodes, n_mp, stride;
   const int64_t* off;
   const int32_t* idx;
-  const double* N;
   const double* dN;
   const double* vol;
   const double* mass;
   const double* sigma;
   const double* fb;
   const double* mb;
-  double* Nb;      // += per pair
-  double* dNb;     // +=
+  const double* x1;    // nodes of state n+1
+  const double* du1;
+  const double* xpb1;  // adjoint of x_p' [3][n_mp]
+  const double* dfb;   // adjoint of dF [9][n_mp]
+  double* Nb;      // written per pair
+  double* dNb;     // written per pair [3][stride]
   double* sigb;    // written
   double* volb;    // +=
 };
 
+// Pair adjoints of state n in one pass: N_I enters x_p' = sum N_I x_I' and the
+// lumped mass m_I = sum N_I m_p; grad N_I enters dF = 1 + sum du_I' (x) grad N_I
+// and the force f_I = -sum v sigma grad N_I.  The MP sums of the force terms
+// give the adjoints of sigma and v.
 constexpr int kAdjAsmLanes = 8;
 __global__ __launch_bounds__(256) void k_adj_assembly(AdjAsmArgs a) {
   const int64_t p = (int64_t)xcd_block() * (256 / kAdjAsmLanes) + threadIdx.x / kAdjAsmLanes;
   const int lane = threadIdx.x % kAdjAsmLanes;
   if (p >= a.n_mp) return;
-  const int64_t n = a.n_mp;
+  const int64_t n = a.n_mp, nn = a.n_nodes;
   const double v = a.vol[p], mp = a.mass[p];
   double s[6];
   for (int c = 0; c < 6; ++c) s[c] = a.sigma[c * n + p];
+  const double xpb[3] = {a.xpb1[p], a.xpb1[n + p], a.xpb1[2 * n + p]};
+  double Fb[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Fb[i][j] = a.dfb[(3 * i + j) * n + p];
   double sb[6] = {0, 0, 0, 0, 0, 0}, vb = 0.0;
   for (int64_t q = a.off[p] + lane; q < a.off[p + 1]; q += kAdjAsmLanes) {
     const int32_t I = a.idx[q];
     const double g[3] = {a.dN[q], a.dN[a.stride + q], a.dN[2 * a.stride + q]};
-    const double f[3] = {a.fb[I], a.fb[a.n_nodes + I], a.fb[2 * a.n_nodes + I]};
-    // m_I += N m_p
-    a.Nb[q] += a.mb[I] * mp;
+    const double f[3] = {a.fb[I], a.fb[nn + I], a.fb[2 * nn + I]};
+    const double xI[3] = {a.x1[I], a.x1[nn + I], a.x1[2 * nn + I]};
+    const double u[3] = {a.du1[I], a.du1[nn + I], a.du1[2 * nn + I]};
+    a.Nb[q] = xI[0] * xpb[0] + xI[1] * xpb[1] + xI[2] * xpb[2] + a.mb[I] * mp;
     // f_I = -v sigma g
     const double sf[3] = {s[0] * f[0] + s[3] * f[1] + s[5] * f[2],
                           s[3] * f[0] + s[1] * f[1] + s[4] * f[2],
                           s[5] * f[0] + s[4] * f[1] + s[2] * f[2]};
-    for (int j = 0; j < 3; ++j) a.dNb[j * a.stride + q] -= v * sf[j];
+    for (int j = 0; j < 3; ++j)
+      a.dNb[j * a.stride + q] = Fb[0][j] * u[0] + Fb[1][j] * u[1] + Fb[2][j] * u[2] - v * sf[j];
     vb -= sf[0] * g[0] + sf[1] * g[1] + sf[2] * g[2];
     sb[0] -= v * f[0] * g[0];
     sb[1] -= v * f[1] * g[1];
@@ -825,7 +855,7 @@ size_t adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp) {
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
   const int64_t nb = (n_mp + kAdjMpBlock - 1) / kAdjMpBlock + 1;
   return al(sizeof(double) * 3 * (size_t)n_mp) + al(sizeof(double) * 4 * (size_t)n_nodes) +
-         al(sizeof(double) * 3 * (size_t)nb);
+         al(sizeof(double) * 3 * (size_t)nb) + al(sizeof(double) * 9 * (size_t)n_mp);
 }
 
 void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_params& p,
@@ -840,12 +870,16 @@ void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_param
   double* mb = fb + 3 * nn;
   c += al(sizeof(double) * 4 * (size_t)nn);
   double* theta_part = (double*)c;
+  c += al(sizeof(double) * 3 * (size_t)((nm + kAdjMpBlock - 1) / kAdjMpBlock + 1));
+  double* dfb = (double*)c;
 
   if (nm > 0) {
+    // K1: shape functions of state n+1
     AdjLmeArgs la{nn, nm, t1.pair_stride, t1.x, t1.xp, t1.lam, t1.nbr_offsets, t1.nbr_idx,
                   b1.N, b1.dN, p.beta, xpb, b1.x, diag};
     const int per = (256 / kAdjG) * kAdjLmeRounds;
     k_adj_lme<<<(unsigned)((nm + per - 1) / per), 256, 0, s>>>(la);
+    // K3: MP update per MP (adjoint of dF to the workspace), then its node terms
     AdjMpArgs ma;
     ma.n_nodes = nn; ma.n_mp = nm; ma.stride = t0.pair_stride;
     ma.off = t0.nbr_offsets; ma.idx = t0.nbr_idx; ma.N = t0.N; ma.dN = t0.dN;
@@ -854,7 +888,7 @@ void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_param
     ma.xpb1 = xpb; ma.volb1 = b1.vol; ma.Fdb1 = b1.Fd; ma.bedb1 = b1.bed; ma.epsb1 = b1.epsbar;
     ma.Tb1 = b1.T; ma.sigb1 = b1.sigma;
     ma.volb = b0.vol; ma.Fdb = b0.Fd; ma.bedb = b0.bed; ma.epsb = b0.epsbar; ma.Tb = b0.T;
-    ma.Nb = b0.N; ma.dNb = b0.dN; ma.xb1 = b1.x; ma.dub1 = b1.du;
+    ma.dfb = dfb;
     ma.theta_part = theta_part;
     ma.M = make_mat<double>(p, dt);
     ma.dt = dt;
@@ -862,8 +896,12 @@ void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_param
     const unsigned nbm = (unsigned)((nm + kAdjMpBlock - 1) / kAdjMpBlock);
     k_adj_mp<<<nbm, kAdjMpBlock, 0, s>>>(ma);
     k_adj_theta<<<1, 256, 0, s>>>(theta_part, nbm, theta_bar);
+    AdjScatArgs sa{nn, nm, t0.pair_stride, t0.nbr_offsets, t0.nbr_idx, t0.N, t0.dN,
+                   xpb, dfb, b1.x, b1.du};
+    k_adj_mp_scatter<<<(unsigned)((nm + kAdjScatMPs - 1) / kAdjScatMPs), 256, 0, s>>>(sa);
   }
   if (nn > 0) {
+    // K5: node update
     AdjNodeArgs na;
     na.n = nn; na.x = t0.x; na.du = t0.du; na.m = t0.m; na.f = t0.f;
     na.xb1 = b1.x; na.dub1 = b1.du; na.xb = b0.x; na.dub = b0.du; na.fb = fb; na.mb = mb;
@@ -873,8 +911,10 @@ void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_param
     k_adj_node<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(na);
   }
   if (nm > 0) {
-    AdjAsmArgs aa{nn, nm, t0.pair_stride, t0.nbr_offsets, t0.nbr_idx, t0.N, t0.dN, t0.vol,
-                  mass, t0.sigma, fb, mb, b0.N, b0.dN, b0.sigma, b0.vol};
+    // K6: pair adjoints of state n, and the adjoints of sigma and v
+    AdjAsmArgs aa{nn, nm, t0.pair_stride, t0.nbr_offsets, t0.nbr_idx, t0.dN, t0.vol,
+                  mass, t0.sigma, fb, mb, t1.x, t1.du, xpb, dfb, b0.N, b0.dN, b0.sigma,
+                  b0.vol};
     k_adj_assembly<<<(unsigned)((nm + (256 / kAdjAsmLanes) - 1) / (256 / kAdjAsmLanes)), 256, 0,
                      s>>>(aa);
   }
