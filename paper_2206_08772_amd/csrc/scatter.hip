@@ -162,7 +162,7 @@ namespace otm {
 // float64 atomic each.  Summation order varies from run to run.
 constexpr int kAsmMPs = 512;
 constexpr int kAsmLanes = 8;
-constexpr int kAsmSlotBits = 11;
+constexpr int kAsmSlotBits = 10;
 constexpr int kAsmSlots = 1 << kAsmSlotBits;
 
 template <typename R>
@@ -219,22 +219,24 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
       c2 = (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2));
       c3 = (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2));
     };
+    const int K = (int)(o1 - o0);
+    auto slot = [&](int t) { return o0 + t; };
     // first 4 slots per lane: loads issued together (row start stands in for
     // slots past the end), then the table updates
     int32_t Iu[4];
     double cu[4][4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int64_t q = o0 + k * kAsmLanes + lane;
-      contrib(q < o1 ? q : o0, Iu[k], cu[k][0], cu[k][1], cu[k][2], cu[k][3]);
+      const int t = k * kAsmLanes + lane;
+      contrib(t < K ? slot(t) : o0, Iu[k], cu[k][0], cu[k][1], cu[k][2], cu[k][3]);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (o0 + k * kAsmLanes + lane < o1) insert(Iu[k], cu[k][0], cu[k][1], cu[k][2], cu[k][3]);
-    for (int64_t q = o0 + 4 * kAsmLanes + lane; q < o1; q += kAsmLanes) {
+      if (k * kAsmLanes + lane < K) insert(Iu[k], cu[k][0], cu[k][1], cu[k][2], cu[k][3]);
+    for (int t = 4 * kAsmLanes + lane; t < K; t += kAsmLanes) {
       int32_t I;
       double c0, c1, c2, c3;
-      contrib(q, I, c0, c1, c2, c3);
+      contrib(slot(t), I, c0, c1, c2, c3);
       insert(I, c0, c1, c2, c3);
     }
   }
