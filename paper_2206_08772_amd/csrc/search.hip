@@ -123,6 +123,20 @@ void launch_fill_i64(int64_t* a, int64_t n, int64_t v, hipStream_t s) {
 }
 static void fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s) { launch_fill_i32(a, n, v, s); }
 
+// Zeroes two int32 arrays in one launch (cell counters before a binning).
+__global__ void k_zero2_i32(int32_t* a, int64_t na, int32_t* b, int64_t nb) {
+  const int64_t n = na > nb ? na : nb;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < na) a[i] = 0;
+    if (i < nb) b[i] = 0;
+  }
+}
+static void zero2_i32(int32_t* a, int64_t na, int32_t* b, int64_t nb, hipStream_t s) {
+  const int64_t n = na > nb ? na : nb;
+  if (n > 0) k_zero2_i32<<<fill_blocks(n), 256, 0, s>>>(a, na, b, nb);
+}
+
 __global__ void k_diag_reset(otm_diag* d) {
   d->flags = 0;
   d->max_support = 0;
@@ -574,7 +588,9 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ stage, int64_t capacity,
     int32_t* __restrict__ idx, int32_t* __restrict__ block_max) {
   __shared__ int32_t rows[kScanMPs * kRowCap];
+  __shared__ uint8_t owner[kScanMPs * kRowCap];  // MP of each output element
   __shared__ int64_t off[kScanMPs + 1];
+  __shared__ int32_t blk_max;
   const int tid = threadIdx.x;
   const int64_t blk = xcd_block();
   const int64_t p0 = blk * kScanMPs;
@@ -594,13 +610,30 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
       const int32_t u = __shfl_xor(m, o);
       m = u > m ? u : m;
     }
-    if (tid == 0) block_max[blk] = m;
+    if (tid == 0) {
+      block_max[blk] = m;
+      blk_max = m;
+    }
   }
   if (offsets[n_mp] > capacity) return;  // lists do not fit: counts only
   for (int i = tid; i < nloc * kRowCap; i += 256) rows[i] = stage[p0 * kRowCap + i];
   __syncthreads();
   const int64_t base = off[0];
   const int total = (int)(off[nloc] - base);
+  if (blk_max <= kRowCap) {
+    // every row is staged: mark the MP of each output element, then copy
+    // with unit-stride stores
+    for (int t = tid; t < nloc * kRowCap; t += 256) {
+      const int i = t / kRowCap, j = t - i * kRowCap;
+      if (j < (int)(off[i + 1] - off[i])) owner[(int)(off[i] - base) + j] = (uint8_t)i;
+    }
+    __syncthreads();
+    for (int e = tid; e < total; e += 256) {
+      const int i = owner[e];
+      idx[base + e] = rows[i * kRowCap + (e - (int)(off[i] - base))];
+    }
+    return;
+  }
   for (int e = tid; e < total; e += 256) {
     // MP of output element e: last t with off[t] - base <= e
     int lo = 0, hi = nloc - 1;
@@ -631,24 +664,23 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
 
 __global__ void k_set_first_offset(int64_t* offsets) { offsets[0] = 0; }
 
-__global__ __launch_bounds__(256) void k_search_done(const int64_t* offsets, int64_t n_mp,
-                                                     const int32_t* block_max, int64_t nblocks,
-                                                     int64_t capacity, otm_diag* diag) {
-  __shared__ int32_t red[256];
+__global__ __launch_bounds__(1024) void k_search_done(const int64_t* offsets, int64_t n_mp,
+                                                      const int32_t* block_max, int64_t nblocks,
+                                                      int64_t capacity, otm_diag* diag) {
+  __shared__ int32_t red[1024 / kWave];
   int32_t m = 0;
-  for (int64_t b = threadIdx.x; b < nblocks; b += 256) m = block_max[b] > m ? block_max[b] : m;
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o)
-      red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + o] ? red[threadIdx.x]
-                                                                 : red[threadIdx.x + o];
-    __syncthreads();
+  for (int64_t b = threadIdx.x; b < nblocks; b += 1024) m = block_max[b] > m ? block_max[b] : m;
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const int32_t u = __shfl_xor(m, o);
+    m = u > m ? u : m;
   }
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
   if (threadIdx.x != 0 || diag == nullptr) return;
+  for (int w = 1; w < 1024 / kWave; ++w) m = red[w] > m ? red[w] : m;
   const int64_t P = offsets[n_mp];
   diag->pairs_needed = P;
-  diag->max_support = red[0];
+  diag->max_support = m;
   if (P > capacity) atomicOr(&diag->flags, 1u << (-OTM_ERR_CAPACITY - 1));
 }
 
@@ -657,8 +689,7 @@ void launch_search(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const d
                    int32_t* nbr_idx, const Workspace& w, otm_diag* diag, hipStream_t s) {
   k_bbox_partial<<<kBBoxBlocks, 256, 0, s>>>(x_nodes, n_nodes, w.bbox_part);
   k_grid_finalize<<<1, 256, 0, s>>>(w.bbox_part, kBBoxBlocks, cell_size, w.cap_cells, w.grid);
-  fill_i32(w.cell_start, w.cap_cells + 1, 0, s);
-  fill_i32(w.cell_cursor, w.cap_cells, 0, s);
+  zero2_i32(w.cell_start, w.cap_cells + 1, w.cell_cursor, w.cap_cells, s);
   const unsigned nbn = (unsigned)((n_nodes + 255) / 256);
   if (nbn > 0)
     k_bin_count<<<nbn, 256, 0, s>>>(x_nodes, n_nodes, w.grid, w.node_cell, w.cell_start);
@@ -669,8 +700,7 @@ void launch_search(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const d
   const double r2 = r_list * r_list;
   if (n_mp > 0) {
     // MPs binned on the same grid (cell_cursor is free again)
-    fill_i32(w.mp_cell_start, w.cap_cells + 1, 0, s);
-    fill_i32(w.cell_cursor, w.cap_cells, 0, s);
+    zero2_i32(w.mp_cell_start, w.cap_cells + 1, w.cell_cursor, w.cap_cells, s);
     const unsigned nbm = (unsigned)((n_mp + 255) / 256);
     k_bin_count<<<nbm, 256, 0, s>>>(x_mp, n_mp, w.grid, w.mp_cell, w.mp_cell_start);
     scan_inclusive(w.mp_cell_start + 1, w.cap_cells, w.scan_aux, s);
@@ -689,7 +719,8 @@ void launch_search(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const d
     k_set_first_offset<<<1, 1, 0, s>>>(nbr_offsets);
   }
   const int64_t nbs_all = (n_mp + kScanMPs - 1) / kScanMPs;
-  k_search_done<<<1, 256, 0, s>>>(nbr_offsets, n_mp, w.block_max, nbs_all, pair_capacity, diag);
+  k_search_done<<<1, 1024, 0, s>>>(nbr_offsets, n_mp, w.block_max, nbs_all, pair_capacity,
+                                   diag);
 }
 
 }  // namespace otm
