@@ -37,6 +37,28 @@ OTM_DEV void node_xyz(const NodeSrc& s, int32_t I, double& a, double& b, double&
   }
 }
 
+// exp(x) for the shifted exponents of the LME weights (x <= 0 up to
+// rounding): Cody-Waite reduction x = k ln2 + r with ln2 split in a 32-bit
+// head and its remainder (k ln2_hi is exact), |r| <= ln2/2, then the Taylor
+// polynomial of degree 12 in Horner form (truncation below 2e-16 relative on
+// that range) and a scale by 2^k; 0 below -745.  The coefficients sit in
+// constant memory, so they reach the FMAs from scalar registers.
+__constant__ double kExpTaylor[13] = {
+    1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664, 0.008333333333333333,
+    0.001388888888888889, 0.0001984126984126984, 2.48015873015873e-05,
+    2.7557319223985893e-06, 2.755731922398589e-07, 2.505210838544172e-08,
+    2.08767569878681e-09};
+OTM_DEV double lme_exp(double x) {
+  const double k = rint(x * 1.4426950408889634);
+  double r = fma(k, -0.6931471803691238, x);
+  r = fma(k, -1.9082149292705877e-10, r);
+  double p = kExpTaylor[12];
+#pragma unroll
+  for (int i = 11; i >= 0; --i) p = fma(p, r, kExpTaylor[i]);
+  const double e = ldexp(p, (int)k);
+  return x < -745.0 ? 0.0 : e;
+}
+
 struct Eval {
   double logZ, Z, fmax;
   double r[3];
@@ -86,7 +108,7 @@ OTM_DEV void lme_eval(const Pairs<G, PPL, CACHED>& pr, int lane, int K, int64_t 
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
       if (k * G + lane < K) {
-        ek[k] = exp(ek[k] - fm);
+        ek[k] = lme_exp(ek[k] - fm);
         accum(ek[k], pr.d[k][0], pr.d[k][1], pr.d[k][2]);
       }
     }
@@ -97,7 +119,7 @@ OTM_DEV void lme_eval(const Pairs<G, PPL, CACHED>& pr, int lane, int K, int64_t 
       node_xyz(ns, I, nx, ny, nz);
       const double dx = px - nx, dy = py - ny, dz = pz - nz;
       const double f = -beta * ((dx * dx + dy * dy) + dz * dz) + (lam[0] * dx + lam[1] * dy + lam[2] * dz);
-      accum(exp(f - fm), dx, dy, dz);
+      accum(lme_exp(f - fm), dx, dy, dz);
     }
   }
   Z = group_sum<G>(Z);
@@ -214,7 +236,7 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
       node_xyz(ns, I, nx, ny, nz);
       const double dx = px - nx, dy = py - ny, dz = pz - nz;
       const double f = -beta * ((dx * dx + dy * dy) + dz * dz) + (lam[0] * dx + lam[1] * dy + lam[2] * dz);
-      finish(q, exp(f - ev.fmax), dx, dy, dz);
+      finish(q, lme_exp(f - ev.fmax), dx, dy, dz);
     }
   }
 }
