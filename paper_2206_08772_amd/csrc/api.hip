@@ -35,6 +35,7 @@ size_t carve_workspace(void* base, size_t bytes, int64_t n_nodes, int64_t n_mp,
       align256(sizeof(int32_t) * (cap_cells + 1)),
       align256(sizeof(int32_t) * (size_t)n_mp),
       align256(sizeof(double4) * (size_t)n_mp),
+      align256(sizeof(double4) * (size_t)pair_capacity),
   };
   size_t total = 0;
   for (size_t s : sizes) total += s;
@@ -54,12 +55,13 @@ size_t carve_workspace(void* base, size_t bytes, int64_t n_nodes, int64_t n_mp,
   w->tr_start = (int64_t*)take(8);
   w->tr_cursor = (int32_t*)take(9);
   w->tr_pairs = (int32_t*)take(10);
-  w->pair_mp = (int32_t*)take(11);
+  w->tr_pos = (int32_t*)take(11);
   w->stage = (int32_t*)take(12);
   w->nodes = (double4*)take(13);
   w->mp_cell_start = (int32_t*)take(14);
   w->mp_cell = (int32_t*)take(15);
   w->mp_sorted = (double4*)take(16);
+  w->contrib = (double4*)take(17);
   return total;
 }
 

@@ -35,13 +35,14 @@ struct Workspace {
   int32_t* block_max;    // [n_mp / 64 + 1] largest support per compaction workgroup
   int64_t* tr_start;     // [n_nodes + 1] influence-list offsets
   int32_t* tr_cursor;    // [n_nodes]
-  int32_t* tr_pairs;     // [pair_capacity] pair ids sorted by node, then pair
-  int32_t* pair_mp;      // [pair_capacity] MP of each pair
+  int32_t* tr_pairs;     // [pair_capacity] pair ids bucketed by node (order within a bucket unset)
+  int32_t* tr_pos;       // [pair_capacity] place of each pair in the node-sorted order
   int32_t* stage;        // [n_mp][kRowCapacity] sorted rows of the one-pass search
   double4* nodes;        // [2 n_nodes] packed node records
   int32_t* mp_cell_start;  // [cap_cells + 1] MPs binned on the search grid
   int32_t* mp_cell;        // [n_mp]
   double4* mp_sorted;      // [n_mp]: x, y, z, MP id
+  double4* contrib;        // [pair_capacity] pair contributions (m, f) in node-sorted order
 };
 
 // Lays the workspace out over [base, base + bytes).  Returns the bytes needed

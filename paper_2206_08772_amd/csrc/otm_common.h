@@ -87,6 +87,37 @@ OTM_DEV double group_max(double v) {
   return group_reduce<G>(v, [](double a, double b) { return fmax(a, b); });
 }
 
+// Active lanes of a wave that count into the same slot share one atomic: the
+// lanes of each distinct slot id are found by ballot, the lowest of them adds
+// the group's size, and each lane takes its rank inside the group.
+// Spatially ordered items (lattice nodes, MPs in hex order, the pairs of
+// neighbouring MPs) put few distinct slots in a wave.  Returns the value the
+// atomic returned for the lane's group plus the lane's rank in it.
+template <typename C>
+OTM_DEV C grouped_atomic_add(C* counters, int32_t cid) {
+  C out = 0;
+  uint64_t todo = __ballot(true);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int32_t lc = __builtin_amdgcn_readlane(cid, leader);
+    const uint64_t same = __ballot(cid == lc);
+    C base = 0;
+    if ((int)__lane_id() == leader) base = atomicAdd(&counters[lc], (C)__popcll(same));
+    if constexpr (sizeof(C) == 8) {
+      const uint64_t u = (uint64_t)base;
+      base = (C)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(u >> 32), leader) << 32) |
+                 __builtin_amdgcn_readlane((uint32_t)u, leader));
+    } else {
+      base = (C)__builtin_amdgcn_readlane((int32_t)base, leader);
+    }
+    if (cid == lc)
+      out = base + (C)__builtin_amdgcn_mbcnt_hi(
+                       (uint32_t)(same >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+    todo &= ~same;
+  }
+  return out;
+}
+
 // ------------------------------------------------------------- 3x3 algebra
 template <typename R>
 struct M3 {

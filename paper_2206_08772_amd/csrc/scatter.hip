@@ -9,18 +9,70 @@
 
 namespace otm {
 
+// Counting sort of the pairs by node.  A workgroup takes 512 consecutive MPs
+// (rows walked by 8 lanes each), counts its pairs per node in an LDS hash
+// table, and adds one global atomic per distinct node; the fill repeats the
+// count, reserves each node's run with one global atomic, and places each
+// pair at its rank inside the workgroup's run.  Bucket order is then fixed
+// by k_tr_sort.
+constexpr int kTrMPs = 512;
+constexpr int kTrLanes = 8;
+constexpr int kTrSlotBits = 11;
+constexpr int kTrSlots = 1 << kTrSlotBits;
+
+struct TrTable {
+  int32_t key[kTrSlots];
+  int32_t cnt[kTrSlots];
+  int32_t base[kTrSlots];
+};
+
+OTM_DEV void tr_clear(TrTable& t) {
+  for (int i = threadIdx.x; i < kTrSlots; i += blockDim.x) {
+    t.key[i] = -1;
+    t.cnt[i] = 0;
+  }
+}
+
+// Slot of node I in the table (claimed if new), or -1 if the table is full.
+OTM_DEV int tr_slot(TrTable& t, int32_t I) {
+  uint32_t h = ((uint32_t)I * 2654435761u) >> (32 - kTrSlotBits);
+  for (int probe = 0; probe < 64; ++probe) {
+    const int32_t prev = atomicCAS(&t.key[h], -1, I);
+    if (prev == -1 || prev == I) return (int)h;
+    h = (h + 1) & (kTrSlots - 1);
+  }
+  return -1;
+}
+
+template <typename Visit>
+OTM_DEV void tr_for_each_pair(int64_t base, int64_t n_mp, const int64_t* __restrict__ offsets,
+                              Visit&& visit) {
+  const int lane = threadIdx.x % kTrLanes;
+  for (int r = 0; r < kTrMPs / (256 / kTrLanes); ++r) {
+    const int64_t p = base + r * (256 / kTrLanes) + threadIdx.x / kTrLanes;
+    if (p >= n_mp) continue;
+    for (int64_t q = offsets[p] + lane; q < offsets[p + 1]; q += kTrLanes) visit(q);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_tr_count(int64_t n_mp, int64_t cap,
                                                   const int64_t* __restrict__ offsets,
                                                   const int32_t* __restrict__ idx,
-                                                  unsigned long long* __restrict__ cnt,
-                                                  int32_t* __restrict__ pair_mp) {
-  const int64_t p = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (p >= n_mp) return;
+                                                  unsigned long long* __restrict__ cnt) {
+  __shared__ TrTable t;
   if (offsets[n_mp] > cap) return;  // lists were not written (capacity)
-  for (int64_t q = offsets[p]; q < offsets[p + 1]; ++q) {
-    atomicAdd(&cnt[idx[q] + 1], 1ull);
-    pair_mp[q] = (int32_t)p;
-  }
+  tr_clear(t);
+  __syncthreads();
+  const int64_t base = (int64_t)xcd_block() * kTrMPs;
+  tr_for_each_pair(base, n_mp, offsets, [&](int64_t q) {
+    const int32_t I = idx[q];
+    const int h = tr_slot(t, I);
+    if (h >= 0) atomicAdd(&t.cnt[h], 1);
+    else atomicAdd(&cnt[I + 1], 1ull);  // crowded table
+  });
+  __syncthreads();
+  for (int i = threadIdx.x; i < kTrSlots; i += blockDim.x)
+    if (t.key[i] >= 0) atomicAdd(&cnt[t.key[i] + 1], (unsigned long long)t.cnt[i]);
 }
 
 __global__ __launch_bounds__(256) void k_tr_fill(int64_t n_mp, int64_t cap,
@@ -29,53 +81,67 @@ __global__ __launch_bounds__(256) void k_tr_fill(int64_t n_mp, int64_t cap,
                                                  const int64_t* __restrict__ start,
                                                  int32_t* __restrict__ cursor,
                                                  int32_t* __restrict__ pairs) {
-  const int64_t p = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (p >= n_mp) return;
+  __shared__ TrTable t;
   if (offsets[n_mp] > cap) return;
-  for (int64_t q = offsets[p]; q < offsets[p + 1]; ++q) {
-    const int32_t I = idx[q];
-    const int32_t slot = atomicAdd(&cursor[I], 1);
-    pairs[start[I] + slot] = (int32_t)q;
+  tr_clear(t);
+  __syncthreads();
+  const int64_t base = (int64_t)xcd_block() * kTrMPs;
+  tr_for_each_pair(base, n_mp, offsets, [&](int64_t q) {
+    const int h = tr_slot(t, idx[q]);
+    if (h >= 0) atomicAdd(&t.cnt[h], 1);
+  });
+  __syncthreads();
+  // reserve each node's run; the counters restart as ranks
+  for (int i = threadIdx.x; i < kTrSlots; i += blockDim.x) {
+    const int32_t I = t.key[i];
+    if (I >= 0) {
+      t.base[i] = (int32_t)start[I] + atomicAdd(&cursor[I], t.cnt[i]);
+      t.cnt[i] = 0;
+    }
   }
+  __syncthreads();
+  tr_for_each_pair(base, n_mp, offsets, [&](int64_t q) {
+    const int32_t I = idx[q];
+    const int h = tr_slot(t, I);  // finds the slot claimed above (or -1 if crowded)
+    const int64_t pos = h >= 0 ? (int64_t)t.base[h] + atomicAdd(&t.cnt[h], 1)
+                               : start[I] + atomicAdd(&cursor[I], 1);
+    pairs[pos] = (int32_t)q;
+  });
 }
 
-// One wave per node: rank sort of the bucket (pair ids are distinct).
-constexpr int kSortLds = 1024;
+// Sixteen lanes per node: the place of each pair of the bucket in ascending
+// pair order (a rank count; pair ids are distinct), written straight to pos_of
+// so the sorted bucket itself is never stored.  Buckets up to kSortCap are
+// ranked from LDS, longer ones (degenerate inputs) from global memory.
+constexpr int kSortLanes = 16;
+constexpr int kSortNodes = 256 / kSortLanes;
+constexpr int kSortCap = 256;
 __global__ __launch_bounds__(256) void k_tr_sort(int64_t n_nodes, const int64_t* __restrict__ start,
-                                                 int32_t* __restrict__ pairs) {
-  __shared__ int32_t buf[4][kSortLds];
-  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int64_t I = (int64_t)blockIdx.x * 4 + w;
+                                                 const int32_t* __restrict__ pairs,
+                                                 int32_t* __restrict__ pos_of) {
+  __shared__ int32_t buf[kSortNodes][kSortCap];
+  const int g = threadIdx.x / kSortLanes, lane = threadIdx.x % kSortLanes;
+  const int64_t I = (int64_t)xcd_block() * kSortNodes + g;
   if (I >= n_nodes) return;
   const int64_t s0 = start[I];
   const int n = (int)(start[I + 1] - s0);
-  if (n <= 1) return;
-  if (n <= kSortLds) {
-    for (int i = lane; i < n; i += kWave) buf[w][i] = pairs[s0 + i];
+  if (n <= kSortCap) {
+    for (int i = lane; i < n; i += kSortLanes) buf[g][i] = pairs[s0 + i];
+    // the group's lanes are in one wave: a wave barrier orders the LDS accesses
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    int32_t vals[kSortLds / kWave];
-    int ranks[kSortLds / kWave];
-    int cntv = 0;
-    for (int i = lane; i < n; i += kWave) {
-      const int32_t v = buf[w][i];
+    for (int i = lane; i < n; i += kSortLanes) {
+      const int32_t v = buf[g][i];
       int r = 0;
-      for (int j = 0; j < n; ++j) r += buf[w][j] < v;
-      vals[cntv] = v;
-      ranks[cntv] = r;
-      ++cntv;
+      for (int j = 0; j < n; ++j) r += buf[g][j] < v;
+      pos_of[v] = (int32_t)(s0 + r);
     }
-    for (int k = 0; k < cntv; ++k) pairs[s0 + ranks[k]] = vals[k];
-  } else if (lane == 0) {
-    // very long bucket: insertion sort in place by one lane
-    for (int i = 1; i < n; ++i) {
+  } else {
+    for (int i = lane; i < n; i += kSortLanes) {
       const int32_t v = pairs[s0 + i];
-      int j = i;
-      while (j > 0 && pairs[s0 + j - 1] > v) {
-        pairs[s0 + j] = pairs[s0 + j - 1];
-        --j;
-      }
-      pairs[s0 + j] = v;
+      int r = 0;
+      for (int j = 0; j < n; ++j) r += pairs[s0 + j] < v;
+      pos_of[v] = (int32_t)(s0 + r);
     }
   }
 }
@@ -86,42 +152,63 @@ void launch_influence_lists(const otm_state& st, const Workspace& w, hipStream_t
   launch_fill_i64(w.tr_start, nn + 1, 0, s);
   launch_fill_i32(w.tr_cursor, nn, 0, s);
   if (nm > 0) {
-    const unsigned nb = (unsigned)((nm + 255) / 256);
+    const unsigned nb = (unsigned)((nm + kTrMPs - 1) / kTrMPs);
     k_tr_count<<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.nbr_idx,
-                                  (unsigned long long*)w.tr_start, w.pair_mp);
+                                  (unsigned long long*)w.tr_start);
     scan_inclusive(w.tr_start + 1, nn, w.scan_aux, s);
-    k_tr_fill<<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.nbr_idx, w.tr_start, w.tr_cursor,
-                                 w.tr_pairs);
-    k_tr_sort<<<(unsigned)((nn + 3) / 4), 256, 0, s>>>(nn, w.tr_start, w.tr_pairs);
+    k_tr_fill<<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.nbr_idx, w.tr_start,
+                                 w.tr_cursor, w.tr_pairs);
+    k_tr_sort<<<(unsigned)((nn + kSortNodes - 1) / kSortNodes), 256, 0, s>>>(nn, w.tr_start,
+                                                                             w.tr_pairs, w.tr_pos);
+  }
+}
+
+// Deterministic assembly.  Per step, each pair's four contributions
+// (N m_p and -v sigma grad N) are computed MP by MP and stored at the pair's
+// place in the node-sorted order; each node then sums its contiguous run in
+// that fixed order (ascending pair id) with a fixed reduction tree, so the
+// result is identical from run to run and the gather reads are unit-stride.
+constexpr int kScLanes = 8;
+constexpr int kScMPs = 256 / kScLanes;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_seg_contrib(
+    int64_t n_mp, int64_t cap, const int64_t* __restrict__ offsets,
+    const double* __restrict__ N, const R* __restrict__ dN, const double* __restrict__ vol,
+    const double* __restrict__ mass, const R* __restrict__ sigma,
+    const int32_t* __restrict__ pos_of, double4* __restrict__ contrib) {
+  const int64_t p = (int64_t)xcd_block() * kScMPs + threadIdx.x / kScLanes;
+  const int lane = threadIdx.x % kScLanes;
+  if (p >= n_mp) return;
+  if (offsets[n_mp] > cap) return;
+  const double mp = mass[p];
+  const R v = (R)vol[p];
+  const R s0 = sigma[p], s1 = sigma[n_mp + p], s2 = sigma[2 * n_mp + p];
+  const R s3 = sigma[3 * n_mp + p], s4 = sigma[4 * n_mp + p], s5 = sigma[5 * n_mp + p];
+  for (int64_t q = offsets[p] + lane; q < offsets[p + 1]; q += kScLanes) {
+    const R g0 = dN[q], g1 = dN[cap + q], g2 = dN[2 * cap + q];
+    contrib[pos_of[q]] = make_double4(N[q] * mp, (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2)),
+                                      (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2)),
+                                      (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2)));
   }
 }
 
 constexpr int kSegLanes = 8;
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_scatter_seg(
-    int64_t n_nodes, int64_t n_mp, int64_t cap, const int64_t* __restrict__ offsets,
-    const int64_t* __restrict__ start, const int32_t* __restrict__ pairs,
-    const int32_t* __restrict__ pair_mp, const double* __restrict__ N, const R* __restrict__ dN,
-    const double* __restrict__ vol, const double* __restrict__ mass,
-    const R* __restrict__ sigma, double* __restrict__ m, double* __restrict__ f) {
+__global__ __launch_bounds__(256) void k_seg_gather(int64_t n_nodes, int64_t n_mp, int64_t cap,
+                                                    const int64_t* __restrict__ offsets,
+                                                    const int64_t* __restrict__ start,
+                                                    const double4* __restrict__ contrib,
+                                                    double* __restrict__ m,
+                                                    double* __restrict__ f) {
   const int64_t I = (int64_t)xcd_block() * (256 / kSegLanes) + threadIdx.x / kSegLanes;
   const int lane = threadIdx.x % kSegLanes;
   if (I >= n_nodes) return;
   if (offsets[n_mp] > cap) return;
   double am = 0, a0 = 0, a1 = 0, a2 = 0;
   for (int64_t j = start[I] + lane; j < start[I + 1]; j += kSegLanes) {
-    const int32_t q = pairs[j];
-    const int32_t p = pair_mp[q];
-    const double w = N[q];
-    am += w * mass[p];
-    const R g0 = dN[q], g1 = dN[cap + q], g2 = dN[2 * cap + q];
-    const R s0 = sigma[p], s1 = sigma[n_mp + p], s2 = sigma[2 * n_mp + p];
-    const R s3 = sigma[3 * n_mp + p], s4 = sigma[4 * n_mp + p], s5 = sigma[5 * n_mp + p];
-    const R v = (R)vol[p];
-    a0 += (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2));
-    a1 += (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2));
-    a2 += (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2));
+    const double4 c = contrib[j];
+    am += c.x; a0 += c.y; a1 += c.z; a2 += c.w;
   }
   am = group_sum<kSegLanes>(am);
   a0 = group_sum<kSegLanes>(a0);
@@ -136,19 +223,22 @@ __global__ __launch_bounds__(256) void k_scatter_seg(
 }
 
 void launch_scatter_segmented(const otm_state& st, const Workspace& w, hipStream_t s) {
-  const int64_t nn = st.n_nodes;
+  const int64_t nn = st.n_nodes, nm = st.n_mp;
   if (nn <= 0) return;
+  if (nm > 0) {
+    const unsigned nb = (unsigned)((nm + kScMPs - 1) / kScMPs);
+    if (st.precision == OTM_FP64)
+      k_seg_contrib<double><<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.N,
+                                               (const double*)st.dN, st.vol, st.mass,
+                                               (const double*)st.sigma, w.tr_pos, w.contrib);
+    else
+      k_seg_contrib<float><<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.N,
+                                              (const float*)st.dN, st.vol, st.mass,
+                                              (const float*)st.sigma, w.tr_pos, w.contrib);
+  }
   const unsigned nb = (unsigned)((nn + (256 / kSegLanes) - 1) / (256 / kSegLanes));
-  if (st.precision == OTM_FP64)
-    k_scatter_seg<double><<<nb, 256, 0, s>>>(nn, st.n_mp, st.pair_capacity, st.nbr_offsets,
-                                             w.tr_start, w.tr_pairs, w.pair_mp, st.N,
-                                             (const double*)st.dN, st.vol, st.mass,
-                                             (const double*)st.sigma, st.m, st.f);
-  else
-    k_scatter_seg<float><<<nb, 256, 0, s>>>(nn, st.n_mp, st.pair_capacity, st.nbr_offsets,
-                                            w.tr_start, w.tr_pairs, w.pair_mp, st.N,
-                                            (const float*)st.dN, st.vol, st.mass,
-                                            (const float*)st.sigma, st.m, st.f);
+  k_seg_gather<<<nb, 256, 0, s>>>(nn, nm, st.pair_capacity, st.nbr_offsets, w.tr_start,
+                                  w.contrib, st.m, st.f);
 }
 
 }  // namespace otm

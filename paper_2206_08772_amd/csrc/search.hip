@@ -247,30 +247,6 @@ OTM_DEV int cell_coord(double x, double lo, double inv_cell, int dim) {
   return c;
 }
 
-// Points of one wave that fall in the same cell share one atomic: the lanes
-// of each distinct cell id are found by ballot, the lowest of them adds the
-// group's size, and each lane takes its rank inside the group.  Spatially
-// ordered points (lattice nodes, MPs in hex order) put few cells in a wave.
-// Returns the value the atomic returned for the lane's group plus the lane's
-// rank in it.
-OTM_DEV int32_t grouped_atomic_add(int32_t* counters, int32_t cid) {
-  int32_t out = 0;
-  uint64_t todo = __ballot(true);
-  while (todo) {
-    const int leader = __builtin_ctzll(todo);
-    const int32_t lc = __builtin_amdgcn_readlane(cid, leader);
-    const uint64_t same = __ballot(cid == lc);
-    int32_t base = 0;
-    if ((int)__lane_id() == leader) base = atomicAdd(&counters[lc], (int32_t)__popcll(same));
-    base = __builtin_amdgcn_readlane(base, leader);
-    if (cid == lc)
-      out = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
-                       (uint32_t)(same >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
-    todo &= ~same;
-  }
-  return out;
-}
-
 __global__ __launch_bounds__(256) void k_bin_count(const double* x, int64_t n, const Grid* g,
                                                    int32_t* node_cell, int32_t* cell_start) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
