@@ -25,7 +25,7 @@ namespace otm {
 // keeps in its workspace (one 32-byte load per node).
 struct NodeSrc {
   const double* x;       // [3][n] (used when packed == nullptr)
-  const double4* packed; // record 2 I = (x, y, z, 0)
+  const double4* packed; // record 2 I = (x, y, z, du_x)
   int64_t n;
 };
 OTM_DEV void node_xyz(const NodeSrc& s, int32_t I, double& a, double& b, double& c) {

@@ -8,9 +8,12 @@
 //     reduce by shuffles and park the 12 sums in LDS;
 //   phase 2 (update): one lane per MP reads its sums back and runs the
 //     constitutive update, so the heavy scalar code uses every lane.
-// The node update also writes each node as two 32-byte records (x, y, z, 0)
-// and (du, 0) to the workspace, so the gathers of the MP pass and of the
-// shape functions fetch a node with one or two loads instead of six.
+// The node update also writes each node as one 64-byte record
+// (x, y, z, du_x, du_y, du_z, 0, 0) to the workspace: the MP pass fetches a
+// node with three 16-byte loads and the shape functions its position with
+// two, instead of six 8-byte loads from the SoA arrays.  The gathers are
+// limited by the texture addresser (one cache-line lookup per cycle), so the
+// number of load instructions per node is what counts.
 // Tensors near the identity are carried as deviations (F - 1, b^e - 1, dF - 1)
 // so that the float32 form of the mixed-precision mode keeps its accuracy.
 #include "constitutive.h"
@@ -59,8 +62,8 @@ __global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restri
     m[i] = 0.0;
     f[i] = 0.0; f[n + i] = 0.0; f[2 * n + i] = 0.0;
   }
-  packed[2 * i] = make_double4(xs[0], xs[1], xs[2], 0.0);
-  packed[2 * i + 1] = make_double4(u[0], u[1], u[2], 0.0);
+  packed[2 * i] = make_double4(xs[0], xs[1], xs[2], u[0]);
+  packed[2 * i + 1] = make_double4(u[1], u[2], 0.0, 0.0);
 }
 
 __global__ __launch_bounds__(256) void k_pack_nodes(int64_t n, const double* __restrict__ x,
@@ -68,8 +71,8 @@ __global__ __launch_bounds__(256) void k_pack_nodes(int64_t n, const double* __r
                                                     double4* __restrict__ packed) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  packed[2 * i] = make_double4(x[i], x[n + i], x[2 * n + i], 0.0);
-  packed[2 * i + 1] = make_double4(du[i], du[n + i], du[2 * n + i], 0.0);
+  packed[2 * i] = make_double4(x[i], x[n + i], x[2 * n + i], du[i]);
+  packed[2 * i + 1] = make_double4(du[n + i], du[2 * n + i], 0.0, 0.0);
 }
 
 void launch_pack_nodes(const otm_state& st, double4* packed, hipStream_t s) {
@@ -114,74 +117,140 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   for (int i = tid; i <= kMpBlock; i += kMpBlock) row[i] = offsets[min(base + i, n_mp)];
   __syncthreads();
 
-  // phase 1: gather with kGather lanes per MP, software-pipelined: a round
-  // issues its node gathers (whose ids arrived in the previous round), then
-  // the pair data of the next round, then does its arithmetic, so each round
-  // waits for one memory latency instead of two.  Slots past the row end load
-  // pair 0 / node 0 and get weight 0, so all loads are branch-free.
+  // phase 1: gather with kGather lanes per MP in kGather rounds of
+  // kMpBlock / kGather MPs, software-pipelined three deep.  Round r issues the
+  // node gathers of round r + 1, then sums round r, then issues the pair data
+  // (N, grad N) of round r + 2 and the node ids of round r + 3.  Vector loads
+  // complete in issue order, so a wait can only leave younger loads in flight;
+  // with this order every wait is for pair data issued two rounds earlier or
+  // for gathers issued one round earlier, never for the newest HBM loads.
+  // Register sets alternate with the parity of the round.  Slots past a row's
+  // end read pair 0 / node 0 and get weight 0, so all loads are branch-free;
+  // pairs past kSlots * kGather (long rows) are added after the pipeline.
   if (lists_ok && have_nodes) {
     const int lane = tid % kGather;
-    // raw loads of one round (slot k of the row, or pair 0 past its end)
-    int32_t iv[kSlots];
-    double wv[kSlots], d0[kSlots], d1[kSlots], d2[kSlots];
-    bool use[kSlots];
-    auto load_pairs = [&](int r) {
-      const int local = r * (kMpBlock / kGather) + tid / kGather;
-      const int64_t o0 = row[local], o1 = row[local + 1];
+    const int grp = tid / kGather;
+    constexpr int kPer = kMpBlock / kGather;
+    struct Ids { int32_t i[kSlots]; bool use[kSlots]; };
+    // grad N stays in its stored type until it is used, so that no
+    // conversion has to wait for a load in the round that issues it
+    struct Pairs { double w[kSlots]; R g0[kSlots], g1[kSlots], g2[kSlots]; };
+    // a node record as three 16-byte pieces: (x, y), (z, du_x), (du_y, du_z)
+    struct Nodes { double2 a[kSlots], b[kSlots], c[kSlots]; bool use[kSlots]; };
+    const double2* __restrict__ nd2 = reinterpret_cast<const double2*>(nodes);
+    auto slot = [&](int r, int k, bool& use) {
+      const int local = r * kPer + grp;
+      const int64_t q = row[local] + k * kGather + lane;
+      use = q < row[local + 1];
+      return use ? q : (int64_t)0;
+    };
+    auto load_ids = [&](Ids& s, int r) {
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) s.i[k] = idx[slot(r, k, s.use[k])];
+    };
+    auto load_pairs = [&](Pairs& s, int r) {
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
-        const int64_t q = o0 + k * kGather + lane;
-        use[k] = q < o1;
-        // unconditional loads (qq is always a valid pair slot); the selects
-        // come where the values are used, one round later
-        const int64_t qq = use[k] ? q : 0;
-        iv[k] = idx[qq];
-        wv[k] = N[qq];
-        d0[k] = (double)dN[qq];
-        d1[k] = (double)dN[cap + qq];
-        d2[k] = (double)dN[2 * cap + qq];
+        bool use;
+        const int64_t q = slot(r, k, use);
+        s.w[k] = N[q];
+        s.g0[k] = dN[q];
+        s.g1[k] = dN[cap + q];
+        s.g2[k] = dN[2 * cap + q];
       }
     };
-    load_pairs(0);
-    for (int r = 0; r < kGather; ++r) {
-      const int local = r * (kMpBlock / kGather) + tid / kGather;
-      double4 xv[kSlots], uv[kSlots];
-      double wc[kSlots], gc[kSlots][3];
+    auto load_nodes = [&](Nodes& s, const Ids& ids) {
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
-        const int32_t I = use[k] ? iv[k] : 0;  // node 0 stands in (idx[0] is unset without pairs)
-        xv[k] = nodes[2 * (int64_t)I];
-        uv[k] = nodes[2 * (int64_t)I + 1];
-        wc[k] = use[k] ? wv[k] : 0.0;
-        gc[k][0] = use[k] ? d0[k] : 0.0;
-        gc[k][1] = use[k] ? d1[k] : 0.0;
-        gc[k][2] = use[k] ? d2[k] : 0.0;
+        const int32_t I = ids.use[k] ? ids.i[k] : 0;  // idx[0] is unset without pairs
+        s.use[k] = ids.use[k];
+        s.a[k] = nd2[4 * (int64_t)I];
+        s.b[k] = nd2[4 * (int64_t)I + 1];
+        s.c[k] = nd2[4 * (int64_t)I + 2];
       }
-      // unconditional (the last round reloads its own rows) so that the
-      // waits below need not cover a path without these loads
-      load_pairs(r + 1 < kGather ? r + 1 : r);
+    };
+    auto sum_round = [&](int r, const Nodes& nd, const Pairs& pr) {
       double a[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      auto add = [&](double wt, double h0, double h1, double h2, const double4& x4,
-                     const double4& u4) {
-        a[0] += wt * x4.x; a[1] += wt * x4.y; a[2] += wt * x4.z;
-        a[3] += u4.x * h0; a[4] += u4.x * h1; a[5] += u4.x * h2;
-        a[6] += u4.y * h0; a[7] += u4.y * h1; a[8] += u4.y * h2;
-        a[9] += u4.z * h0; a[10] += u4.z * h1; a[11] += u4.z * h2;
-      };
 #pragma unroll
-      for (int k = 0; k < kSlots; ++k) add(wc[k], gc[k][0], gc[k][1], gc[k][2], xv[k], uv[k]);
-      // pairs past kSlots * kGather (long rows), read directly
-      const int64_t o0 = row[local], o1 = row[local + 1];
-      for (int64_t q = o0 + kSlots * kGather + lane; q < o1; q += kGather) {
-        const int32_t J = idx[q];
-        add(N[q], (double)dN[q], (double)dN[cap + q], (double)dN[2 * cap + q],
-            nodes[2 * (int64_t)J], nodes[2 * (int64_t)J + 1]);
+      for (int k = 0; k < kSlots; ++k) {
+        const double wt = nd.use[k] ? pr.w[k] : 0.0;
+        const double h0 = nd.use[k] ? (double)pr.g0[k] : 0.0;
+        const double h1 = nd.use[k] ? (double)pr.g1[k] : 0.0;
+        const double h2 = nd.use[k] ? (double)pr.g2[k] : 0.0;
+        const double x0 = nd.a[k].x, x1 = nd.a[k].y, x2 = nd.b[k].x;
+        const double u0 = nd.b[k].y, u1 = nd.c[k].x, u2 = nd.c[k].y;
+        a[0] += wt * x0; a[1] += wt * x1; a[2] += wt * x2;
+        a[3] += u0 * h0; a[4] += u0 * h1; a[5] += u0 * h2;
+        a[6] += u1 * h0; a[7] += u1 * h1; a[8] += u1 * h2;
+        a[9] += u2 * h0; a[10] += u2 * h1; a[11] += u2 * h2;
       }
 #pragma unroll
       for (int c = 0; c < 12; ++c) a[c] = group_sum<kGather>(a[c]);
       if (lane == 0) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) sums[c][local] = a[c];
+        for (int c = 0; c < 12; ++c) sums[c][r * kPer + grp] = a[c];
+      }
+    };
+    // rounds past the last reload the last round's rows (uniform control flow)
+    auto cl = [](int r) { return r < kGather ? r : kGather - 1; };
+    Ids i0, i1;
+    Pairs p0, p1;
+    Nodes n0, n1;
+    // the prologue issues in the loop's own order (pairs r, ids r + 1,
+    // gathers r, pairs r + 1, ids r + 2), so the waits at the loop head need
+    // not assume an older order
+    load_ids(i0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_pairs(p0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_ids(i1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_nodes(n0, i0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_pairs(p1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_ids(i0, 2);
+    static_assert(kGather % 2 == 0, "rounds are taken in pairs");
+    for (int r = 0; r < kGather; r += 2) {
+      __builtin_amdgcn_sched_barrier(0);
+      load_nodes(n1, i1);             // gathers of round r + 1
+      __builtin_amdgcn_sched_barrier(0);
+      sum_round(r, n0, p0);
+      __builtin_amdgcn_sched_barrier(0);
+      load_pairs(p0, cl(r + 2));
+      load_ids(i1, cl(r + 3));
+      __builtin_amdgcn_sched_barrier(0);
+      load_nodes(n0, i0);             // gathers of round r + 2
+      __builtin_amdgcn_sched_barrier(0);
+      sum_round(r + 1, n1, p1);
+      __builtin_amdgcn_sched_barrier(0);
+      load_pairs(p1, cl(r + 3));
+      load_ids(i0, cl(r + 4));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // long rows: the pairs past kSlots * kGather, summed per group and added
+    // to the row's sums (the same lane wrote them, so no barrier is needed)
+    for (int r = 0; r < kGather; ++r) {
+      const int local = r * kPer + grp;
+      const int64_t o0 = row[local], o1 = row[local + 1];
+      if (o1 - o0 <= kSlots * kGather) continue;  // uniform within the group
+      double a[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int64_t q = o0 + kSlots * kGather + lane; q < o1; q += kGather) {
+        const int32_t J = idx[q];
+        const double wt = N[q];
+        const double h0 = (double)dN[q], h1 = (double)dN[cap + q], h2 = (double)dN[2 * cap + q];
+        const double2 ra = nd2[4 * (int64_t)J], rb = nd2[4 * (int64_t)J + 1];
+        const double2 rc = nd2[4 * (int64_t)J + 2];
+        a[0] += wt * ra.x; a[1] += wt * ra.y; a[2] += wt * rb.x;
+        a[3] += rb.y * h0; a[4] += rb.y * h1; a[5] += rb.y * h2;
+        a[6] += rc.x * h0; a[7] += rc.x * h1; a[8] += rc.x * h2;
+        a[9] += rc.y * h0; a[10] += rc.y * h1; a[11] += rc.y * h2;
+      }
+#pragma unroll
+      for (int c = 0; c < 12; ++c) a[c] = group_sum<kGather>(a[c]);
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sums[c][local] += a[c];
       }
     }
   } else {
