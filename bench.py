@@ -10,7 +10,9 @@ functions and nodal force assembly.
 
 The main line is float64 with atomic assembly; the mixed-precision mode and
 the deterministic (segmented) assembly are timed the same way and reported
-under "variants".  Inputs are resident in HBM before the timed region; the
+under "variants", together with the Taylor rod at the paper's own size
+(27,840 MPs, 2000 steps; eager and graph-replayed) beside the paper's
+per-step times.  Inputs are resident in HBM before the timed region; the
 timed region is bracketed by device synchronisation and HIP events on the
 stream the kernels run on.  Per-phase durations come from events recorded by
 the library between its kernels (otm_step_profiled).
@@ -187,6 +189,59 @@ def roofline_entry(nbytes, ms):
                 frac=round(gbs / HBM_PEAK_GBS, 4))
 
 
+# ------------------------------------------------- the paper's own rod size
+# The paper's Taylor-rod timing table (Sec. 4.1): 2000 steps of 28,423 MPs on
+# Haswell cores, total wall time 2697.26 s on 1 core and 23.78 s on 239 cores
+# (whole parallel step, halo exchange and VTK output included).
+PAPER_ROD_S_PER_STEP = {"1_core": 2697.26 / 2000, "239_cores": 23.78 / 2000}
+
+
+def run_paper_rod(warmup=5, graph_steps=10):
+    """The Taylor rod of Sec. 4.1 at the paper's size (5,959 nodes, 27,840
+    MPs, linear hardening, 227 m/s, dt = 4e-9 s), float64 with atomic
+    assembly and lists rebuilt every step, timed over all 2000 steps of the
+    paper's run: eager otm_step calls, and replays of a HIP graph of
+    ``graph_steps`` captured steps (one launch per replay)."""
+    import torch
+    import otm_workloads as W
+    from paper_2206_08772_amd.sim import Sim
+    w = W.config_by_name("paper_rod")
+    p = W.params_from_workload(w)
+    steps = w.steps
+    out = dict(workload=f"{w.name}: {w.n_nodes} nodes, {w.n_mp} MPs, J2 linear hardening, "
+                        f"dt 4e-9 s, {steps} steps, float64, atomic assembly",
+               steps=steps)
+    for mode in ("eager", "graph"):
+        sim = Sim(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, precision="fp64")
+        sim.init()
+        for _ in range(warmup):
+            sim.step()
+        g = sim.capture(graph_steps) if mode == "graph" else None
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        if g is None:
+            for _ in range(steps):
+                sim.step()
+        else:
+            for _ in range(steps // graph_steps):
+                g.replay()
+        t1.record()
+        torch.cuda.synchronize()
+        sim.check_diag()
+        ms = t0.elapsed_time(t1) / steps
+        out[mode] = dict(ms_per_step=round(ms, 4), value=round(w.n_mp / (ms * 1e-3), 1))
+        del sim, g
+        torch.cuda.empty_cache()
+    best = min(out["eager"]["ms_per_step"], out["graph"]["ms_per_step"]) * 1e-3
+    out["paper_s_per_step"] = {k: round(v, 5) for k, v in PAPER_ROD_S_PER_STEP.items()}
+    out["speedup_vs_paper"] = {k: round(v / best, 1) for k, v in PAPER_ROD_S_PER_STEP.items()}
+    out["note"] = ("paper: 28,423 MPs on Haswell cores, whole parallel step including halo "
+                   "exchange and output; context, not a target")
+    return out
+
+
 # ------------------------------------------------------------ adjoint ratio
 def adjoint_ratio(every=20):
     """Gradient of a rollout loss on the adjoint-rod workload (268k MPs, 200
@@ -257,8 +312,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="taylor_rod")
-    ap.add_argument("--variants", default="mixed,segmented",
-                    help="extra timed variants: mixed, segmented (comma separated, or none)")
+    ap.add_argument("--variants", default="mixed,segmented,paper_rod",
+                    help="extra timed variants: mixed, segmented, paper_rod (comma separated, "
+                         "or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -286,6 +342,9 @@ def main():
     main_run = run_variant(w, "fp64", "atomic", args.steps, args.warmup)
     variants = {}
     for v in [s for s in args.variants.split(",") if s and s != "none"]:
+        if v == "paper_rod":
+            variants[v] = run_paper_rod()
+            continue
         prec = "mixed" if v == "mixed" else "fp64"
         scat = "segmented" if v == "segmented" else "atomic"
         r = run_variant(w, prec, scat, args.steps, args.warmup)

@@ -183,7 +183,7 @@ def jc_params(seed):
 
 def taylor_rod(h, seed, radius=3.2e-3, length=21.12e-3, speed=190.0, steps=100,
                model=MODEL_J2_JC, skin_h=0.0, rebuild_every=1, name="taylor_rod",
-               material=None):
+               material=None, dt=None):
     """Cylinder of radius R and length L (z axis) on a jittered lattice,
     flying at -speed along z into a rigid frictionless wall z = 0.
 
@@ -204,7 +204,8 @@ def taylor_rod(h, seed, radius=3.2e-3, length=21.12e-3, speed=190.0, steps=100,
                             Y0=400e6, H=100e6, **jc_params(seed))
     v0 = np.zeros_like(x)
     v0[:, 2] = -speed
-    dt = 0.1 * h / material.wave_speed
+    if dt is None:
+        dt = 0.1 * h / material.wave_speed
     return Workload(name, h, x, X, x_mp, vol, material.rho0 * vol, v0, material, dt, steps,
                     skin=skin_h * h, rebuild_every=rebuild_every, wall=True)
 
@@ -218,6 +219,10 @@ def config_by_name(name):
                    a 0.1 h skin, 200 steps
     adjoint_rod    ~50k nodes / ~268k MPs, 200 steps (gradient workload)
     small_rod      ~0.8k nodes / ~3.5k MPs rod for long oracle trajectories
+    paper_rod      the Taylor rod of Sec. 4.1 at the paper's size: L = 32.4 mm,
+                   R = 3.2 mm, 227 m/s, linear hardening Y0 = 400 MPa,
+                   H = 100 MPa, dt = 4e-9 s, 2000 steps; h = 0.55 mm gives
+                   5,959 nodes / 27,840 MPs (the paper's mesh: 5,966 / 28,423)
     """
     if name == "elastic_cube":
         return elastic_cube()
@@ -231,6 +236,9 @@ def config_by_name(name):
     if name == "small_rod":
         return taylor_rod(h=0.8e-3, seed=5, radius=3.2e-3, length=10.4e-3, steps=100,
                           name="small_rod")
+    if name == "paper_rod":
+        return taylor_rod(h=0.55e-3, seed=6, radius=3.2e-3, length=32.4e-3, speed=227.0,
+                          steps=2000, model=MODEL_J2_LINEAR, name="paper_rod", dt=4e-9)
     raise KeyError(name)
 
 

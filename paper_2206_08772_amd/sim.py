@@ -202,6 +202,23 @@ class Sim:
         for _ in range(steps):
             self.step(rebuild=((self.n + 1) % rebuild_every == 0))
 
+    def capture(self, steps=1, rebuild=True):
+        """A HIP graph of ``steps`` consecutive otm_step calls on this state
+        (lists rebuilt every step if ``rebuild``).  One replay advances the
+        state by ``steps`` steps with a single launch, which pays off when a
+        step is short enough for kernel launches to dominate.  The graph holds
+        this Sim's device pointers and is valid for its lifetime; the step
+        path records no memset and no host synchronisation.  Take at least one
+        eager step first, so that every kernel is loaded before capture."""
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.graph(g):
+            for _ in range(steps):
+                check(lib().otm_step(C.byref(self.st), C.byref(self.p), self.dt,
+                                     1 if rebuild else 0, self.mode, self.ws.ptr, self.ws.nbytes,
+                                     _ptr(self.diag), _stream()), "otm_step (capture)")
+        return StepGraph(self, g, steps)
+
     def refresh(self, rebuild=True):
         check(lib().otm_refresh(C.byref(self.st), C.byref(self.p), 1 if rebuild else 0, self.mode,
                                 self.ws.ptr, self.ws.nbytes, _ptr(self.diag), _stream()),
@@ -240,3 +257,14 @@ class Sim:
         out["N"] = g(self.N[:P])
         out["dN"] = g(self.dN[:, :P]).T.copy()
         return out
+
+
+class StepGraph:
+    """Replayable capture of a fixed number of steps of one Sim."""
+
+    def __init__(self, sim, graph, steps):
+        self.sim, self.graph, self.steps = sim, graph, steps
+
+    def replay(self):
+        self.graph.replay()
+        self.sim.n += self.steps

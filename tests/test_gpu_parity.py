@@ -252,3 +252,18 @@ def test_linear_hardening_and_neo_hooke_models(cube):
     assert st.epsbar.max() > 0
     bad = {k: v for k, v in errs.items() if not v < FP64_TOL}
     assert not bad, bad
+
+
+def test_paper_rod_20_steps_fp64():
+    """The Taylor rod of Sec. 4.1 at the paper's size (5,959 nodes, 27,840 MPs;
+    227 m/s, linear hardening, dt = 4e-9 s): the first 20 of its 2000 steps,
+    with plastic flow at the wall from the first steps."""
+    w = W.config_by_name("paper_rod")
+    st, p = _oracle_run(w, 20)
+    g, _ = _gpu_run(w, 20)
+    assert st.epsbar.max() > 0.01
+    assert np.array_equal(g["offsets"], st.offsets) and np.array_equal(g["idx"], st.idx)
+    errs = compare(gpu_fields(g, w.x_nodes, w.x_mp, p["T_r"]),
+                   oracle_fields(st, w.x_nodes, w.x_mp, p["T_r"]))
+    bad = {k: v for k, v in errs.items() if not v < FP64_TOL}
+    assert not bad, bad
