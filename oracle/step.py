@@ -20,14 +20,22 @@ done at the end of the previous step (and once at t = 0), so that
   6. LME shape functions                      (Sec. 2.3)
   7. lumped mass and nodal force              (nodal mass and residual
        m_I = sum_p N_Ip m_p,                   equations, no body force,
-       f_I = -sum_p v_p sigma_p grad N_Ip      no tractions, no
-                                               stabilisation term)
+       f_I = -sum_p v_p sigma_p grad N_Ip      no tractions)
+           - eps sum_p N_Ip e_Ip              (stabilisation term, when
+                                               eps_stab > 0)
 
 Readings: du_0 = dt v_0 at the nodes (the central difference needs one
 increment to start); the wall is rigid and frictionless: a node whose
 predicted gap g = (x* - x_bar).n is negative is projected onto the plane and
 its increment set to the projected motion; a node that has left every
 support (zero lumped mass, zero force) keeps its increment.
+
+Stabilisation (Sec. 2.1, stabilised residual and under-integration error):
+e_Ip = [(x_I - x_p) - dF_p (x_I,prev - x_p,prev)] / |x_I,prev - x_p,prev|
+with dF_p the increment of the step just taken, x_p,prev the MP position
+before it and x_I,prev = x_I - du_I.  The paper gives no value for eps; it
+is read as one constant with the units of a force.  At t = 0 there is no
+previous configuration and no term.
 """
 from __future__ import annotations
 
@@ -58,6 +66,10 @@ class State:
     N: np.ndarray
     dN: np.ndarray
     n: int = 0
+    # MP positions before and deformation-gradient increment of the last
+    # MP update (None before the first step)
+    xp_prev: np.ndarray = None
+    dF: np.ndarray = None
 
     def copy(self):
         return State(**{k: (v.copy() if isinstance(v, np.ndarray) else v)
@@ -76,6 +88,9 @@ def assemble(st, p):
                                  minlength=n_nodes)
     # f_I,i = - sum_p v_p sigma_p,ij dN_Ip,j
     contrib = -st.vol[mp_of_pair, None] * np.einsum("qij,qj->qi", st.sigma[mp_of_pair], st.dN)
+    eps = p.get("eps_stab", 0.0)
+    if eps != 0.0 and st.xp_prev is not None:
+        contrib = contrib - eps * st.N[:, None] * underintegration_error(st, mp_of_pair)
     f = np.zeros((n_nodes, 3), dtype=contrib.dtype)
     for i in range(3):
         f[:, i] = np.bincount(st.idx, weights=contrib[:, i].real, minlength=n_nodes)
@@ -83,6 +98,17 @@ def assemble(st, p):
             f[:, i] = f[:, i] + 1j * np.bincount(st.idx, weights=contrib[:, i].imag,
                                                  minlength=n_nodes)
     st.m, st.f = m, f
+
+
+def underintegration_error(st, mp_of_pair):
+    """e_Ip per pair (stabilisation term, Sec. 2.1): the change of the pair's
+    relative position not explained by the MP's deformation-gradient
+    increment, over the pair's previous distance."""
+    d = st.x[st.idx] - st.xp[mp_of_pair]
+    d_prev = (st.x - st.du)[st.idx] - st.xp_prev[mp_of_pair]
+    mapped = np.einsum("qij,qj->qi", st.dF[mp_of_pair], d_prev)
+    dist = np.sqrt((d_prev * d_prev).sum(axis=1))
+    return (d - mapped) / dist[:, None]
 
 
 def node_update(st, p):
@@ -123,6 +149,7 @@ def mp_update(st, p):
         raise FloatingPointError("inverted material point (det dF <= 0) at "
                                  f"{int(np.nonzero(J_dF.real <= 0)[0][0])}")
     st.vol = J_dF * st.vol
+    st.xp_prev, st.dF = st.xp, dF
     st.xp = xp
     J_new = material.det3(F_new)
     if p["model"] == material.NEOHOOKE:
