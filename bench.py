@@ -10,7 +10,8 @@ functions and nodal force assembly.
 
 The main line is float64 with atomic assembly; the mixed-precision mode and
 the deterministic (segmented) assembly are timed the same way and reported
-under "variants", together with the Taylor rod at the paper's own size
+under "variants", as is the step with the stabilisation term (eps = mu h^2),
+together with the Taylor rod at the paper's own size
 (27,840 MPs, 2000 steps; eager and graph-replayed) beside the paper's
 per-step times.  Inputs are resident in HBM before the timed region; the
 timed region is bracketed by device synchronisation and HIP events on the
@@ -119,14 +120,14 @@ def hip_runtime():
     return rt
 
 
-def run_variant(w, precision, scatter, steps, warmup):
+def run_variant(w, precision, scatter, steps, warmup, **over):
     import ctypes as C
     import torch
     import otm_workloads as W
     from paper_2206_08772_amd import _lib
     from paper_2206_08772_amd.sim import Sim, _ptr, _stream
 
-    p = W.params_from_workload(w)
+    p = W.params_from_workload(w, **over)
     sim = Sim(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, precision=precision,
               scatter=scatter)
     sim.init()
@@ -312,9 +313,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="taylor_rod")
-    ap.add_argument("--variants", default="mixed,segmented,paper_rod",
-                    help="extra timed variants: mixed, segmented, paper_rod (comma separated, "
-                         "or none)")
+    ap.add_argument("--variants", default="mixed,segmented,stabilised,paper_rod",
+                    help="extra timed variants: mixed, segmented, stabilised, paper_rod "
+                         "(comma separated, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -347,12 +348,17 @@ def main():
             continue
         prec = "mixed" if v == "mixed" else "fp64"
         scat = "segmented" if v == "segmented" else "atomic"
-        r = run_variant(w, prec, scat, args.steps, args.warmup)
+        over = {}
+        if v == "stabilised":       # the stabilisation term with eps = mu h^2
+            over["eps_stab"] = w.material.E / (2 * (1 + w.material.nu)) * w.h ** 2
+        r = run_variant(w, prec, scat, args.steps, args.warmup, **over)
         pm = dict(r["phase_ms"])
         if scat == "segmented":      # markers 4..6: influence lists, then the gather
             pm["influence_lists"] = pm.pop("assembly")
         variants[v] = dict(value=round(r["value"], 1), ms_per_step=round(r["ms_per_step"], 4),
                            phase_ms={k: round(x, 4) for k, x in pm.items()})
+        if over:
+            variants[v]["eps_stab"] = over["eps_stab"]
         if prec == "mixed":
             nb = mp_pass_bytes(w.n_mp, w.n_nodes, r["pairs"], "mixed", w.material.model)
             variants[v]["mp_pass_roofline"] = roofline_entry(nb, r["phase_ms"]["mp_update"])

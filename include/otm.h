@@ -93,7 +93,14 @@ typedef struct otm_params {
   double rm_tol;          /* return-map relative step / bracket tolerance */
   double wall_x[3];       /* a point of the wall plane */
   double wall_n[3];       /* unit normal of the wall, pointing into the body */
-  double eps_stab;        /* stabilisation penalty: must be 0 */
+  double eps_stab;        /* stabilisation penalty eps >= 0, a force (0: off).
+                             With eps > 0, otm_step adds -eps sum_p N_Ip e_Ip
+                             to f (Sec. 2.1, stabilised residual) with
+                             e_Ip = [(x_I - x_p) - dF_p (x_I,prev - x_p,prev)]
+                             / |x_I,prev - x_p,prev|, x_I,prev = x_I - du_I, and
+                             needs st->xp_prev and st->dFm1; otm_init and
+                             otm_refresh (no previous configuration) add no
+                             term; otm_step_adjoint rejects eps > 0 */
   double body_force[3];   /* specific body force: must be 0 */
 } otm_params;
 
@@ -123,6 +130,11 @@ typedef struct otm_state {
   int32_t* nbr_idx;       /* [pair_capacity] */
   double* N;              /* [pair_capacity] */
   void* dN;               /* [3][pair_capacity] (double / float) */
+  /* stabilisation history, written by otm_step's MP update when
+     params.eps_stab > 0 (may be NULL otherwise) */
+  double* xp_prev;        /* [3][n_mp] MP positions before the last MP update */
+  double* dFm1;           /* [9][n_mp] dF - 1 of the last MP update (float64 in
+                             both precisions), row-major per MP */
 } otm_state;
 
 /* Device-side failure record (lives in device memory). */
@@ -279,7 +291,8 @@ size_t otm_adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp);
  * the Hencky stress and of the exponential map and the implicit derivative
  * of the scalar return equation; wall contact and plastic onset are
  * differentiated on their active branch.  Supports longer than 48 nodes are
- * reported as OTM_ERR_SUPPORT in diag.
+ * reported as OTM_ERR_SUPPORT in diag.  The stabilisation term has no
+ * adjoint: p->eps_stab > 0 returns OTM_ERR_ARG.
  */
 otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_params* p,
                             double dt, const double* mass, otm_state_bar* bar_next,

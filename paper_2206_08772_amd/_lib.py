@@ -50,7 +50,7 @@ class State(C.Structure):
         ("Fd", C.c_void_p), ("bed", C.c_void_p), ("epsbar", C.c_void_p), ("T", C.c_void_p),
         ("sigma", C.c_void_p),
         ("nbr_offsets", C.c_void_p), ("nbr_idx", C.c_void_p), ("N", C.c_void_p),
-        ("dN", C.c_void_p),
+        ("dN", C.c_void_p), ("xp_prev", C.c_void_p), ("dFm1", C.c_void_p),
     ]
 
 

@@ -87,7 +87,7 @@ static otm_status check_params(const otm_params* p) {
   if (!(p->r_list > 0) || !(p->cell_size >= p->r_list) || !(p->beta > 0)) return OTM_ERR_ARG;
   if (!(p->lme_tol > 0) || p->lme_max_iter < 1 || p->rm_max_iter < 1) return OTM_ERR_ARG;
   if (!(p->E > 0) || !(p->nu > -1.0 && p->nu < 0.5) || !(p->rho0 > 0)) return OTM_ERR_ARG;
-  if (p->eps_stab != 0.0) return OTM_ERR_ARG;
+  if (!(p->eps_stab >= 0.0) || !isfinite(p->eps_stab)) return OTM_ERR_ARG;
   if (p->body_force[0] != 0.0 || p->body_force[1] != 0.0 || p->body_force[2] != 0.0)
     return OTM_ERR_ARG;
   if (p->model == OTM_J2_JC && !(p->T_m > p->T_r && p->Cp > 0 && p->eps_dot0 > 0))
@@ -125,10 +125,13 @@ static void mark(hipEvent_t* ev, int k, hipStream_t s) {
 }
 
 // search (optional) + shape functions + mass/force assembly
-// (packed: the node records in the workspace are current)
+// (packed: the node records in the workspace are current; stab: add the
+// stabilisation term, which needs the history the MP update just wrote)
 static void refresh_impl(otm_state& st, const otm_params& p, bool rebuild, int32_t mode,
                          const Workspace& w, otm_diag* diag, hipStream_t s,
-                         hipEvent_t* ev = nullptr, bool packed = false) {
+                         hipEvent_t* ev = nullptr, bool packed = false, bool stab = false) {
+  const Stab sb = stab ? Stab{p.eps_stab, w.nodes, st.xp, st.xp_prev, st.dFm1}
+                       : Stab{0.0, nullptr, nullptr, nullptr, nullptr};
   if (!packed) launch_pack_nodes(st, w.nodes, s);
   if (rebuild)
     launch_search(st.n_nodes, st.x, st.n_mp, st.xp, p.r_list, p.cell_size, st.pair_capacity,
@@ -139,11 +142,11 @@ static void refresh_impl(otm_state& st, const otm_params& p, bool rebuild, int32
              s);
   mark(ev, 4, s);
   if (mode == OTM_SCATTER_ATOMIC) {
-    launch_assemble_atomic(st, s);
+    launch_assemble_atomic(st, sb, s);
   } else {
     if (rebuild) launch_influence_lists(st, w, s);
     mark(ev, 5, s);
-    launch_scatter_segmented(st, w, s);
+    launch_scatter_segmented(st, w, sb, s);
   }
   mark(ev, 6, s);
 }
@@ -277,6 +280,8 @@ static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32
   if (scatter_mode != OTM_SCATTER_ATOMIC && scatter_mode != OTM_SCATTER_SEGMENTED)
     return OTM_ERR_ARG;
   if (!dev_ok(diag, 8)) return OTM_ERR_ARG;
+  const bool stab = p->eps_stab > 0.0;
+  if (stab && (!dev_ok(st->xp_prev, 8) || !dev_ok(st->dFm1, 8))) return OTM_ERR_ARG;
   Workspace w;
   if (check_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &w) != OTM_OK)
     return OTM_ERR_ARG;
@@ -285,7 +290,7 @@ static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32
   mark(ev, 1, s);
   launch_mp_update(*st, *p, dt, w.nodes, diag, s);
   mark(ev, 2, s);
-  refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true);
+  refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true, stab);
   return hip_status();
 }
 
@@ -331,6 +336,7 @@ otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_p
   otm_status e;
   if ((e = check_params(p)) != OTM_OK) return e;
   if (p->model == OTM_NEOHOOKE) return OTM_ERR_ARG;  // adjoint covers the J2 models
+  if (p->eps_stab != 0.0) return OTM_ERR_ARG;        // no adjoint of the stabilisation
   if (!tape_ok(tn) || !tape_ok(tn1) || !bar_ok(bar_next) || !bar_ok(bar)) return OTM_ERR_ARG;
   if (tn->n_nodes != tn1->n_nodes || tn->n_mp != tn1->n_mp) return OTM_ERR_ARG;
   if (!(dt > 0) || !dev_ok(mass, 8) || !dev_ok(theta_bar, 8) || !dev_ok(diag, 8))

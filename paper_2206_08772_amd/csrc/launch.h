@@ -61,14 +61,16 @@ void launch_search(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const d
                    int32_t* nbr_idx, const Workspace& w, otm_diag* diag, hipStream_t s);
 
 // LME shape functions (float64 Newton; dN stored per precision).
-// ``packed`` (nullable): node records (x, y, z, 0) at even indices.
+// ``packed`` (nullable): node records (x, y, z, du_x) at even indices.
 void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const double* x_mp,
                 const int64_t* nbr_offsets, const int32_t* nbr_idx, int64_t pair_capacity,
                 double beta, double tol, int32_t max_iter, double* lam, double* N, void* dN,
                 int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s);
 
 // Nodes and material points.
-// Node records: packed[2 I] = (x, y, z, 0), packed[2 I + 1] = (du, 0).
+// Node records: packed[2 I] = (x, y, z, du_x), packed[2 I + 1] = (du_y, du_z, 0, 0).
+// The MP update also writes the stabilisation history (st.xp_prev, st.dFm1)
+// when p.eps_stab > 0.
 void launch_node_update(const otm_state& st, const otm_params& p, double dt, bool zero_mf,
                         double4* packed, otm_diag* diag, hipStream_t s);
 void launch_pack_nodes(const otm_state& st, double4* packed, hipStream_t s);
@@ -80,11 +82,23 @@ void launch_zero(double* a, int64_t n, hipStream_t s);
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_i64(int64_t* a, int64_t n, int64_t v, hipStream_t s);
 
+// Inputs of the stabilisation term -eps sum_p N_Ip e_Ip of the nodal force
+// (eps == 0: no term): the node records of this step, the MP positions, and
+// the MP positions and dF - 1 before / of the MP update of this step.
+struct Stab {
+  double eps;
+  const double4* nodes;
+  const double* xp;
+  const double* xp_prev;
+  const double* dFm1;
+};
+
 // Segmented (deterministic) assembly.
 void launch_influence_lists(const otm_state& st, const Workspace& w, hipStream_t s);
-void launch_scatter_segmented(const otm_state& st, const Workspace& w, hipStream_t s);
+void launch_scatter_segmented(const otm_state& st, const Workspace& w, const Stab& sb,
+                              hipStream_t s);
 // Atomic assembly (m and f must be zero beforehand).
-void launch_assemble_atomic(const otm_state& st, hipStream_t s);
+void launch_assemble_atomic(const otm_state& st, const Stab& sb, hipStream_t s);
 
 void launch_diag_reset(otm_diag* d, hipStream_t s);
 

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     int64_t cap, const double* __restrict__ N, const R* __restrict__ dN,
     double* __restrict__ xp, double* __restrict__ vol, R* __restrict__ Fd, R* __restrict__ bed,
     double* __restrict__ epsbar, double* __restrict__ T, R* __restrict__ sigma, Mat<R> M,
-    otm_diag* diag) {
+    double* __restrict__ xp_prev, double* __restrict__ dFm1, otm_diag* diag) {
   // phase 1: the 12 gathered sums of each MP; phase 2: the MP's eigenvectors,
   // logarithmic strains and J parked over the return-map solve (each lane
   // only touches its own column)
@@ -271,6 +271,14 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   const double detdF = 1.0 + det_one_plus_minus_one(H);
   if (!(detdF > 0.0)) diag_fail(diag, OTM_ERR_INVERTED, (uint64_t)p);
   vol[p] = detdF * vol[p];
+  if (dFm1 != nullptr) {  // history of the stabilisation term
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xp_prev[c * n_mp + p] = xp[c * n_mp + p];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dFm1[(3 * i + j) * n_mp + p] = H.a[i][j];
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) xp[c * n_mp + p] = xnew[c];
 
@@ -403,14 +411,16 @@ void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
   const int64_t n = st.n_mp;
   if (n <= 0) return;
   const unsigned nb = (unsigned)((n + kMpBlock - 1) / kMpBlock);
+  double* hist_x = p.eps_stab > 0.0 ? st.xp_prev : nullptr;
+  double* hist_f = p.eps_stab > 0.0 ? st.dFm1 : nullptr;
   if (st.precision == OTM_FP64)
     k_mp_update<double><<<nb, kMpBlock, 0, s>>>(
         packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const double*)st.dN, st.xp, st.vol, (double*)st.Fd, (double*)st.bed, st.epsbar, st.T,
-        (double*)st.sigma, make_mat<double>(p, dt), diag);
+        (double*)st.sigma, make_mat<double>(p, dt), hist_x, hist_f, diag);
   else
     k_mp_update<float><<<nb, kMpBlock, 0, s>>>(
         packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const float*)st.dN, st.xp, st.vol, (float*)st.Fd, (float*)st.bed, st.epsbar, st.T,
-        (float*)st.sigma, make_mat<float>(p, dt), diag);
+        (float*)st.sigma, make_mat<float>(p, dt), hist_x, hist_f, diag);
 }
 
 // ------------------------------------------------------------------- t = 0

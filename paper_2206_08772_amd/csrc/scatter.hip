@@ -9,6 +9,47 @@
 
 namespace otm {
 
+// Stabilisation term of the nodal force (Sec. 2.1, stabilised residual):
+// pair (p, I) adds -eps N_Ip e_Ip with the under-integration error
+//   e_Ip = [(x_I - x_p) - (1 + H_p)(x_I,prev - x_p,prev)] / |x_I,prev - x_p,prev|,
+// H_p = dF_p - 1 of this step's MP update, x_I,prev = x_I - du_I.  Float64 in
+// both precisions (positions and their differences).
+struct StabMP {
+  double x[3], xq[3], H[9];
+};
+
+OTM_DEV void stab_load(const Stab& sb, int64_t n_mp, int64_t p, StabMP& m) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    m.x[c] = sb.xp[c * n_mp + p];
+    m.xq[c] = sb.xp_prev[c * n_mp + p];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) m.H[k] = sb.dFm1[k * n_mp + p];
+}
+
+OTM_DEV void stab_add(const Stab& sb, const StabMP& m, int32_t I, double Nq, double& c1,
+                      double& c2, double& c3) {
+  const double2* __restrict__ nd = reinterpret_cast<const double2*>(sb.nodes);
+  const double2 ra = nd[4 * (int64_t)I], rb = nd[4 * (int64_t)I + 1];
+  const double2 rc = nd[4 * (int64_t)I + 2];
+  const double xi[3] = {ra.x, ra.y, rb.x}, ui[3] = {rb.y, rc.x, rc.y};
+  double d[3], dp[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d[k] = xi[k] - m.x[k];
+    dp[k] = (xi[k] - ui[k]) - m.xq[k];
+  }
+  const double w = -sb.eps * Nq / sqrt((dp[0] * dp[0] + dp[1] * dp[1]) + dp[2] * dp[2]);
+  double e[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    e[i] = d[i] - (dp[i] + (m.H[3 * i] * dp[0] + m.H[3 * i + 1] * dp[1] + m.H[3 * i + 2] * dp[2]));
+  c1 += w * e[0];
+  c2 += w * e[1];
+  c3 += w * e[2];
+}
+
 // Counting sort of the pairs by node.  A workgroup takes 512 consecutive MPs
 // (rows walked by 8 lanes each), counts its pairs per node in an LDS hash
 // table, and adds one global atomic per distinct node; the fill repeats the
@@ -171,12 +212,13 @@ void launch_influence_lists(const otm_state& st, const Workspace& w, hipStream_t
 constexpr int kScLanes = 8;
 constexpr int kScMPs = 256 / kScLanes;
 
-template <typename R>
+template <typename R, bool STAB>
 __global__ __launch_bounds__(256) void k_seg_contrib(
     int64_t n_mp, int64_t cap, const int64_t* __restrict__ offsets,
-    const double* __restrict__ N, const R* __restrict__ dN, const double* __restrict__ vol,
-    const double* __restrict__ mass, const R* __restrict__ sigma,
-    const int32_t* __restrict__ pos_of, double4* __restrict__ contrib) {
+    const int32_t* __restrict__ idx, const double* __restrict__ N, const R* __restrict__ dN,
+    const double* __restrict__ vol, const double* __restrict__ mass,
+    const R* __restrict__ sigma, const int32_t* __restrict__ pos_of,
+    double4* __restrict__ contrib, Stab sb) {
   const int64_t p = (int64_t)xcd_block() * kScMPs + threadIdx.x / kScLanes;
   const int lane = threadIdx.x % kScLanes;
   if (p >= n_mp) return;
@@ -185,11 +227,16 @@ __global__ __launch_bounds__(256) void k_seg_contrib(
   const R v = (R)vol[p];
   const R s0 = sigma[p], s1 = sigma[n_mp + p], s2 = sigma[2 * n_mp + p];
   const R s3 = sigma[3 * n_mp + p], s4 = sigma[4 * n_mp + p], s5 = sigma[5 * n_mp + p];
+  StabMP sm;
+  if constexpr (STAB) stab_load(sb, n_mp, p, sm);
   for (int64_t q = offsets[p] + lane; q < offsets[p + 1]; q += kScLanes) {
     const R g0 = dN[q], g1 = dN[cap + q], g2 = dN[2 * cap + q];
-    contrib[pos_of[q]] = make_double4(N[q] * mp, (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2)),
-                                      (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2)),
-                                      (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2)));
+    const double Nq = N[q];
+    double c1 = (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2));
+    double c2 = (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2));
+    double c3 = (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2));
+    if constexpr (STAB) stab_add(sb, sm, idx[q], Nq, c1, c2, c3);
+    contrib[pos_of[q]] = make_double4(Nq * mp, c1, c2, c3);
   }
 }
 
@@ -222,19 +269,25 @@ __global__ __launch_bounds__(256) void k_seg_gather(int64_t n_nodes, int64_t n_m
   }
 }
 
-void launch_scatter_segmented(const otm_state& st, const Workspace& w, hipStream_t s) {
+template <typename R, bool STAB>
+static void seg_contrib(const otm_state& st, const Workspace& w, const Stab& sb, hipStream_t s) {
+  const int64_t nm = st.n_mp;
+  const unsigned nb = (unsigned)((nm + kScMPs - 1) / kScMPs);
+  k_seg_contrib<R, STAB><<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.nbr_idx,
+                                            st.N, (const R*)st.dN, st.vol, st.mass,
+                                            (const R*)st.sigma, w.tr_pos, w.contrib, sb);
+}
+
+void launch_scatter_segmented(const otm_state& st, const Workspace& w, const Stab& sb,
+                              hipStream_t s) {
   const int64_t nn = st.n_nodes, nm = st.n_mp;
   if (nn <= 0) return;
   if (nm > 0) {
-    const unsigned nb = (unsigned)((nm + kScMPs - 1) / kScMPs);
+    const bool stab = sb.eps > 0.0;
     if (st.precision == OTM_FP64)
-      k_seg_contrib<double><<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.N,
-                                               (const double*)st.dN, st.vol, st.mass,
-                                               (const double*)st.sigma, w.tr_pos, w.contrib);
+      stab ? seg_contrib<double, true>(st, w, sb, s) : seg_contrib<double, false>(st, w, sb, s);
     else
-      k_seg_contrib<float><<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.N,
-                                              (const float*)st.dN, st.vol, st.mass,
-                                              (const float*)st.sigma, w.tr_pos, w.contrib);
+      stab ? seg_contrib<float, true>(st, w, sb, s) : seg_contrib<float, false>(st, w, sb, s);
   }
   const unsigned nb = (unsigned)((nn + (256 / kSegLanes) - 1) / (256 / kSegLanes));
   k_seg_gather<<<nb, 256, 0, s>>>(nn, nm, st.pair_capacity, st.nbr_offsets, w.tr_start,
@@ -255,12 +308,12 @@ constexpr int kAsmLanes = 8;
 constexpr int kAsmSlotBits = 10;
 constexpr int kAsmSlots = 1 << kAsmSlotBits;
 
-template <typename R>
+template <typename R, bool STAB>
 __global__ __launch_bounds__(256) void k_assemble_atomic(
     int64_t n_nodes, int64_t n_mp, int64_t cap, const int64_t* __restrict__ offsets,
     const int32_t* __restrict__ idx, const double* __restrict__ N, const R* __restrict__ dN,
     const double* __restrict__ vol, const double* __restrict__ mass, const R* __restrict__ sigma,
-    double* __restrict__ m, double* __restrict__ f) {
+    double* __restrict__ m, double* __restrict__ f, Stab sb) {
   __shared__ int32_t keys[kAsmSlots];
   __shared__ double vals[4][kAsmSlots];
   const int tid = threadIdx.x;
@@ -281,6 +334,8 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
     const R s3 = sigma[3 * n_mp + p], s4 = sigma[4 * n_mp + p], s5 = sigma[5 * n_mp + p];
     const int64_t o0 = offsets[p], o1 = offsets[p + 1];
     if (o1 == o0) continue;
+    StabMP sm;
+    if constexpr (STAB) stab_load(sb, n_mp, p, sm);
     auto insert = [&](int32_t I, double c0, double c1, double c2, double c3) {
       uint32_t h = ((uint32_t)I * 2654435761u) >> (32 - kAsmSlotBits);
       int slot = -1;
@@ -304,10 +359,12 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
     auto contrib = [&](int64_t q, int32_t& I, double& c0, double& c1, double& c2, double& c3) {
       I = idx[q];
       const R g0 = dN[q], g1 = dN[cap + q], g2 = dN[2 * cap + q];
-      c0 = N[q] * mp;
+      const double Nq = N[q];
+      c0 = Nq * mp;
       c1 = (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2));
       c2 = (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2));
       c3 = (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2));
+      if constexpr (STAB) stab_add(sb, sm, I, Nq, c1, c2, c3);
     };
     const int K = (int)(o1 - o0);
     auto slot = [&](int t) { return o0 + t; };
@@ -341,20 +398,23 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
   }
 }
 
-void launch_assemble_atomic(const otm_state& st, hipStream_t s) {
+template <typename R, bool STAB>
+static void assemble_atomic(const otm_state& st, const Stab& sb, hipStream_t s) {
   const int64_t nm = st.n_mp;
-  if (nm <= 0) return;
   const unsigned nb = (unsigned)((nm + kAsmMPs - 1) / kAsmMPs);
-  if (st.precision == OTM_FP64)
-    k_assemble_atomic<double><<<nb, 256, 0, s>>>(st.n_nodes, nm, st.pair_capacity,
-                                                 st.nbr_offsets, st.nbr_idx, st.N,
-                                                 (const double*)st.dN, st.vol, st.mass,
-                                                 (const double*)st.sigma, st.m, st.f);
-  else
-    k_assemble_atomic<float><<<nb, 256, 0, s>>>(st.n_nodes, nm, st.pair_capacity,
+  k_assemble_atomic<R, STAB><<<nb, 256, 0, s>>>(st.n_nodes, nm, st.pair_capacity,
                                                 st.nbr_offsets, st.nbr_idx, st.N,
-                                                (const float*)st.dN, st.vol, st.mass,
-                                                (const float*)st.sigma, st.m, st.f);
+                                                (const R*)st.dN, st.vol, st.mass,
+                                                (const R*)st.sigma, st.m, st.f, sb);
+}
+
+void launch_assemble_atomic(const otm_state& st, const Stab& sb, hipStream_t s) {
+  if (st.n_mp <= 0) return;
+  const bool stab = sb.eps > 0.0;
+  if (st.precision == OTM_FP64)
+    stab ? assemble_atomic<double, true>(st, sb, s) : assemble_atomic<double, false>(st, sb, s);
+  else
+    stab ? assemble_atomic<float, true>(st, sb, s) : assemble_atomic<float, false>(st, sb, s);
 }
 
 }  // namespace otm

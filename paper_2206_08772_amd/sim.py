@@ -47,7 +47,7 @@ def make_params(p):
         q.wall_x[i] = float(wx[i])
         q.wall_n[i] = float(wn[i])
         q.body_force[i] = 0.0
-    q.eps_stab = 0.0
+    q.eps_stab = float(p.get("eps_stab", 0.0))
     return q
 
 
@@ -149,6 +149,10 @@ class Sim:
         self.epsbar = torch.zeros(nm, dtype=torch.float64, device=dev)
         self.T = torch.zeros(nm, dtype=torch.float64, device=dev)
         self.sigma = torch.zeros(6, nm, dtype=rdt, device=dev)
+        # history of the stabilisation term (written by each step's MP update)
+        self.stab = float(params.get("eps_stab", 0.0)) > 0.0
+        self.xp_prev = torch.zeros(3, nm, dtype=torch.float64, device=dev) if self.stab else None
+        self.dFm1 = torch.zeros(9, nm, dtype=torch.float64, device=dev) if self.stab else None
         self.offsets = torch.zeros(nm + 1, dtype=torch.int64, device=dev)
         self.v0 = soa(v0_nodes, dev)
         if pair_capacity is None:
@@ -184,6 +188,8 @@ class Sim:
         s.nbr_idx = _ptr(self.idx).value
         s.N = _ptr(self.N).value
         s.dN = _ptr(self.dN).value
+        s.xp_prev = _ptr(self.xp_prev).value if self.stab else None
+        s.dFm1 = _ptr(self.dFm1).value if self.stab else None
 
     # ---------------------------------------------------------------- calls
     def init(self):
