@@ -137,12 +137,16 @@ static void refresh_impl(otm_state& st, const otm_params& p, bool rebuild, int32
     launch_search(st.n_nodes, st.x, st.n_mp, st.xp, p.r_list, p.cell_size, st.pair_capacity,
                   st.nbr_offsets, st.nbr_idx, w, diag, s);
   mark(ev, 3, s);
+  // the atomic assembly without the stabilisation term runs inside the
+  // shape-function kernel, on N and grad N while they are in registers
+  const bool fuse = mode == OTM_SCATTER_ATOMIC && !stab;
+  const AsmIn fused{st.vol, st.mass, st.sigma, st.m, st.f, st.n_nodes};
   launch_lme(st.n_nodes, st.x, st.n_mp, st.xp, st.nbr_offsets, st.nbr_idx, st.pair_capacity,
              p.beta, p.lme_tol, p.lme_max_iter, st.lam, st.N, st.dN, st.precision, w.nodes, diag,
-             s);
+             s, fuse ? &fused : nullptr);
   mark(ev, 4, s);
   if (mode == OTM_SCATTER_ATOMIC) {
-    launch_assemble_atomic(st, sb, s);
+    if (!fuse) launch_assemble_atomic(st, sb, s);
   } else {
     if (rebuild) launch_influence_lists(st, w, s);
     mark(ev, 5, s);

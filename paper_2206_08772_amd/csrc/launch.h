@@ -60,12 +60,26 @@ void launch_search(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const d
                    double r_list, double cell_size, int64_t pair_capacity, int64_t* nbr_offsets,
                    int32_t* nbr_idx, const Workspace& w, otm_diag* diag, hipStream_t s);
 
+// Inputs of the atomic assembly when it is fused into the shape-function
+// kernel (m and f must be zero beforehand; sigma is double or float per the
+// precision).
+struct AsmIn {
+  const double* vol;
+  const double* mass;
+  const void* sigma;
+  double* m;
+  double* f;
+  int64_t n_nodes;
+};
+
 // LME shape functions (float64 Newton; dN stored per precision).
 // ``packed`` (nullable): node records (x, y, z, du_x) at even indices.
+// ``fused`` (nullable): also assemble m and f from the new N and grad N.
 void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const double* x_mp,
                 const int64_t* nbr_offsets, const int32_t* nbr_idx, int64_t pair_capacity,
                 double beta, double tol, int32_t max_iter, double* lam, double* N, void* dN,
-                int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s);
+                int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s,
+                const AsmIn* fused = nullptr);
 
 // Nodes and material points.
 // Node records: packed[2 I] = (x, y, z, du_x), packed[2 I + 1] = (du_y, du_z, 0, 0).

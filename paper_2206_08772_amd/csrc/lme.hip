@@ -146,12 +146,49 @@ OTM_DEV void store_dn(DN* dN, int64_t cap, int64_t q, const double g[3]) {
   dN[2 * cap + q] = (DN)g[2];
 }
 
-template <int G, int PPL, bool CACHED, typename DN>
+// What happens to each finished pair besides storing N and grad N.
+struct NoSink {
+  OTM_DEV void begin(int64_t) {}
+  OTM_DEV void operator()(int64_t, double, const double*) {}
+};
+
+// Fused nodal assembly (nodal mass and residual equations, Sec. 2.1): the
+// pair's m and f contributions, with the same arithmetic as the standalone
+// assembly kernel (grad N rounded to its stored type R first), go into the
+// workgroup's node table.  begin() loads the MP's mass, volume and stress
+// once the Newton solve is done.
+template <typename R>
+struct AsmSink {
+  NodeTable* t;
+  const int32_t* idx;
+  const double* vol;
+  const double* mass;
+  const R* sigma;
+  double* m;
+  double* f;
+  int64_t n_nodes, n_mp;
+  double mp;
+  R v, s0, s1, s2, s3, s4, s5;
+  OTM_DEV void begin(int64_t p) {
+    mp = mass[p];
+    v = (R)vol[p];
+    s0 = sigma[p]; s1 = sigma[n_mp + p]; s2 = sigma[2 * n_mp + p];
+    s3 = sigma[3 * n_mp + p]; s4 = sigma[4 * n_mp + p]; s5 = sigma[5 * n_mp + p];
+  }
+  OTM_DEV void operator()(int64_t q, double Nq, const double g[3]) {
+    const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
+    table_insert(*t, idx[q], Nq * mp, (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2)),
+                 (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2)),
+                 (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2)), m, f, n_nodes);
+  }
+};
+
+template <int G, int PPL, bool CACHED, typename DN, class Sink>
 OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, const double* __restrict__ xp,
                        const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
                        int64_t cap, double beta, double tol, int max_iter,
                        double* __restrict__ lam_io, double* __restrict__ Nout,
-                       DN* __restrict__ dN, otm_diag* diag) {
+                       DN* __restrict__ dN, otm_diag* diag, Sink& sink) {
   const int64_t off = offsets[p];
   const int K = (int)(offsets[p + 1] - off);
   const double px = xp[p], py = xp[n_mp + p], pz = xp[2 * n_mp + p];
@@ -214,6 +251,7 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
   double Mi[6], det;
   sym_inv(ev.J, Mi, det);
   const double iz = 1.0 / ev.Z;
+  sink.begin(p);
   auto finish = [&](int q, double e, double dx, double dy, double dz) {
     const double Nq = e * iz;
     const double d3[3] = {dx, dy, dz};
@@ -222,6 +260,7 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
     g[0] *= -Nq; g[1] *= -Nq; g[2] *= -Nq;
     Nout[off + q] = Nq;
     store_dn<DN>(dN, cap, off + q, g);
+    sink(off + q, Nq, g);
   };
   if constexpr (CACHED) {
 #pragma unroll
@@ -254,21 +293,86 @@ __global__ __launch_bounds__(256) void k_lme(NodeSrc ns, int64_t n_mp, const dou
   if (p >= n_mp) return;  // whole group leaves together
   if (offsets[n_mp] > cap) return;  // lists were not written (capacity)
   const int K = (int)(offsets[p + 1] - offsets[p]);
+  NoSink sink;
   if (K <= G * PPL)
     lme_point<G, PPL, true, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
-                                max_iter, lam, N, dN, diag);
+                                max_iter, lam, N, dN, diag, sink);
   else
     lme_point<G, PPL, false, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
-                                 max_iter, lam, N, dN, diag);
+                                 max_iter, lam, N, dN, diag, sink);
+}
+
+// Shape functions with the atomic nodal assembly fused in.  A fixed grid of
+// kLmeAsmBlocks workgroups (two per CU at this kernel's register use) each
+// take a contiguous range of MPs in rounds of 256 / G; every
+// kLmeAsmFlushRounds rounds (512 MPs, spatially compact) the node table is
+// flushed to m and f.  The round count is the same for every lane of a
+// workgroup, so the barriers around a flush are reached by all of them.
+constexpr int kLmeAsmBlocks = 512;
+
+template <int G, int PPL, typename DN>
+__global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
+                                                 const double* __restrict__ xp,
+                                                 const int64_t* __restrict__ offsets,
+                                                 const int32_t* __restrict__ idx, int64_t cap,
+                                                 double beta, double tol, int max_iter,
+                                                 double* __restrict__ lam,
+                                                 double* __restrict__ N, DN* __restrict__ dN,
+                                                 otm_diag* diag, AsmIn a) {
+  constexpr int per_round = 256 / G;
+  constexpr int flush_rounds = 512 / per_round;
+  __shared__ NodeTable table;
+  const int tid = threadIdx.x;
+  table_clear(table, tid, 256);
+  __syncthreads();
+  const int64_t chunk = (n_mp + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)xcd_block() * chunk;
+  const int64_t hi = lo + chunk < n_mp ? lo + chunk : n_mp;
+  const bool ok = offsets[n_mp] <= cap;  // lists were written (capacity)
+  const int lane = tid % G;
+  AsmSink<DN> sink{&table, idx, a.vol, a.mass, (const DN*)a.sigma, a.m, a.f, a.n_nodes, n_mp};
+  int r = 0;
+  for (int64_t p0 = lo; p0 < hi; p0 += per_round) {
+    const int64_t p = p0 + tid / G;
+    if (ok && p < hi) {
+      const int K = (int)(offsets[p + 1] - offsets[p]);
+      if (K <= G * PPL)
+        lme_point<G, PPL, true, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
+                                    max_iter, lam, N, dN, diag, sink);
+      else
+        lme_point<G, PPL, false, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
+                                     max_iter, lam, N, dN, diag, sink);
+    }
+    if (++r == flush_rounds) {
+      r = 0;
+      __syncthreads();
+      table_flush(table, tid, 256, a.m, a.f, a.n_nodes);
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  table_flush(table, tid, 256, a.m, a.f, a.n_nodes);
 }
 
 void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const double* x_mp,
                 const int64_t* nbr_offsets, const int32_t* nbr_idx, int64_t pair_capacity,
                 double beta, double tol, int32_t max_iter, double* lam, double* N, void* dN,
-                int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s) {
+                int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s,
+                const AsmIn* fused) {
   if (n_mp <= 0) return;
   const NodeSrc ns{x_nodes, packed, n_nodes};
   constexpr int G = 4, PPL = 10;
+  if (fused != nullptr) {
+    if (precision == OTM_FP64)
+      k_lme_asm<G, PPL, double><<<kLmeAsmBlocks, 256, 0, s>>>(
+          ns, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity, beta, tol, max_iter, lam, N,
+          (double*)dN, diag, *fused);
+    else
+      k_lme_asm<G, PPL, float><<<kLmeAsmBlocks, 256, 0, s>>>(
+          ns, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity, beta, tol, max_iter, lam, N,
+          (float*)dN, diag, *fused);
+    return;
+  }
   const unsigned nb = (unsigned)((n_mp + (256 / G) - 1) / (256 / G));
   if (precision == OTM_FP64)
     k_lme<G, PPL, double><<<nb, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx,

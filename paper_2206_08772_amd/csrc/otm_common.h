@@ -246,4 +246,63 @@ OTM_HD void sym_mul_vec(const double M[6], const double v[3], double o[3]) {
   o[2] = M[5] * v[0] + M[4] * v[1] + M[2] * v[2];
 }
 
+// ------------------------------------------------ nodal assembly table
+// A workgroup's per-node sums of (m, f) in LDS: open addressing on the node
+// id (multiplicative hash, linear probing).  A pair whose node finds no slot
+// within 32 probes goes straight to memory with float64 atomics; flush adds
+// each occupied slot's four sums to m and f with one atomic each and clears
+// the table.  Summation order varies from run to run.
+constexpr int kTableBits = 10;
+constexpr int kTableSlots = 1 << kTableBits;
+
+struct NodeTable {
+  int32_t keys[kTableSlots];
+  double vals[4][kTableSlots];
+};
+
+OTM_DEV void table_clear(NodeTable& t, int tid, int nthreads) {
+  for (int s = tid; s < kTableSlots; s += nthreads) {
+    t.keys[s] = -1;
+    t.vals[0][s] = t.vals[1][s] = t.vals[2][s] = t.vals[3][s] = 0.0;
+  }
+}
+
+OTM_DEV void table_insert(NodeTable& t, int32_t I, double c0, double c1, double c2, double c3,
+                          double* m, double* f, int64_t n_nodes) {
+  uint32_t h = ((uint32_t)I * 2654435761u) >> (32 - kTableBits);
+  int slot = -1;
+  for (int probe = 0; probe < 32; ++probe) {
+    const int32_t prev = atomicCAS(&t.keys[h], -1, I);
+    if (prev == -1 || prev == I) { slot = (int)h; break; }
+    h = (h + 1) & (kTableSlots - 1);
+  }
+  if (slot >= 0) {
+    atomicAdd(&t.vals[0][slot], c0);
+    atomicAdd(&t.vals[1][slot], c1);
+    atomicAdd(&t.vals[2][slot], c2);
+    atomicAdd(&t.vals[3][slot], c3);
+  } else {  // crowded table: straight to memory
+    atomicAdd(&m[I], c0);
+    atomicAdd(&f[I], c1);
+    atomicAdd(&f[n_nodes + I], c2);
+    atomicAdd(&f[2 * n_nodes + I], c3);
+  }
+}
+
+// Every lane of the workgroup calls this after a barrier; it ends cleared
+// (a barrier is needed before the next inserts).
+OTM_DEV void table_flush(NodeTable& t, int tid, int nthreads, double* m, double* f,
+                         int64_t n_nodes) {
+  for (int s = tid; s < kTableSlots; s += nthreads) {
+    const int32_t I = t.keys[s];
+    if (I < 0) continue;
+    atomicAdd(&m[I], t.vals[0][s]);
+    atomicAdd(&f[I], t.vals[1][s]);
+    atomicAdd(&f[n_nodes + I], t.vals[2][s]);
+    atomicAdd(&f[2 * n_nodes + I], t.vals[3][s]);
+    t.keys[s] = -1;
+    t.vals[0][s] = t.vals[1][s] = t.vals[2][s] = t.vals[3][s] = 0.0;
+  }
+}
+
 }  // namespace otm

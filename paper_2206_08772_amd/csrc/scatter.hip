@@ -300,13 +300,12 @@ namespace otm {
 
 // Atomic assembly with workgroup pre-aggregation.  A workgroup takes 512
 // consecutive MPs (spatially compact, so they share most of their nodes),
-// sums their contributions per node in an LDS hash table (open addressing on
-// the node id), then adds each distinct node's four sums to m and f with one
-// float64 atomic each.  Summation order varies from run to run.
+// sums their contributions per node in an LDS table (NodeTable), then adds
+// each distinct node's four sums to m and f with one float64 atomic each.
+// Summation order varies from run to run.  Without the stabilisation term
+// the step fuses this into the shape-function kernel instead (lme.hip).
 constexpr int kAsmMPs = 512;
 constexpr int kAsmLanes = 8;
-constexpr int kAsmSlotBits = 10;
-constexpr int kAsmSlots = 1 << kAsmSlotBits;
 
 template <typename R, bool STAB>
 __global__ __launch_bounds__(256) void k_assemble_atomic(
@@ -314,13 +313,9 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
     const int32_t* __restrict__ idx, const double* __restrict__ N, const R* __restrict__ dN,
     const double* __restrict__ vol, const double* __restrict__ mass, const R* __restrict__ sigma,
     double* __restrict__ m, double* __restrict__ f, Stab sb) {
-  __shared__ int32_t keys[kAsmSlots];
-  __shared__ double vals[4][kAsmSlots];
+  __shared__ NodeTable table;
   const int tid = threadIdx.x;
-  for (int s = tid; s < kAsmSlots; s += 256) {
-    keys[s] = -1;
-    vals[0][s] = vals[1][s] = vals[2][s] = vals[3][s] = 0.0;
-  }
+  table_clear(table, tid, 256);
   __syncthreads();
   const bool ok = offsets[n_mp] <= cap;
   const int64_t base = (int64_t)xcd_block() * kAsmMPs;
@@ -337,24 +332,7 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
     StabMP sm;
     if constexpr (STAB) stab_load(sb, n_mp, p, sm);
     auto insert = [&](int32_t I, double c0, double c1, double c2, double c3) {
-      uint32_t h = ((uint32_t)I * 2654435761u) >> (32 - kAsmSlotBits);
-      int slot = -1;
-      for (int probe = 0; probe < 32; ++probe) {
-        const int32_t prev = atomicCAS(&keys[h], -1, I);
-        if (prev == -1 || prev == I) { slot = (int)h; break; }
-        h = (h + 1) & (kAsmSlots - 1);
-      }
-      if (slot >= 0) {
-        atomicAdd(&vals[0][slot], c0);
-        atomicAdd(&vals[1][slot], c1);
-        atomicAdd(&vals[2][slot], c2);
-        atomicAdd(&vals[3][slot], c3);
-      } else {  // crowded table: straight to memory
-        atomicAdd(&m[I], c0);
-        atomicAdd(&f[I], c1);
-        atomicAdd(&f[n_nodes + I], c2);
-        atomicAdd(&f[2 * n_nodes + I], c3);
-      }
+      table_insert(table, I, c0, c1, c2, c3, m, f, n_nodes);
     };
     auto contrib = [&](int64_t q, int32_t& I, double& c0, double& c1, double& c2, double& c3) {
       I = idx[q];
@@ -388,14 +366,7 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
     }
   }
   __syncthreads();
-  for (int s = tid; s < kAsmSlots; s += 256) {
-    const int32_t I = keys[s];
-    if (I < 0) continue;
-    atomicAdd(&m[I], vals[0][s]);
-    atomicAdd(&f[I], vals[1][s]);
-    atomicAdd(&f[n_nodes + I], vals[2][s]);
-    atomicAdd(&f[2 * n_nodes + I], vals[3][s]);
-  }
+  table_flush(table, tid, 256, m, f, n_nodes);
 }
 
 template <typename R, bool STAB>
