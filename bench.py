@@ -354,8 +354,10 @@ def main():
             over["eps_stab"] = w.material.E / (2 * (1 + w.material.nu)) * w.h ** 2
         r = run_variant(w, prec, scat, args.steps, args.warmup, **over)
         pm = dict(r["phase_ms"])
-        if scat == "segmented":      # markers 4..6: influence lists, then the gather
-            pm["influence_lists"] = pm.pop("assembly")
+        if scat == "segmented":      # markers 3..6: lists, LME + contributions, node sums
+            pm["influence_lists"] = pm.pop("lme")
+            pm["lme_contributions"] = pm.pop("assembly")
+            pm["node_sums"] = pm.pop("segmented")
         elif not over:               # assembly fused into the shape-function kernel
             pm["lme_assembly"] = pm.pop("lme") + pm.pop("assembly")
         variants[v] = dict(value=round(r["value"], 1), ms_per_step=round(r["ms_per_step"], 4),

@@ -137,20 +137,38 @@ static void refresh_impl(otm_state& st, const otm_params& p, bool rebuild, int32
     launch_search(st.n_nodes, st.x, st.n_mp, st.xp, p.r_list, p.cell_size, st.pair_capacity,
                   st.nbr_offsets, st.nbr_idx, w, diag, s);
   mark(ev, 3, s);
-  // the atomic assembly without the stabilisation term runs inside the
-  // shape-function kernel, on N and grad N while they are in registers
-  const bool fuse = mode == OTM_SCATTER_ATOMIC && !stab;
+  // Without the stabilisation term the assembly's per-pair work runs inside
+  // the shape-function kernel, on N and grad N while they are in registers:
+  // the atomic mode sums into LDS node tables there; the segmented mode
+  // stores each pair's contributions in node order there (its influence
+  // lists, which depend only on the support lists, are built first) and a
+  // last kernel sums each node's run.  Events (profiled step): atomic
+  // 3 | LME + assembly | 4 | 6; segmented 3 | influence lists | 4 | LME +
+  // contributions | 5 | node sums | 6; with the stabilisation term 3 | LME |
+  // 4 | assembly (atomic), or 4 | lists | 5 | contributions + sums (segmented) | 6.
+  const bool fuse_atomic = mode == OTM_SCATTER_ATOMIC && !stab;
+  const bool fuse_seg = mode == OTM_SCATTER_SEGMENTED && !stab;
+  if (fuse_seg) {
+    if (rebuild) launch_influence_lists(st, w, s);
+    mark(ev, 4, s);
+  }
   const AsmIn fused{st.vol, st.mass, st.sigma, st.m, st.f, st.n_nodes};
+  const SegIn seg{st.vol, st.mass, st.sigma, w.tr_pos, w.contrib};
   launch_lme(st.n_nodes, st.x, st.n_mp, st.xp, st.nbr_offsets, st.nbr_idx, st.pair_capacity,
              p.beta, p.lme_tol, p.lme_max_iter, st.lam, st.N, st.dN, st.precision, w.nodes, diag,
-             s, fuse ? &fused : nullptr);
-  mark(ev, 4, s);
-  if (mode == OTM_SCATTER_ATOMIC) {
-    if (!fuse) launch_assemble_atomic(st, sb, s);
-  } else {
-    if (rebuild) launch_influence_lists(st, w, s);
+             s, fuse_atomic ? &fused : nullptr, fuse_seg ? &seg : nullptr);
+  if (fuse_seg) {
     mark(ev, 5, s);
-    launch_scatter_segmented(st, w, sb, s);
+    launch_seg_gather(st, w, s);
+  } else {
+    mark(ev, 4, s);
+    if (mode == OTM_SCATTER_ATOMIC) {
+      if (!fuse_atomic) launch_assemble_atomic(st, sb, s);
+    } else {
+      if (rebuild) launch_influence_lists(st, w, s);
+      mark(ev, 5, s);
+      launch_scatter_segmented(st, w, sb, s);
+    }
   }
   mark(ev, 6, s);
 }

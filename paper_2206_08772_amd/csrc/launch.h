@@ -72,14 +72,25 @@ struct AsmIn {
   int64_t n_nodes;
 };
 
+// Inputs of the deterministic assembly's contribution store when it is fused
+// into the shape-function kernel (the influence lists must be current).
+struct SegIn {
+  const double* vol;
+  const double* mass;
+  const void* sigma;
+  const int32_t* pos_of;
+  double4* contrib;
+};
+
 // LME shape functions (float64 Newton; dN stored per precision).
 // ``packed`` (nullable): node records (x, y, z, du_x) at even indices.
 // ``fused`` (nullable): also assemble m and f from the new N and grad N.
+// ``seg`` (nullable): also store every pair's contributions in node order.
 void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const double* x_mp,
                 const int64_t* nbr_offsets, const int32_t* nbr_idx, int64_t pair_capacity,
                 double beta, double tol, int32_t max_iter, double* lam, double* N, void* dN,
                 int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s,
-                const AsmIn* fused = nullptr);
+                const AsmIn* fused = nullptr, const SegIn* seg = nullptr);
 
 // Nodes and material points.
 // Node records: packed[2 I] = (x, y, z, du_x), packed[2 I + 1] = (du_y, du_z, 0, 0).
@@ -111,6 +122,8 @@ struct Stab {
 void launch_influence_lists(const otm_state& st, const Workspace& w, hipStream_t s);
 void launch_scatter_segmented(const otm_state& st, const Workspace& w, const Stab& sb,
                               hipStream_t s);
+// Only the per-node ordered sums (contributions already stored).
+void launch_seg_gather(const otm_state& st, const Workspace& w, hipStream_t s);
 // Atomic assembly (m and f must be zero beforehand).
 void launch_assemble_atomic(const otm_state& st, const Stab& sb, hipStream_t s);
 

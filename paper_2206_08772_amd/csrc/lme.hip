@@ -183,6 +183,33 @@ struct AsmSink {
   }
 };
 
+// Fused contribution store of the deterministic assembly: the pair's four
+// contributions (the standalone contribution kernel's arithmetic) go to its
+// place in the node-sorted order, where each node later sums them in order.
+template <typename R>
+struct SegSink {
+  const double* vol;
+  const double* mass;
+  const R* sigma;
+  const int32_t* pos_of;
+  double4* contrib;
+  int64_t n_mp;
+  double mp;
+  R v, s0, s1, s2, s3, s4, s5;
+  OTM_DEV void begin(int64_t p) {
+    mp = mass[p];
+    v = (R)vol[p];
+    s0 = sigma[p]; s1 = sigma[n_mp + p]; s2 = sigma[2 * n_mp + p];
+    s3 = sigma[3 * n_mp + p]; s4 = sigma[4 * n_mp + p]; s5 = sigma[5 * n_mp + p];
+  }
+  OTM_DEV void operator()(int64_t q, double Nq, const double g[3]) {
+    const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
+    contrib[pos_of[q]] = make_double4(Nq * mp, (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2)),
+                                      (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2)),
+                                      (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2)));
+  }
+};
+
 template <int G, int PPL, bool CACHED, typename DN, class Sink>
 OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, const double* __restrict__ xp,
                        const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
@@ -280,20 +307,19 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
   }
 }
 
-template <int G, int PPL, typename DN>
+template <int G, int PPL, typename DN, class Sink>
 __global__ __launch_bounds__(256) void k_lme(NodeSrc ns, int64_t n_mp, const double* __restrict__ xp,
                                              const int64_t* __restrict__ offsets,
                                              const int32_t* __restrict__ idx, int64_t cap,
                                              double beta, double tol, int max_iter,
                                              double* __restrict__ lam, double* __restrict__ N,
-                                             DN* __restrict__ dN, otm_diag* diag) {
+                                             DN* __restrict__ dN, otm_diag* diag, Sink sink) {
   constexpr int per_block = 256 / G;
   const int64_t p = (int64_t)xcd_block() * per_block + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (p >= n_mp) return;  // whole group leaves together
   if (offsets[n_mp] > cap) return;  // lists were not written (capacity)
   const int K = (int)(offsets[p + 1] - offsets[p]);
-  NoSink sink;
   if (K <= G * PPL)
     lme_point<G, PPL, true, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
                                 max_iter, lam, N, dN, diag, sink);
@@ -358,7 +384,7 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
                 const int64_t* nbr_offsets, const int32_t* nbr_idx, int64_t pair_capacity,
                 double beta, double tol, int32_t max_iter, double* lam, double* N, void* dN,
                 int32_t precision, const double4* packed, otm_diag* diag, hipStream_t s,
-                const AsmIn* fused) {
+                const AsmIn* fused, const SegIn* seg) {
   if (n_mp <= 0) return;
   const NodeSrc ns{x_nodes, packed, n_nodes};
   constexpr int G = 4, PPL = 10;
@@ -374,14 +400,25 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
     return;
   }
   const unsigned nb = (unsigned)((n_mp + (256 / G) - 1) / (256 / G));
-  if (precision == OTM_FP64)
-    k_lme<G, PPL, double><<<nb, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx,
-                                             pair_capacity, beta, tol, max_iter, lam, N,
-                                             (double*)dN, diag);
-  else
-    k_lme<G, PPL, float><<<nb, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx,
-                                            pair_capacity, beta, tol, max_iter, lam, N,
-                                            (float*)dN, diag);
+  auto run = [&](auto sink, auto* dn) {
+    k_lme<G, PPL><<<nb, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity, beta,
+                                     tol, max_iter, lam, N, dn, diag, sink);
+  };
+  if (precision == OTM_FP64) {
+    if (seg != nullptr)
+      run(SegSink<double>{seg->vol, seg->mass, (const double*)seg->sigma, seg->pos_of,
+                          seg->contrib, n_mp},
+          (double*)dN);
+    else
+      run(NoSink{}, (double*)dN);
+  } else {
+    if (seg != nullptr)
+      run(SegSink<float>{seg->vol, seg->mass, (const float*)seg->sigma, seg->pos_of,
+                         seg->contrib, n_mp},
+          (float*)dN);
+    else
+      run(NoSink{}, (float*)dN);
+  }
 }
 
 }  // namespace otm

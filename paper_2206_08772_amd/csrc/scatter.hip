@@ -289,8 +289,14 @@ void launch_scatter_segmented(const otm_state& st, const Workspace& w, const Sta
     else
       stab ? seg_contrib<float, true>(st, w, sb, s) : seg_contrib<float, false>(st, w, sb, s);
   }
+  launch_seg_gather(st, w, s);
+}
+
+void launch_seg_gather(const otm_state& st, const Workspace& w, hipStream_t s) {
+  const int64_t nn = st.n_nodes;
+  if (nn <= 0) return;
   const unsigned nb = (unsigned)((nn + (256 / kSegLanes) - 1) / (256 / kSegLanes));
-  k_seg_gather<<<nb, 256, 0, s>>>(nn, nm, st.pair_capacity, st.nbr_offsets, w.tr_start,
+  k_seg_gather<<<nb, 256, 0, s>>>(nn, st.n_mp, st.pair_capacity, st.nbr_offsets, w.tr_start,
                                   w.contrib, st.m, st.f);
 }
 
