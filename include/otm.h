@@ -227,6 +227,7 @@ otm_status otm_refresh(otm_state* st, const otm_params* p, int32_t rebuild,
  *           in r_list they stay valid for several steps)
  *   shapes  LME at the new MP positions (warm-started multipliers)
  *   forces  m_I = sum N_I m_p;  f_I = -sum v_p sigma_p grad N_I
+ *           (- eps sum N_I e_I with params.eps_stab > 0)
  * scatter_mode selects the force assembly; the segmented mode keeps its
  * influence lists in the workspace, so pass the same workspace on every call.
  */
@@ -301,10 +302,14 @@ otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_p
 
 /*
  * otm_step with phase markers: events[k] (host array of 7 caller-created
- * hipEvent_t; a NULL entry is skipped) is recorded on s at the start of
- * phase k: 0 node update, 1 MP update, 2 search (or the point where it would
- * run), 3 shape functions, 4 assembly (atomic mode) or influence lists
- * (segmented mode), 5 segmented gather (segmented mode only), 6 end of step.
+ * hipEvent_t; a NULL entry is skipped) are recorded on s between the phases:
+ * 0 | node update | 1 | MP update | 2 | search (if rebuild) | 3, then
+ *   atomic mode:      shape functions with the assembly | 4 | 6
+ *   segmented mode:   influence lists (if rebuild) | 4 | shape functions with
+ *                     the contribution store | 5 | ordered node sums | 6
+ *   with eps_stab > 0: shape functions | 4 | assembly (atomic) | 6, or
+ *                     shape functions | 4 | influence lists | 5 |
+ *                     contributions and node sums (segmented) | 6.
  * Same work and results as otm_step.
  */
 otm_status otm_step_profiled(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
