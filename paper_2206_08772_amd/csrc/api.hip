@@ -13,10 +13,13 @@ static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t carve_workspace(void* base, size_t bytes, int64_t n_nodes, int64_t n_mp,
                        int64_t pair_capacity, Workspace* w) {
   const int64_t cap_cells = (n_nodes > 0 ? n_nodes : 0) + 1024;
-  int64_t scan_n = n_mp + 1;
-  if (cap_cells + 1 > scan_n) scan_n = cap_cells + 1;
-  if (n_nodes + 1 > scan_n) scan_n = n_nodes + 1;
-  const int64_t scan_blocks = (scan_n + kScanBlock - 1) / kScanBlock + 1;
+  // block totals of the largest scan: the MP offsets, the node influence
+  // offsets, or the node and MP cell counts scanned together (two arrays)
+  auto blocks = [](int64_t n) { return (n + kScanBlock - 1) / kScanBlock; };
+  int64_t scan_blocks = blocks(n_mp + 1);
+  if (2 * blocks(cap_cells + 1) > scan_blocks) scan_blocks = 2 * blocks(cap_cells + 1);
+  if (blocks(n_nodes + 1) > scan_blocks) scan_blocks = blocks(n_nodes + 1);
+  scan_blocks += 1;
   const size_t sizes[] = {
       align256(sizeof(Grid)),
       align256(sizeof(double) * 6 * kBBoxBlocks),
@@ -36,6 +39,7 @@ size_t carve_workspace(void* base, size_t bytes, int64_t n_nodes, int64_t n_mp,
       align256(sizeof(int32_t) * (size_t)n_mp),
       align256(sizeof(double4) * (size_t)n_mp),
       align256(sizeof(double4) * (size_t)pair_capacity),
+      align256(sizeof(int32_t) * cap_cells),
   };
   size_t total = 0;
   for (size_t s : sizes) total += s;
@@ -62,6 +66,7 @@ size_t carve_workspace(void* base, size_t bytes, int64_t n_nodes, int64_t n_mp,
   w->mp_cell = (int32_t*)take(15);
   w->mp_sorted = (double4*)take(16);
   w->contrib = (double4*)take(17);
+  w->mp_cell_cursor = (int32_t*)take(18);
   return total;
 }
 

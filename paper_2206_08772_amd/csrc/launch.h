@@ -40,6 +40,7 @@ struct Workspace {
   int32_t* stage;        // [n_mp][kRowCapacity] sorted rows of the one-pass search
   double4* nodes;        // [2 n_nodes] packed node records (x, y, z, du_x), (du_y, du_z, 0, 0)
   int32_t* mp_cell_start;  // [cap_cells + 1] MPs binned on the search grid
+  int32_t* mp_cell_cursor; // [cap_cells]
   int32_t* mp_cell;        // [n_mp]
   double4* mp_sorted;      // [n_mp]: x, y, z, MP id
   double4* contrib;        // [pair_capacity] pair contributions (m, f) in node-sorted order

@@ -13,11 +13,16 @@
 namespace otm {
 
 // ---------------------------------------------------------------- prefix sum
+// Inclusive scan in three passes: each workgroup scans kScanBlock elements
+// and writes its total, one workgroup scans the totals (exclusive), each
+// workgroup adds its offset.  Two arrays of equal length (the node and MP
+// cell counts) go through the same three launches: workgroup b works on
+// array b / nb, and the totals of each array are scanned separately.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_scan_blocks(T* a, int64_t n, int64_t* aux) {
+OTM_DEV void scan_block(T* a, int64_t n, int64_t blk, int64_t* total) {
   __shared__ T s[1024];
   const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)tid * 4;
+  const int64_t base = blk * kScanBlock + (int64_t)tid * 4;
   T v[4];
   T run = 0;
 #pragma unroll
@@ -40,57 +45,77 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(T* a, int64_t n, int64_t* 
     const int64_t i = base + k;
     if (i < n) a[i] = v[k] + excl;
   }
-  if (tid == 1023) aux[blockIdx.x] = (int64_t)s[1023];
+  if (tid == 1023) *total = (int64_t)s[1023];
 }
 
-// Exclusive scan of the block totals by one workgroup (any count).
-__global__ __launch_bounds__(1024) void k_scan_aux(int64_t* aux, int64_t nb) {
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_blocks(T* a, T* b, int64_t n, int64_t nb,
+                                                      int64_t* aux) {
+  const int64_t seg = blockIdx.x / nb;
+  scan_block(seg == 0 ? a : b, n, blockIdx.x - seg * nb, aux + blockIdx.x);
+}
+
+// Exclusive scan of nseg segments of nb block totals by one workgroup.
+__global__ __launch_bounds__(1024) void k_scan_aux(int64_t* aux, int64_t nb, int nseg) {
   __shared__ int64_t s[1024];
   __shared__ int64_t carry;
   const int tid = threadIdx.x;
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
-    const int64_t i = b0 + tid;
-    const int64_t v = i < nb ? aux[i] : 0;
-    s[tid] = v;
+  for (int seg = 0; seg < nseg; ++seg) {
+    int64_t* t = aux + seg * nb;
+    if (tid == 0) carry = 0;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const int64_t add = tid >= o ? s[tid - o] : 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+      const int64_t i = b0 + tid;
+      const int64_t v = i < nb ? t[i] : 0;
+      s[tid] = v;
       __syncthreads();
-      s[tid] += add;
+      for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t add = tid >= o ? s[tid - o] : 0;
+        __syncthreads();
+        s[tid] += add;
+        __syncthreads();
+      }
+      if (i < nb) t[i] = carry + s[tid] - v;
+      __syncthreads();
+      if (tid == 0) carry += s[1023];
       __syncthreads();
     }
-    if (i < nb) aux[i] = carry + s[tid] - v;
-    __syncthreads();
-    if (tid == 0) carry += s[1023];
-    __syncthreads();
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_scan_add(T* a, int64_t n, const int64_t* aux) {
+__global__ __launch_bounds__(1024) void k_scan_add(T* a, T* b, int64_t n, int64_t nb,
+                                                   const int64_t* aux) {
   const int64_t add = aux[blockIdx.x];
   if (add == 0) return;
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  const int64_t seg = blockIdx.x / nb;
+  T* arr = seg == 0 ? a : b;
+  const int64_t base = (blockIdx.x - seg * nb) * kScanBlock;
   for (int k = threadIdx.x; k < kScanBlock; k += 1024) {
     const int64_t i = base + k;
-    if (i < n) a[i] += (T)add;
+    if (i < n) arr[i] += (T)add;
   }
 }
 
+// b == nullptr: one array
 template <typename T>
-static void scan_impl(T* a, int64_t n, int64_t* aux, hipStream_t s) {
+static void scan_impl(T* a, T* b, int64_t n, int64_t* aux, hipStream_t s) {
   if (n <= 0) return;
   const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-  k_scan_blocks<T><<<dim3((unsigned)nb), dim3(1024), 0, s>>>(a, n, aux);
+  const int nseg = b == nullptr ? 1 : 2;
+  const unsigned grid = (unsigned)(nb * nseg);
+  k_scan_blocks<T><<<grid, 1024, 0, s>>>(a, b, n, nb, aux);
   if (nb > 1) {
-    k_scan_aux<<<1, 1024, 0, s>>>(aux, nb);
-    k_scan_add<T><<<dim3((unsigned)nb), dim3(1024), 0, s>>>(a, n, aux);
+    k_scan_aux<<<1, 1024, 0, s>>>(aux, nb, nseg);
+    k_scan_add<T><<<grid, 1024, 0, s>>>(a, b, n, nb, aux);
   }
 }
-void scan_inclusive(int64_t* a, int64_t n, int64_t* aux, hipStream_t s) { scan_impl(a, n, aux, s); }
-void scan_inclusive(int32_t* a, int64_t n, int64_t* aux, hipStream_t s) { scan_impl(a, n, aux, s); }
+void scan_inclusive(int64_t* a, int64_t n, int64_t* aux, hipStream_t s) {
+  scan_impl<int64_t>(a, nullptr, n, aux, s);
+}
+void scan_inclusive(int32_t* a, int64_t n, int64_t* aux, hipStream_t s) {
+  scan_impl<int32_t>(a, nullptr, n, aux, s);
+}
 
 // ---------------------------------------------------------------- fills
 __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
@@ -121,21 +146,6 @@ void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s) {
 void launch_fill_i64(int64_t* a, int64_t n, int64_t v, hipStream_t s) {
   if (n > 0) k_fill_i64<<<fill_blocks(n), 256, 0, s>>>(a, n, v);
 }
-static void fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s) { launch_fill_i32(a, n, v, s); }
-
-// Zeroes two int32 arrays in one launch (cell counters before a binning).
-__global__ void k_zero2_i32(int32_t* a, int64_t na, int32_t* b, int64_t nb) {
-  const int64_t n = na > nb ? na : nb;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (i < na) a[i] = 0;
-    if (i < nb) b[i] = 0;
-  }
-}
-static void zero2_i32(int32_t* a, int64_t na, int32_t* b, int64_t nb, hipStream_t s) {
-  const int64_t n = na > nb ? na : nb;
-  if (n > 0) k_zero2_i32<<<fill_blocks(n), 256, 0, s>>>(a, na, b, nb);
-}
 
 __global__ void k_diag_reset(otm_diag* d) {
   d->flags = 0;
@@ -148,8 +158,28 @@ __global__ void k_diag_reset(otm_diag* d) {
 void launch_diag_reset(otm_diag* d, hipStream_t s) { k_diag_reset<<<1, 1, 0, s>>>(d); }
 
 // ---------------------------------------------------------------- cell grid
-__global__ __launch_bounds__(256) void k_bbox_partial(const double* x, int64_t n, double* part) {
+// Bounding box partials of the nodes; the same launch clears the cell
+// counters and cursors of the node and MP binnings that follow.
+struct BinCounters {
+  int32_t* node_start;  // [cap + 1]
+  int32_t* node_cursor; // [cap]
+  int32_t* mp_start;    // [cap + 1]
+  int32_t* mp_cursor;   // [cap]
+  int64_t cap;
+};
+
+__global__ __launch_bounds__(256) void k_bbox_partial(const double* x, int64_t n, double* part,
+                                                      BinCounters z) {
   __shared__ double sh[6][256];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= z.cap;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    z.node_start[i] = 0;
+    z.mp_start[i] = 0;
+    if (i < z.cap) {
+      z.node_cursor[i] = 0;
+      z.mp_cursor[i] = 0;
+    }
+  }
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -247,28 +277,52 @@ OTM_DEV int cell_coord(double x, double lo, double inv_cell, int dim) {
   return c;
 }
 
-__global__ __launch_bounds__(256) void k_bin_count(const double* x, int64_t n, const Grid* g,
-                                                   int32_t* node_cell, int32_t* cell_start) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Counting sort of two point sets (nodes, then MPs) on one grid, each pass
+// one launch: thread i < n_a takes point i of set a, threads from b0 (n_a
+// rounded up to a wave, so no wave mixes the sets and the wave-grouped
+// atomics see one counter array) take set b.
+struct BinSet {
+  const double* x;     // [3][n]
+  int64_t n;
+  int32_t* cell;       // [n] cell of each point
+  int32_t* start;      // [cap + 1] counts, then offsets
+  int32_t* cursor;     // [cap]
+  double4* sorted;     // [n] (x, y, z, index) in cell order
+};
+
+OTM_DEV bool bin_pick(const BinSet& a, const BinSet& b, int64_t b0, const BinSet*& set,
+                      int64_t& i) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < a.n) { set = &a; i = t; return true; }
+  if (t >= b0 && t - b0 < b.n) { set = &b; i = t - b0; return true; }
+  return false;
+}
+
+__global__ __launch_bounds__(256) void k_bin_count(BinSet a, BinSet b, int64_t b0,
+                                                   const Grid* g) {
+  const BinSet* set;
+  int64_t i;
+  if (!bin_pick(a, b, b0, set, i)) return;
+  const double* x = set->x;
+  const int64_t n = set->n;
   const double inv = 1.0 / g->cell;
   const int cx = cell_coord(x[i], g->lo[0], inv, g->dims[0]);
   const int cy = cell_coord(x[n + i], g->lo[1], inv, g->dims[1]);
   const int cz = cell_coord(x[2 * n + i], g->lo[2], inv, g->dims[2]);
   const int32_t cid = (cz * g->dims[1] + cy) * g->dims[0] + cx;
-  node_cell[i] = cid;
-  grouped_atomic_add(cell_start + 1, cid);
+  set->cell[i] = cid;
+  grouped_atomic_add(set->start + 1, cid);
 }
 
-__global__ __launch_bounds__(256) void k_bin_fill(const double* x, int64_t n,
-                                                  const int32_t* node_cell,
-                                                  const int32_t* cell_start, int32_t* cursor,
-                                                  double4* sorted) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t cid = node_cell[i];
-  const int32_t pos = cell_start[cid] + grouped_atomic_add(cursor, cid);
-  sorted[pos] = make_double4(x[i], x[n + i], x[2 * n + i], (double)i);
+__global__ __launch_bounds__(256) void k_bin_fill(BinSet a, BinSet b, int64_t b0) {
+  const BinSet* set;
+  int64_t i;
+  if (!bin_pick(a, b, b0, set, i)) return;
+  const double* x = set->x;
+  const int64_t n = set->n;
+  const int32_t cid = set->cell[i];
+  const int32_t pos = set->start[cid] + grouped_atomic_add(set->cursor, cid);
+  set->sorted[pos] = make_double4(x[i], x[n + i], x[2 * n + i], (double)i);
 }
 
 // ---------------------------------------------------------------- MP lists
@@ -663,25 +717,22 @@ __global__ __launch_bounds__(1024) void k_search_done(const int64_t* offsets, in
 void launch_search(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const double* x_mp,
                    double r_list, double cell_size, int64_t pair_capacity, int64_t* nbr_offsets,
                    int32_t* nbr_idx, const Workspace& w, otm_diag* diag, hipStream_t s) {
-  k_bbox_partial<<<kBBoxBlocks, 256, 0, s>>>(x_nodes, n_nodes, w.bbox_part);
+  const BinCounters z{w.cell_start, w.cell_cursor, w.mp_cell_start, w.mp_cell_cursor,
+                      w.cap_cells};
+  k_bbox_partial<<<kBBoxBlocks, 256, 0, s>>>(x_nodes, n_nodes, w.bbox_part, z);
   k_grid_finalize<<<1, 256, 0, s>>>(w.bbox_part, kBBoxBlocks, cell_size, w.cap_cells, w.grid);
-  zero2_i32(w.cell_start, w.cap_cells + 1, w.cell_cursor, w.cap_cells, s);
-  const unsigned nbn = (unsigned)((n_nodes + 255) / 256);
-  if (nbn > 0)
-    k_bin_count<<<nbn, 256, 0, s>>>(x_nodes, n_nodes, w.grid, w.node_cell, w.cell_start);
-  scan_inclusive(w.cell_start + 1, w.cap_cells, w.scan_aux, s);
-  if (nbn > 0)
-    k_bin_fill<<<nbn, 256, 0, s>>>(x_nodes, n_nodes, w.node_cell, w.cell_start, w.cell_cursor,
-                                   w.sorted);
+  // nodes and MPs binned on the grid together: one count, one two-array scan,
+  // one fill
+  const BinSet nodes{x_nodes, n_nodes, w.node_cell, w.cell_start, w.cell_cursor, w.sorted};
+  const BinSet mps{x_mp, n_mp, w.mp_cell, w.mp_cell_start, w.mp_cell_cursor, w.mp_sorted};
+  const int64_t b0 = (n_nodes + kWave - 1) / kWave * kWave;
+  const int64_t nt = b0 + n_mp;
+  const unsigned nbt = (unsigned)((nt + 255) / 256);
+  if (nbt > 0) k_bin_count<<<nbt, 256, 0, s>>>(nodes, mps, b0, w.grid);
+  scan_impl<int32_t>(w.cell_start + 1, w.mp_cell_start + 1, w.cap_cells, w.scan_aux, s);
+  if (nbt > 0) k_bin_fill<<<nbt, 256, 0, s>>>(nodes, mps, b0);
   const double r2 = r_list * r_list;
   if (n_mp > 0) {
-    // MPs binned on the same grid (cell_cursor is free again)
-    zero2_i32(w.mp_cell_start, w.cap_cells + 1, w.cell_cursor, w.cap_cells, s);
-    const unsigned nbm = (unsigned)((n_mp + 255) / 256);
-    k_bin_count<<<nbm, 256, 0, s>>>(x_mp, n_mp, w.grid, w.mp_cell, w.mp_cell_start);
-    scan_inclusive(w.mp_cell_start + 1, w.cap_cells, w.scan_aux, s);
-    k_bin_fill<<<nbm, 256, 0, s>>>(x_mp, n_mp, w.mp_cell, w.mp_cell_start, w.cell_cursor,
-                                   w.mp_sorted);
     // a fixed grid (a multiple of the 8 XCDs) strides over the cells
     k_cell_scan<<<kCellBlocks, kCellWaves * kWave, 0, s>>>(r2, w.grid, w.cap_cells, w.cell_start,
                                                    w.sorted, w.mp_cell_start, w.mp_sorted,
