@@ -267,3 +267,24 @@ def test_paper_rod_20_steps_fp64():
                    oracle_fields(st, w.x_nodes, w.x_mp, p["T_r"]))
     bad = {k: v for k, v in errs.items() if not v < FP64_TOL}
     assert not bad, bad
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+@pytest.mark.parametrize("scatter,eps", [("atomic", 0.0), ("segmented", 0.0), ("atomic", 1.0),
+                                         ("segmented", 1.0)])
+def test_tiny_bodies_every_assembly_path(n, scatter, eps):
+    """Lattices of 3^3, 4^3 and 5^3 nodes (48, 162 and 384 MPs): fewer MPs
+    than the 512 workgroups of the fused shape-function kernel, so at most
+    one MP per workgroup and most of them empty; with and without the
+    stabilisation term (eps in units of mu h^2); 5 steps against the
+    oracle."""
+    w = W.elastic_cube(n=n, h=1.0, seed=0, steps=5)
+    mu = w.material.E / (2 * (1 + w.material.nu))
+    over = dict(eps_stab=eps * mu * w.h ** 2)
+    st, p = _oracle_run(w, 5, **over)
+    g, _ = _gpu_run(w, 5, scatter=scatter, **over)
+    assert np.array_equal(g["offsets"], st.offsets) and np.array_equal(g["idx"], st.idx)
+    errs = compare(gpu_fields(g, w.x_nodes, w.x_mp, p["T_r"]),
+                   oracle_fields(st, w.x_nodes, w.x_mp, p["T_r"]))
+    bad = {k: v for k, v in errs.items() if not v < FP64_TOL}
+    assert not bad, bad
