@@ -235,6 +235,32 @@ otm_status otm_step(otm_state* st, const otm_params* p, double dt, int32_t rebui
                     int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
                     hipStream_t s);
 
+/* Support lists and shape functions of one configuration (device arrays with
+ * the layouts and pair capacity of the otm_state they go with). */
+typedef struct otm_lists {
+  int64_t* nbr_offsets;   /* [n_mp+1] */
+  int32_t* nbr_idx;       /* [pair_capacity] */
+  double* N;              /* [pair_capacity] */
+  void* dN;               /* [3][pair_capacity], the state's precision */
+} otm_lists;
+
+/*
+ * otm_step (same step, Alg. 1) with the step's support lists and shape
+ * functions written into the arrays of *next instead of over the state's own.
+ * The MP update reads the lists of step n from the arrays *st points to; the
+ * search (rebuild != 0; with rebuild == 0 the offsets and ids of step n are
+ * first copied into next) and the shape functions then fill *next, and on
+ * success the four list pointers of *st are set to those of *next.  The
+ * arrays *st pointed to before the call are neither written nor freed: they
+ * still hold step n's lists and shape functions, so a caller that records a
+ * trajectory (checkpointed adjoints) keeps them without a copy.  next's arrays
+ * must not overlap the state's.  Errors as for otm_step (OTM_ERR_ARG also for
+ * a NULL or misaligned next; *st is then unchanged).
+ */
+otm_status otm_step_into(otm_state* st, const otm_lists* next, const otm_params* p, double dt,
+                         int32_t rebuild, int32_t scatter_mode, void* ws, size_t ws_bytes,
+                         otm_diag* diag, hipStream_t s);
+
 /* One stored step of a forward trajectory (host struct of device pointers,
  * float64 state as in otm_state with precision OTM_FP64).  Pair arrays N and
  * dN have component stride pair_stride.  m and f are the lumped mass and

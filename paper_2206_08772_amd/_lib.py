@@ -54,6 +54,11 @@ class State(C.Structure):
     ]
 
 
+class Lists(C.Structure):
+    """otm_lists: support lists and shape functions of one configuration."""
+    _fields_ = [(k, C.c_void_p) for k in ("nbr_offsets", "nbr_idx", "N", "dN")]
+
+
 class Diag(C.Structure):
     _fields_ = [
         ("flags", C.c_uint32), ("max_support", C.c_int32),
@@ -99,6 +104,9 @@ _SIGS = {
                                 C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "otm_step": (C.c_int32, [C.POINTER(State), C.POINTER(Params), C.c_double, C.c_int32,
                              C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "otm_step_into": (C.c_int32, [C.POINTER(State), C.POINTER(Lists), C.POINTER(Params),
+                                  C.c_double, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
+                                  C.c_void_p, C.c_void_p]),
     "otm_step_profiled": (C.c_int32, [C.POINTER(State), C.POINTER(Params), C.c_double,
                                       C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                       C.c_void_p, C.c_void_p]),

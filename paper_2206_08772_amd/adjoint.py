@@ -1,9 +1,10 @@
 """Checkpointed reverse-mode gradients of OTM rollouts (float64, J2 models).
 
 ``OTMRollout`` is a ``torch.autograd.Function``: its forward runs N explicit
-steps of libotm and keeps a copy of the state every ``k`` steps; its backward
-walks the segments in reverse, re-runs each segment from its checkpoint while
-keeping every step's state (the tape), then calls ``otm_step_adjoint`` step
+steps of libotm and keeps a copy of the state every ``k`` steps and at the
+last step; its backward walks the segments in reverse, re-runs the interior
+steps of each segment from its first checkpoint while keeping every state
+(the tape; both ends are checkpoints), then calls ``otm_step_adjoint`` step
 by step.  Device buffers are torch tensors; all arithmetic is in libotm.
 
 Gradients: with respect to the hardening constants (A, B, n of the
@@ -21,8 +22,10 @@ from . import _lib
 from ._lib import StateBar, Tape, check, lib
 from .sim import Sim, _ptr, _stream
 
-STATE_FIELDS = ("x", "du", "m", "f", "xp", "vol", "lam", "Fd", "bed", "epsbar", "T", "sigma",
-                "offsets", "idx", "N", "dN")
+LIST_FIELDS = ("offsets", "idx", "N", "dN")
+STATE_FIELDS = ("x", "du", "m", "f", "xp", "vol", "lam", "Fd", "bed", "epsbar", "T",
+                "sigma") + LIST_FIELDS
+POINT_FIELDS = STATE_FIELDS[:-len(LIST_FIELDS)]   # node and MP fields
 
 
 def snapshot(sim):
@@ -30,9 +33,13 @@ def snapshot(sim):
     return {k: getattr(sim, k).clone() for k in STATE_FIELDS}
 
 
-def restore(sim, snap):
-    for k in STATE_FIELDS:
-        getattr(sim, k).copy_(snap[k])
+def snapshot_into(sim, snap, fields=STATE_FIELDS):
+    """Copy state fields into preallocated tensors."""
+    torch._foreach_copy_([snap[k] for k in fields], [getattr(sim, k) for k in fields])
+
+
+def restore(sim, snap, fields=STATE_FIELDS):
+    torch._foreach_copy_([getattr(sim, k) for k in fields], [snap[k] for k in fields])
 
 
 def tape_struct(snap, n_nodes, n_mp, cap):
@@ -70,11 +77,12 @@ class Bars:
 
 def rollout_forward(sim, steps, every, rebuild_every=1):
     """Run ``steps`` steps from the initialised ``sim``, keeping a checkpoint
-    every ``every`` steps (and at 0).  Returns the checkpoint dict."""
+    every ``every`` steps, at 0 and at the last step.  Returns the checkpoint
+    dict."""
     ckpt = {0: snapshot(sim)}
     for n in range(1, steps + 1):
         sim.step(rebuild=(n % rebuild_every == 0))
-        if n % every == 0 and n < steps:
+        if n % every == 0 or n == steps:
             ckpt[n] = snapshot(sim)
     return ckpt
 
@@ -91,23 +99,39 @@ def rollout_backward(sim, ckpt, steps, every, xbar_final, rebuild_every=1):
     mass = sim.mass
     nxt, cur = Bars(nn, nm, cap, dev), Bars(nn, nm, cap, dev)
     nxt.x.copy_(xbar_final)
-    starts = sorted(ckpt)
+    starts = sorted(k for k in ckpt if k < steps)
+    if not starts or starts[0] != 0 or steps not in ckpt:
+        raise ValueError("checkpoints must include step 0 and the last step")
+    # A segment's two ends are checkpoints, so only its interior states are
+    # re-run; their tape (every - 1 states) is allocated once and refilled.
+    # Each re-run step writes its lists and shape functions straight into its
+    # tape entry (otm_step_into), so only node and MP fields are copied.
+    tape = [snapshot(sim) for _ in range(max(min(every, steps) - 1, 0))]
+    own_lists = {k: getattr(sim, k) for k in LIST_FIELDS}
     for s0 in reversed(starts):
         s1 = min(s0 + every, steps)
-        restore(sim, ckpt[s0])
-        tape = [snapshot(sim)]
-        for n in range(s0 + 1, s1 + 1):
-            sim.step(rebuild=(n % rebuild_every == 0))
-            tape.append(snapshot(sim))
+        if s1 not in ckpt:
+            raise ValueError(f"missing checkpoint at step {s1}")
+        states = [ckpt[s0]]
+        if s1 - s0 > 1:
+            restore(sim, ckpt[s0], POINT_FIELDS)
+            sim.use_lists(ckpt[s0])          # read by the first step's MP update only
+            for n in range(s0 + 1, s1):
+                entry = tape[n - s0 - 1]
+                sim.step_into(entry, rebuild=(n % rebuild_every == 0))
+                snapshot_into(sim, entry, POINT_FIELDS)
+                states.append(entry)
+        states.append(ckpt[s1])
         for j in range(s1 - s0 - 1, -1, -1):
-            t0 = tape_struct(tape[j], nn, nm, cap)
-            t1 = tape_struct(tape[j + 1], nn, nm, cap)
+            t0 = tape_struct(states[j], nn, nm, cap)
+            t1 = tape_struct(states[j + 1], nn, nm, cap)
             bn, bc = nxt.struct(), cur.struct()
             check(L.otm_step_adjoint(C.byref(t0), C.byref(t1), C.byref(sim.p), sim.dt,
                                      _ptr(mass), C.byref(bn), C.byref(bc), _ptr(theta), _ptr(ws),
                                      ws_bytes, _ptr(sim.diag), _stream()), "otm_step_adjoint")
             nxt, cur = cur, nxt
-        del tape
+    sim.use_lists(own_lists)
+    del tape
     sim.check_diag()
     return theta, nxt
 

@@ -158,13 +158,16 @@ OTM_DEV FlowPartials flow_partials(const Mat<double>& M, double eb, double x, do
 }
 
 // ---------------------------------------------------------------- K1: LME
-constexpr int kAdjG = 16;       // lanes per MP
-constexpr int kAdjPPL = 3;      // pairs per lane held in registers
-constexpr int kAdjLmeRounds = 8;  // MPs per workgroup = 16 * rounds
+// Supports of up to 40 nodes take 8 lanes with 5 pairs each (one launch);
+// the rare longer ones, up to 48, a second launch with 16 lanes x 3 pairs.
+constexpr int kAdjG = 8, kAdjPPL = 5;
+constexpr int kAdjLongG = 16, kAdjLongPPL = 3;
+static_assert(kAdjLongG * kAdjLongPPL == 48, "the documented adjoint support limit");
+constexpr int kAdjLmeRounds = 8;  // MPs per workgroup = (256 / G) * rounds
 
 struct AdjLmeArgs {
   int64_t n_nodes, n_mp, stride;
-  const double* x;       // nodes of state n+1 [3][n_nodes]
+  const double4* nrec;   // node records of state n+1: 2 I = (x, y, z, du_x)
   const double* xp;      // [3][n_mp]
   const double* lam;     // [3][n_mp]
   const int64_t* off;
@@ -177,9 +180,21 @@ struct AdjLmeArgs {
   otm_diag* diag;
 };
 
+// Handles the MPs with KMIN < K <= G * PPL support nodes; the launch with
+// KMIN = 0 also writes the zero adjoint of empty supports, the one with LAST
+// that of over-long supports, which it reports.
+template <int G, int PPL, int KMIN, bool LAST>
 __global__ __launch_bounds__(256) void k_adj_lme(AdjLmeArgs a) {
-  constexpr int G = kAdjG, PPL = kAdjPPL;
   __shared__ NodeSums<3, 10> tab;
+  if constexpr (KMIN > 0) {
+    // workgroups without a support longer than KMIN leave at once
+    bool any = false;
+    for (int round = 0; round < kAdjLmeRounds; ++round) {
+      const int64_t p = ((int64_t)xcd_block() * kAdjLmeRounds + round) * (256 / G) + threadIdx.x / G;
+      if (p < a.n_mp && threadIdx.x % G == 0) any |= a.off[p + 1] - a.off[p] > KMIN;
+    }
+    if (!__syncthreads_or(any)) return;
+  }
   sums_clear(tab);
   __syncthreads();
   double* const dst[3] = {a.xb, a.xb + a.n_nodes, a.xb + 2 * a.n_nodes};
@@ -189,8 +204,8 @@ __global__ __launch_bounds__(256) void k_adj_lme(AdjLmeArgs a) {
     if (p >= a.n_mp) continue;
     const int64_t o = a.off[p];
     const int K = (int)(a.off[p + 1] - o);
-    if (K == 0 || K > G * PPL) {
-      if (lane == 0) {
+    if (K <= KMIN || K > G * PPL) {
+      if (lane == 0 && ((KMIN == 0 && K == 0) || (LAST && K > G * PPL))) {
         a.xpb[p] = a.xpb[a.n_mp + p] = a.xpb[2 * a.n_mp + p] = 0.0;
         if (K > 0) diag_fail(a.diag, OTM_ERR_SUPPORT, (uint64_t)p);
       }
@@ -208,10 +223,10 @@ __global__ __launch_bounds__(256) void k_adj_lme(AdjLmeArgs a) {
       use[k] = q < K;
       const int64_t qq = o + (use[k] ? q : 0);
       node[k] = a.idx[qq];
-      const int32_t I = node[k];
-      d[k][0] = px - a.x[I];
-      d[k][1] = py - a.x[a.n_nodes + I];
-      d[k][2] = pz - a.x[2 * a.n_nodes + I];
+      const double4 xI = a.nrec[2 * (int64_t)node[k]];
+      d[k][0] = px - xI.x;
+      d[k][1] = py - xI.y;
+      d[k][2] = pz - xI.z;
       Nb[k] = a.Nb[qq];
       Gb[k][0] = a.dNb[qq];
       Gb[k][1] = a.dNb[a.stride + qq];
@@ -327,6 +342,7 @@ __global__ __launch_bounds__(256) void k_adj_lme(AdjLmeArgs a) {
 // ------------------------------------------------ K3: MP update (J2 model)
 constexpr int kAdjMpBlock = 128;
 constexpr int kAdjGather = 8;
+constexpr int kAdjGatherSlots = 4;
 
 struct AdjMpArgs {
   int64_t n_nodes, n_mp, stride;  // stride: pair arrays of state n
@@ -340,9 +356,8 @@ struct AdjMpArgs {
   const double* bed;
   const double* epsbar;
   const double* T;
-  // nodes of state n+1
-  const double* x1;
-  const double* du1;
+  // node records of state n+1: 2 I = (x, y, z, du_x), 2 I + 1 = (du_y, du_z, 0, 0)
+  const double4* nrec;
   // adjoints of state n+1 (in)
   const double* xpb1;   // from K1
   const double* volb1;
@@ -598,12 +613,36 @@ __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
     const int64_t p = base + local;
     double h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (p < a.n_mp) {
-      for (int64_t q = a.off[p] + lane; q < a.off[p + 1]; q += kAdjGather) {
-        const int32_t I = a.idx[q];
-        const double g[3] = {a.dN[q], a.dN[a.stride + q], a.dN[2 * a.stride + q]};
-        const double u[3] = {a.du1[I], a.du1[a.n_nodes + I], a.du1[2 * a.n_nodes + I]};
-        for (int i = 0; i < 3; ++i)
-          for (int j = 0; j < 3; ++j) h[3 * i + j] += u[i] * g[j];
+      // kAdjGatherSlots pairs per lane at a time, all loads issued before the
+      // first use (slots past the support reload pair q0 and are not used)
+      constexpr int L = kAdjGather, S = kAdjGatherSlots;
+      const int64_t q0 = a.off[p], q1 = a.off[p + 1];
+      const double* recd = reinterpret_cast<const double*>(a.nrec);
+      for (int64_t base = q0; base < q1; base += L * S) {
+        int32_t I[S];
+        double g[S][3], u[S][3];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+          const int64_t q = base + k * L + lane;
+          const int64_t qq = q < q1 ? q : q0;
+          I[k] = a.idx[qq];
+          g[k][0] = a.dN[qq];
+          g[k][1] = a.dN[a.stride + qq];
+          g[k][2] = a.dN[2 * a.stride + qq];
+        }
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+          u[k][0] = recd[8 * (int64_t)I[k] + 3];
+          const double2 r1 = reinterpret_cast<const double2*>(a.nrec)[4 * (int64_t)I[k] + 2];
+          u[k][1] = r1.x;
+          u[k][2] = r1.y;
+        }
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+          if (base + k * L + lane >= q1) continue;
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) h[3 * i + j] += u[k][i] * g[k][j];
+        }
       }
     }
     for (int c = 0; c < 9; ++c) h[c] = group_sum<kAdjGather>(h[c]);
@@ -654,6 +693,8 @@ __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
 // their nodes) and then added with one float64 atomic per node and value.
 constexpr int kAdjScatMPs = 256;
 constexpr int kAdjScatLanes = 8;
+constexpr int kAdjScatSlots = 4;
+constexpr int kAdjScatBits = 10;
 
 struct AdjScatArgs {
   int64_t n_nodes, n_mp, stride;
@@ -668,7 +709,7 @@ struct AdjScatArgs {
 };
 
 __global__ __launch_bounds__(256) void k_adj_mp_scatter(AdjScatArgs a) {
-  __shared__ NodeSums<6, 10> tab;
+  __shared__ NodeSums<6, kAdjScatBits> tab;
   sums_clear(tab);
   __syncthreads();
   double* const dst[6] = {a.xb1, a.xb1 + a.n_nodes, a.xb1 + 2 * a.n_nodes,
@@ -683,16 +724,33 @@ __global__ __launch_bounds__(256) void k_adj_mp_scatter(AdjScatArgs a) {
     double Fb[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) Fb[i][j] = a.dfb[(3 * i + j) * n + p];
-    for (int64_t q = a.off[p] + lane; q < a.off[p + 1]; q += kAdjScatLanes) {
-      const int32_t I = a.idx[q];
-      const double w = a.N[q];
-      const double g[3] = {a.dN[q], a.dN[a.stride + q], a.dN[2 * a.stride + q]};
-      double c[6];
-      for (int i = 0; i < 3; ++i) {
-        c[i] = w * xpb[i];
-        c[3 + i] = Fb[i][0] * g[0] + Fb[i][1] * g[1] + Fb[i][2] * g[2];
+    // kAdjScatSlots pairs per lane at a time, loads first (slots past the
+    // support reload pair q0 and are not used)
+    constexpr int L = kAdjScatLanes, S = kAdjScatSlots;
+    const int64_t q0 = a.off[p], q1 = a.off[p + 1];
+    for (int64_t base = q0; base < q1; base += L * S) {
+      int32_t I[S];
+      double w[S], g[S][3];
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const int64_t q = base + k * L + lane;
+        const int64_t qq = q < q1 ? q : q0;
+        I[k] = a.idx[qq];
+        w[k] = a.N[qq];
+        g[k][0] = a.dN[qq];
+        g[k][1] = a.dN[a.stride + qq];
+        g[k][2] = a.dN[2 * a.stride + qq];
       }
-      sums_add(tab, I, c, dst);
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        if (base + k * L + lane >= q1) continue;
+        double c[6];
+        for (int i = 0; i < 3; ++i) {
+          c[i] = w[k] * xpb[i];
+          c[3 + i] = Fb[i][0] * g[k][0] + Fb[i][1] * g[k][1] + Fb[i][2] * g[k][2];
+        }
+        sums_add(tab, I[k], c, dst);
+      }
     }
   }
   __syncthreads();
@@ -710,8 +768,7 @@ struct AdjNodeArgs {
   const double* dub1;
   double* xb;         // out: adjoint of x_n, du_n
   double* dub;
-  double* fb;         // out: adjoint of f_n, m_n
-  double* mb;
+  double4* fmb;       // out: adjoints of f_n and m_n per node (f_x, f_y, f_z, m)
   double dt2;
   int wall;
   double wx[3], wn[3];
@@ -755,14 +812,14 @@ __global__ __launch_bounds__(256) void k_adj_node(AdjNodeArgs a) {
       pb[c] = xsb[c];
     }
   }
-  double fm = 0.0;
+  double fm = 0.0, fb[3];
   for (int c = 0; c < 3; ++c) {
     a.xb[c * n + i] = xb[c];
     a.dub[c * n + i] = pb[c];
-    a.fb[c * n + i] = has_mass ? a.dt2 / mi * pb[c] : 0.0;
+    fb[c] = has_mass ? a.dt2 / mi * pb[c] : 0.0;
     fm += fv[c] * pb[c];
   }
-  a.mb[i] = has_mass ? -a.dt2 * fm / (mi * mi) : 0.0;
+  a.fmb[i] = make_double4(fb[0], fb[1], fb[2], has_mass ? -a.dt2 * fm / (mi * mi) : 0.0);
 }
 
 // ------------------------------------------------------- K6: assembly
@@ -774,10 +831,8 @@ struct AdjAsmArgs {
   const double* vol;
   const double* mass;
   const double* sigma;
-  const double* fb;
-  const double* mb;
-  const double* x1;    // nodes of state n+1
-  const double* du1;
+  const double4* fmb;   // adjoints of f and m per node (K5)
+  const double4* nrec;  // node records of state n+1 (x, y, z, du_x), (du_y, du_z, 0, 0)
   const double* xpb1;  // adjoint of x_p' [3][n_mp]
   const double* dfb;   // adjoint of dF [9][n_mp]
   double* Nb;      // written per pair
@@ -791,11 +846,13 @@ struct AdjAsmArgs {
 // and the force f_I = -sum v sigma grad N_I.  The MP sums of the force terms
 // give the adjoints of sigma and v.
 constexpr int kAdjAsmLanes = 8;
+constexpr int kAdjAsmSlots = 4;   // pairs per lane whose loads are issued together
 __global__ __launch_bounds__(256) void k_adj_assembly(AdjAsmArgs a) {
-  const int64_t p = (int64_t)xcd_block() * (256 / kAdjAsmLanes) + threadIdx.x / kAdjAsmLanes;
-  const int lane = threadIdx.x % kAdjAsmLanes;
+  constexpr int L = kAdjAsmLanes, S = kAdjAsmSlots;
+  const int64_t p = (int64_t)xcd_block() * (256 / L) + threadIdx.x / L;
+  const int lane = threadIdx.x % L;
   if (p >= a.n_mp) return;
-  const int64_t n = a.n_mp, nn = a.n_nodes;
+  const int64_t n = a.n_mp;
   const double v = a.vol[p], mp = a.mass[p];
   double s[6];
   for (int c = 0; c < 6; ++c) s[c] = a.sigma[c * n + p];
@@ -804,29 +861,54 @@ __global__ __launch_bounds__(256) void k_adj_assembly(AdjAsmArgs a) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) Fb[i][j] = a.dfb[(3 * i + j) * n + p];
   double sb[6] = {0, 0, 0, 0, 0, 0}, vb = 0.0;
-  for (int64_t q = a.off[p] + lane; q < a.off[p + 1]; q += kAdjAsmLanes) {
-    const int32_t I = a.idx[q];
-    const double g[3] = {a.dN[q], a.dN[a.stride + q], a.dN[2 * a.stride + q]};
-    const double f[3] = {a.fb[I], a.fb[nn + I], a.fb[2 * nn + I]};
-    const double xI[3] = {a.x1[I], a.x1[nn + I], a.x1[2 * nn + I]};
-    const double u[3] = {a.du1[I], a.du1[nn + I], a.du1[2 * nn + I]};
-    a.Nb[q] = xI[0] * xpb[0] + xI[1] * xpb[1] + xI[2] * xpb[2] + a.mb[I] * mp;
-    // f_I = -v sigma g
-    const double sf[3] = {s[0] * f[0] + s[3] * f[1] + s[5] * f[2],
-                          s[3] * f[0] + s[1] * f[1] + s[4] * f[2],
-                          s[5] * f[0] + s[4] * f[1] + s[2] * f[2]};
-    for (int j = 0; j < 3; ++j)
-      a.dNb[j * a.stride + q] = Fb[0][j] * u[0] + Fb[1][j] * u[1] + Fb[2][j] * u[2] - v * sf[j];
-    vb -= sf[0] * g[0] + sf[1] * g[1] + sf[2] * g[2];
-    sb[0] -= v * f[0] * g[0];
-    sb[1] -= v * f[1] * g[1];
-    sb[2] -= v * f[2] * g[2];
-    sb[3] -= v * (f[0] * g[1] + f[1] * g[0]);
-    sb[4] -= v * (f[1] * g[2] + f[2] * g[1]);
-    sb[5] -= v * (f[0] * g[2] + f[2] * g[0]);
+  const int64_t q0 = a.off[p], q1 = a.off[p + 1];
+  const double2* rec2 = reinterpret_cast<const double2*>(a.nrec);
+  // S pairs per lane at a time: every load of the chunk is issued before the
+  // first use (slots past the support reload pair q0 and are not used)
+  for (int64_t base = q0; base < q1; base += L * S) {
+    int32_t I[S];
+    double g[S][3];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const int64_t q = base + k * L + lane;
+      const int64_t qq = q < q1 ? q : q0;
+      I[k] = a.idx[qq];
+      g[k][0] = a.dN[qq];
+      g[k][1] = a.dN[a.stride + qq];
+      g[k][2] = a.dN[2 * a.stride + qq];
+    }
+    double4 r0[S], fm[S];
+    double2 r1[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      r0[k] = a.nrec[2 * (int64_t)I[k]];
+      r1[k] = rec2[4 * (int64_t)I[k] + 2];   // (du_y, du_z)
+      fm[k] = a.fmb[I[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const int64_t q = base + k * L + lane;
+      if (q >= q1) continue;
+      const double f[3] = {fm[k].x, fm[k].y, fm[k].z};
+      const double u[3] = {r0[k].w, r1[k].x, r1[k].y};
+      a.Nb[q] = r0[k].x * xpb[0] + r0[k].y * xpb[1] + r0[k].z * xpb[2] + fm[k].w * mp;
+      // f_I = -v sigma g
+      const double sf[3] = {s[0] * f[0] + s[3] * f[1] + s[5] * f[2],
+                            s[3] * f[0] + s[1] * f[1] + s[4] * f[2],
+                            s[5] * f[0] + s[4] * f[1] + s[2] * f[2]};
+      for (int j = 0; j < 3; ++j)
+        a.dNb[j * a.stride + q] = Fb[0][j] * u[0] + Fb[1][j] * u[1] + Fb[2][j] * u[2] - v * sf[j];
+      vb -= sf[0] * g[k][0] + sf[1] * g[k][1] + sf[2] * g[k][2];
+      sb[0] -= v * f[0] * g[k][0];
+      sb[1] -= v * f[1] * g[k][1];
+      sb[2] -= v * f[2] * g[k][2];
+      sb[3] -= v * (f[0] * g[k][1] + f[1] * g[k][0]);
+      sb[4] -= v * (f[1] * g[k][2] + f[2] * g[k][1]);
+      sb[5] -= v * (f[0] * g[k][2] + f[2] * g[k][0]);
+    }
   }
-  for (int c = 0; c < 6; ++c) sb[c] = group_sum<kAdjAsmLanes>(sb[c]);
-  vb = group_sum<kAdjAsmLanes>(vb);
+  for (int c = 0; c < 6; ++c) sb[c] = group_sum<L>(sb[c]);
+  vb = group_sum<L>(vb);
   if (lane == 0) {
     for (int c = 0; c < 6; ++c) a.sigb[c * n + p] = sb[c];
     a.volb[p] += vb;
@@ -854,8 +936,9 @@ __global__ __launch_bounds__(256) void k_adj_theta(const double* part, int64_t n
 size_t adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp) {
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
   const int64_t nb = (n_mp + kAdjMpBlock - 1) / kAdjMpBlock + 1;
-  return al(sizeof(double) * 3 * (size_t)n_mp) + al(sizeof(double) * 4 * (size_t)n_nodes) +
-         al(sizeof(double) * 3 * (size_t)nb) + al(sizeof(double) * 9 * (size_t)n_mp);
+  return al(sizeof(double) * 3 * (size_t)n_mp) + al(sizeof(double4) * (size_t)n_nodes) +
+         al(sizeof(double) * 3 * (size_t)nb) + al(sizeof(double) * 9 * (size_t)n_mp) +
+         al(sizeof(double4) * 2 * (size_t)n_nodes);
 }
 
 void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_params& p,
@@ -866,25 +949,37 @@ void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_param
   char* c = (char*)ws;
   double* xpb = (double*)c;
   c += al(sizeof(double) * 3 * (size_t)nm);
-  double* fb = (double*)c;
-  double* mb = fb + 3 * nn;
-  c += al(sizeof(double) * 4 * (size_t)nn);
+  double4* fmb = (double4*)c;
+  c += al(sizeof(double4) * (size_t)nn);
   double* theta_part = (double*)c;
   c += al(sizeof(double) * 3 * (size_t)((nm + kAdjMpBlock - 1) / kAdjMpBlock + 1));
   double* dfb = (double*)c;
+  c += al(sizeof(double) * 9 * (size_t)nm);
+  double4* nrec = (double4*)c;
 
+  if (nm > 0 && nn > 0) {
+    // node records of state n+1, the forward's layout
+    otm_state ns{};
+    ns.n_nodes = nn;
+    ns.x = const_cast<double*>(t1.x);
+    ns.du = const_cast<double*>(t1.du);
+    launch_pack_nodes(ns, nrec, s);
+  }
   if (nm > 0) {
     // K1: shape functions of state n+1
-    AdjLmeArgs la{nn, nm, t1.pair_stride, t1.x, t1.xp, t1.lam, t1.nbr_offsets, t1.nbr_idx,
+    AdjLmeArgs la{nn, nm, t1.pair_stride, nrec, t1.xp, t1.lam, t1.nbr_offsets, t1.nbr_idx,
                   b1.N, b1.dN, p.beta, xpb, b1.x, diag};
     const int per = (256 / kAdjG) * kAdjLmeRounds;
-    k_adj_lme<<<(unsigned)((nm + per - 1) / per), 256, 0, s>>>(la);
+    k_adj_lme<kAdjG, kAdjPPL, 0, false><<<(unsigned)((nm + per - 1) / per), 256, 0, s>>>(la);
+    const int per_long = (256 / kAdjLongG) * kAdjLmeRounds;
+    k_adj_lme<kAdjLongG, kAdjLongPPL, kAdjG * kAdjPPL, true>
+        <<<(unsigned)((nm + per_long - 1) / per_long), 256, 0, s>>>(la);
     // K3: MP update per MP (adjoint of dF to the workspace), then its node terms
     AdjMpArgs ma;
     ma.n_nodes = nn; ma.n_mp = nm; ma.stride = t0.pair_stride;
     ma.off = t0.nbr_offsets; ma.idx = t0.nbr_idx; ma.N = t0.N; ma.dN = t0.dN;
     ma.vol = t0.vol; ma.Fd = t0.Fd; ma.bed = t0.bed; ma.epsbar = t0.epsbar; ma.T = t0.T;
-    ma.x1 = t1.x; ma.du1 = t1.du;
+    ma.nrec = nrec;
     ma.xpb1 = xpb; ma.volb1 = b1.vol; ma.Fdb1 = b1.Fd; ma.bedb1 = b1.bed; ma.epsb1 = b1.epsbar;
     ma.Tb1 = b1.T; ma.sigb1 = b1.sigma;
     ma.volb = b0.vol; ma.Fdb = b0.Fd; ma.bedb = b0.bed; ma.epsb = b0.epsbar; ma.Tb = b0.T;
@@ -904,7 +999,7 @@ void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_param
     // K5: node update
     AdjNodeArgs na;
     na.n = nn; na.x = t0.x; na.du = t0.du; na.m = t0.m; na.f = t0.f;
-    na.xb1 = b1.x; na.dub1 = b1.du; na.xb = b0.x; na.dub = b0.du; na.fb = fb; na.mb = mb;
+    na.xb1 = b1.x; na.dub1 = b1.du; na.xb = b0.x; na.dub = b0.du; na.fmb = fmb;
     na.dt2 = dt * dt;
     na.wall = p.wall_enabled;
     for (int k = 0; k < 3; ++k) { na.wx[k] = p.wall_x[k]; na.wn[k] = p.wall_n[k]; }
@@ -913,8 +1008,7 @@ void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_param
   if (nm > 0) {
     // K6: pair adjoints of state n, and the adjoints of sigma and v
     AdjAsmArgs aa{nn, nm, t0.pair_stride, t0.nbr_offsets, t0.nbr_idx, t0.dN, t0.vol,
-                  mass, t0.sigma, fb, mb, t1.x, t1.du, xpb, dfb, b0.N, b0.dN, b0.sigma,
-                  b0.vol};
+                  mass, t0.sigma, fmb, nrec, xpb, dfb, b0.N, b0.dN, b0.sigma, b0.vol};
     k_adj_assembly<<<(unsigned)((nm + (256 / kAdjAsmLanes) - 1) / (256 / kAdjAsmLanes)), 256, 0,
                      s>>>(aa);
   }

@@ -300,9 +300,18 @@ otm_status otm_init(otm_state* st, const otm_params* p, double dt, const double*
 
 static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
                             int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
-                            hipEvent_t* ev, hipStream_t s) {
+                            hipEvent_t* ev, hipStream_t s, const otm_lists* next = nullptr) {
   otm_status e;
   if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
+  if (next != nullptr) {
+    const size_t rs = st->precision == OTM_FP64 ? 8 : 4;
+    if (!dev_ok(next->nbr_offsets, 8) || !dev_ok(next->nbr_idx, 4) || !dev_ok(next->N, 8) ||
+        !dev_ok(next->dN, rs))
+      return OTM_ERR_ARG;
+    if (next->nbr_offsets == st->nbr_offsets || next->nbr_idx == st->nbr_idx ||
+        next->N == st->N || next->dN == st->dN)
+      return OTM_ERR_ARG;
+  }
   if (!(dt > 0)) return OTM_ERR_ARG;
   if (scatter_mode != OTM_SCATTER_ATOMIC && scatter_mode != OTM_SCATTER_SEGMENTED)
     return OTM_ERR_ARG;
@@ -317,14 +326,41 @@ static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32
   mark(ev, 1, s);
   launch_mp_update(*st, *p, dt, w.nodes, diag, s);
   mark(ev, 2, s);
-  refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true, stab);
-  return hip_status();
+  if (next == nullptr) {
+    refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true, stab);
+    return hip_status();
+  }
+  otm_state to = *st;
+  to.nbr_offsets = next->nbr_offsets;
+  to.nbr_idx = next->nbr_idx;
+  to.N = next->N;
+  to.dN = next->dN;
+  if (rebuild == 0) {  // the lists of step n carry over
+    if (hipMemcpyAsync(to.nbr_offsets, st->nbr_offsets, sizeof(int64_t) * (size_t)(st->n_mp + 1),
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return OTM_ERR_HIP;
+    if (st->pair_capacity > 0 &&
+        hipMemcpyAsync(to.nbr_idx, st->nbr_idx, sizeof(int32_t) * (size_t)st->pair_capacity,
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return OTM_ERR_HIP;
+  }
+  refresh_impl(to, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true, stab);
+  if ((e = hip_status()) != OTM_OK) return e;
+  *st = to;
+  return OTM_OK;
 }
 
 otm_status otm_step(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
                     int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
                     hipStream_t s) {
   return step_impl(st, p, dt, rebuild, scatter_mode, ws, ws_bytes, diag, nullptr, s);
+}
+
+otm_status otm_step_into(otm_state* st, const otm_lists* next, const otm_params* p, double dt,
+                         int32_t rebuild, int32_t scatter_mode, void* ws, size_t ws_bytes,
+                         otm_diag* diag, hipStream_t s) {
+  if (next == nullptr) return OTM_ERR_ARG;
+  return step_impl(st, p, dt, rebuild, scatter_mode, ws, ws_bytes, diag, nullptr, s, next);
 }
 
 otm_status otm_step_profiled(otm_state* st, const otm_params* p, double dt, int32_t rebuild,

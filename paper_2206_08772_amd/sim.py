@@ -204,6 +204,35 @@ class Sim:
               "otm_step")
         self.n += 1
 
+    def step_into(self, lists, rebuild=True):
+        """One step whose new support lists and shape functions go to the
+        tensors of ``lists`` (a dict with offsets, idx, N, dN shaped like this
+        Sim's); afterwards the Sim uses those tensors, and the ones it used
+        before still hold the previous step's lists, unchanged."""
+        out = _lib.Lists()
+        out.nbr_offsets = _ptr(lists["offsets"]).value
+        out.nbr_idx = _ptr(lists["idx"]).value
+        out.N = _ptr(lists["N"]).value
+        out.dN = _ptr(lists["dN"]).value
+        check(lib().otm_step_into(C.byref(self.st), C.byref(out), C.byref(self.p), self.dt,
+                                  1 if rebuild else 0, self.mode, self.ws.ptr, self.ws.nbytes,
+                                  _ptr(self.diag), _stream()), "otm_step_into")
+        self.offsets, self.idx, self.N, self.dN = (lists["offsets"], lists["idx"], lists["N"],
+                                                   lists["dN"])
+        self.n += 1
+
+    def use_lists(self, lists):
+        """Point the state at other list / shape-function tensors (no copy).
+        Graphs captured before keep the old addresses."""
+        for k in ("offsets", "idx", "N", "dN"):
+            t = lists[k]
+            ref = getattr(self, k)
+            if t.shape != ref.shape or t.dtype != ref.dtype or t.device != ref.device:
+                raise ValueError(f"lists[{k!r}] does not match the state's {k}")
+        self.offsets, self.idx, self.N, self.dN = (lists["offsets"], lists["idx"], lists["N"],
+                                                   lists["dN"])
+        self._fill_state()
+
     def run(self, steps, rebuild_every=1):
         for _ in range(steps):
             self.step(rebuild=((self.n + 1) % rebuild_every == 0))

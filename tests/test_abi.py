@@ -141,3 +141,27 @@ def test_kernel_resource_parser():
     r = kernel_resources(txt)
     assert r["k_one"] == {"VGPRs": 120, "AGPRs": 0, "ScratchSize": 0, "VGPRs Spill": 0}
     assert r["k_two"] == {"VGPRs": 256, "AGPRs": 58, "ScratchSize": 16, "VGPRs Spill": 4}
+
+
+def test_step_into_rejects_missing_misaligned_or_aliased_lists(L):
+    """otm_step_into checks the target lists before anything is enqueued."""
+    lib = L.lib()
+    p = _params(L)
+    st = _fake_state(L)
+    ws, diag = C.c_void_p(1 << 20), C.c_void_p(1 << 20)
+
+    def call(nxt):
+        return lib.otm_step_into(C.byref(st), nxt, C.byref(p), 1e-3, 1, 0, ws, 1 << 30, diag,
+                                 None)
+
+    assert call(None) == L.OTM_ERR_ARG
+    nxt = L.Lists()
+    nxt.nbr_offsets, nxt.nbr_idx, nxt.N, nxt.dN = 2 << 20, 2 << 20, 2 << 20, (2 << 20) + 4
+    assert call(C.byref(nxt)) == L.OTM_ERR_ARG          # misaligned float64 dN
+    nxt.dN = 2 << 20
+    nxt.N = st.N                                        # overlaps the state's N
+    before = (st.nbr_offsets, st.nbr_idx, st.N, st.dN)
+    assert call(C.byref(nxt)) == L.OTM_ERR_ARG
+    assert (st.nbr_offsets, st.nbr_idx, st.N, st.dN) == before
+    nxt.N, nxt.nbr_offsets = 2 << 20, 0                 # missing offsets
+    assert call(C.byref(nxt)) == L.OTM_ERR_ARG

@@ -33,13 +33,22 @@ def _gpu_grad(problem, speed, p, target):
     return float(loss), theta.grad.cpu().numpy(), float(sp.grad)
 
 
-def test_adjoint_matches_complex_step_oracle():
+@pytest.mark.parametrize("radius_scale", [1.0, 1.15])
+def test_adjoint_matches_complex_step_oracle(radius_scale):
     """Tiny J2/JC rod, 8 steps, checkpoints every 3: gradients of the final
-    position mismatch with respect to A, B, n and the impact speed."""
+    position mismatch with respect to A, B, n and the impact speed.  The wider
+    search radius gives supports of 20 to 45 nodes, so the MPs above 40 go
+    through the adjoint's long-support launch."""
     w = W.taylor_rod(h=0.8e-3, seed=5, radius=2.4e-3, length=6.4e-3, steps=8, name="tiny_rod")
     p = W.params_from_workload(w)
+    r = p["r_list"] * radius_scale
+    p = dict(p, r_list=r, cell_size=max(p["cell_size"], r))
     steps = 8
     lists, _ = OG.nominal_lists(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, steps)
+    K = np.concatenate([np.diff(off) for off, _ in lists[1:]])
+    assert K.max() <= 48
+    if radius_scale > 1:
+        assert (K > 40).sum() > 50
     # target: the oracle with perturbed hardening constants
     pt = dict(p, A=p["A"] * 1.05, B=p["B"] * 0.95, n=p["n"] + 0.02)
     tgt_lists, st_t = OG.nominal_lists(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, pt,
