@@ -319,6 +319,8 @@ def main():
                          "(comma separated, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="print only the adjoint/forward time ratio (one JSON line)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a reference kernel "
                          "of known traffic for HBM byte counters)")
@@ -339,6 +341,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.adjoint_only:
+        print(json.dumps(adjoint_ratio()), flush=True)
+        return
     w = W.config_by_name(args.workload)
 
     main_run = run_variant(w, "fp64", "atomic", args.steps, args.warmup)
