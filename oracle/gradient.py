@@ -75,3 +75,42 @@ def complex_step_gradient(x_nodes, x_mp, vol, mass, v0, p, steps, lists, x_targe
     st = rollout(x_nodes, x_mp, vol, mass, v0c, p, steps, lists, complex_step=True)
     grads["speed"] = loss(st, x_target).imag / h
     return grads
+
+
+# ------------------------------------------------- one step as a state map
+STEP_FIELDS = ("x", "du", "vol", "F", "be", "epsbar", "T", "sigma", "N", "dN")
+
+
+def step_map(st, p, lists_next):
+    """One step (Alg. 1) as a map of the state fields STEP_FIELDS: the lumped
+    mass and force are assembled from the state's own N, grad N, sigma and v
+    (nodal mass / residual equations), then the node update, the MP update
+    with the shape functions of step n, and the shape functions of step n+1 on
+    the given (frozen) lists.  Returns a new State; ``st`` is not changed."""
+    s = st.copy()
+    S.assemble(s, p)
+    S.node_update(s, p)
+    S.mp_update(s, p)
+    s.offsets, s.idx = lists_next
+    S.shape(s, p)
+    return s
+
+
+def step_jvp(st, p, lists_next, direction=None, param=None):
+    """Directional derivative of step_map by complex step.  ``direction`` maps
+    some of STEP_FIELDS to tangent arrays of their shapes; ``param`` names a
+    material constant to differentiate by (per unit of that constant).
+    Returns {field: derivative array} for every field in STEP_FIELDS."""
+    pc = dict(p, spectral="series", polish=3)
+    s = st.copy()
+    for k in STEP_FIELDS + ("xp", "lam", "m", "f"):
+        setattr(s, k, np.asarray(getattr(s, k), complex))
+    h = 1e-20
+    if direction:
+        for k, d in direction.items():
+            setattr(s, k, getattr(s, k) + 1j * h * np.asarray(d, float))
+    if param is not None:
+        h = 1e-20 * abs(p[param])
+        pc[param] = p[param] + 1j * h
+    out = step_map(s, pc, lists_next)
+    return {k: np.asarray(getattr(out, k)).imag / h for k in STEP_FIELDS}

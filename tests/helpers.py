@@ -30,3 +30,28 @@ def gpu_fields(g, x0_nodes, xp0, T_r):
 def compare(gf, of, fields=None):
     keys = fields or [k for k in of if k in gf]
     return {k: rel_err(gf[k], of[k]) for k in keys}
+
+
+def step_directions(st, rng):
+    """Seeded tangent directions for the one-step map, one per state field,
+    each scaled to its field: symmetric for b^e and sigma (stored as six
+    components), and for epsbar and T only where the MP has flowed or
+    heated (epsbar > 0, T > T at rest), away from the kinks at zero flow and
+    at the reference temperature."""
+    def sym(a):
+        return 0.5 * (a + np.swapaxes(a, -1, -2))
+    n = st.xp.shape[0]
+    rms = lambda a: float(np.sqrt(np.mean(np.abs(a) ** 2))) or 1.0
+    T0 = float(st.T.min())
+    return dict(
+        x=rng.standard_normal(st.x.shape) * rms(st.du),
+        du=rng.standard_normal(st.du.shape) * rms(st.du),
+        vol=rng.standard_normal(n) * st.vol,
+        F=rng.standard_normal((n, 3, 3)) * rms(st.F - np.eye(3)),
+        be=sym(rng.standard_normal((n, 3, 3))) * rms(st.be - np.eye(3)),
+        epsbar=rng.standard_normal(n) * st.epsbar,
+        T=rng.standard_normal(n) * (st.T - T0),
+        sigma=sym(rng.standard_normal((n, 3, 3))) * rms(st.sigma),
+        N=rng.standard_normal(st.N.shape) * st.N,
+        dN=rng.standard_normal(st.dN.shape) * rms(st.dN),
+    )

@@ -115,3 +115,152 @@ def test_adjoint_against_finite_differences_adjoint_rod():
     rel["speed"] = abs(gsp - fd) / abs(fd)
     print("adjoint vs central differences (relative):", rel)
     assert all(v <= 1e-4 for v in rel.values()), rel
+
+
+# ------------------------------------------------------ dot-product test
+SYM = ((0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2))   # stored order of b^e and sigma
+
+
+def _gpu_layout(field, a):
+    """Oracle array -> the library's device layout (as a host array)."""
+    a = np.asarray(a, np.float64)
+    if field in ("x", "du", "xp", "lam", "f"):
+        return np.ascontiguousarray(a.T)
+    if field == "F":
+        return np.ascontiguousarray((a - np.eye(3)).reshape(-1, 9).T)
+    if field == "be":
+        a = a - np.eye(3)
+    if field in ("be", "sigma"):
+        return np.stack([a[:, i, j] for i, j in SYM])
+    if field == "dN":
+        return np.ascontiguousarray(a.T)
+    return a
+
+
+def _tangent_layout(field, a):
+    """A tangent (or derivative) of an oracle field in the stored components
+    the adjoint is taken with respect to."""
+    a = np.asarray(a, np.float64)
+    if field in ("x", "du", "dN"):
+        return np.ascontiguousarray(a.T)
+    if field == "F":
+        return np.ascontiguousarray(a.reshape(-1, 9).T)
+    if field in ("be", "sigma"):
+        return np.stack([a[:, i, j] for i, j in SYM])
+    return a
+
+
+BAR_OF = {"x": "x", "du": "du", "vol": "vol", "F": "Fd", "be": "bed", "epsbar": "epsbar",
+          "T": "T", "sigma": "sigma", "N": "N", "dN": "dN"}
+
+
+def _tape(st, cap):
+    from paper_2206_08772_amd._lib import Tape
+    from paper_2206_08772_amd.sim import _ptr
+    keep = {}
+    t = Tape()
+    t.n_nodes, t.n_mp, t.pair_stride = st.x.shape[0], st.xp.shape[0], cap
+    for k, name in (("x", "x"), ("du", "du"), ("m", "m"), ("f", "f"), ("xp", "xp"),
+                    ("vol", "vol"), ("lam", "lam"), ("F", "Fd"), ("be", "bed"),
+                    ("epsbar", "epsbar"), ("T", "T"), ("sigma", "sigma")):
+        keep[name] = torch.from_numpy(_gpu_layout(k, getattr(st, k))).cuda()
+    P = st.idx.shape[0]
+    N = np.zeros(cap)
+    N[:P] = st.N
+    dN = np.zeros((3, cap))
+    dN[:, :P] = st.dN.T
+    keep["N"] = torch.from_numpy(N).cuda()
+    keep["dN"] = torch.from_numpy(dN).cuda()
+    keep["offsets"] = torch.from_numpy(np.asarray(st.offsets, np.int64)).cuda()
+    idx = np.zeros(cap, np.int32)
+    idx[:P] = st.idx
+    keep["idx"] = torch.from_numpy(idx).cuda()
+    for name in ("x", "du", "m", "f", "xp", "vol", "lam", "Fd", "bed", "epsbar", "T", "sigma",
+                 "N", "dN"):
+        setattr(t, name, _ptr(keep[name]).value)
+    t.nbr_offsets = _ptr(keep["offsets"]).value
+    t.nbr_idx = _ptr(keep["idx"]).value
+    return t, keep
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+def test_adjoint_step_dot_products_against_oracle_jvp():
+    """For one step of the tiny rod (state after 4 steps: plastic flow, heating
+    and wall contact under way), <bar_n, delta> from otm_step_adjoint equals
+    <bar_{n+1}, J delta> from the oracle's complex-step derivative of the
+    one-step map, for every (input field, output field) block: a seeded
+    adjoint on one output field at a time, a seeded tangent of one input field
+    at a time.  The hardening-constant gradient is checked the same way."""
+    import ctypes as C
+    from oracle import step as OS
+    from paper_2206_08772_amd import _lib
+    from paper_2206_08772_amd.adjoint import Bars
+    from paper_2206_08772_amd.sim import _ptr, _stream, make_params, new_diag, read_diag
+    from tests.helpers import step_directions
+    w = W.taylor_rod(h=0.8e-3, seed=5, radius=2.4e-3, length=6.4e-3, steps=8, name="tiny_rod")
+    p = W.params_from_workload(w)
+    lists, _ = OG.nominal_lists(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, 5)
+    st = OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, 4, lists)
+    s1 = OG.step_map(st, p, lists[5])
+    OS.assemble(s1, p)
+    assert st.epsbar.max() > 0
+    dirs = step_directions(st, np.random.default_rng(1))
+    jvp = {k: OG.step_jvp(st, p, lists[5], direction={k: dirs[k]}) for k in OG.STEP_FIELDS}
+    jvp_th = {k: OG.step_jvp(st, p, lists[5], param=k) for k in ("A", "B", "n")}
+
+    L = _lib.lib()
+    nn, nm = st.x.shape[0], st.xp.shape[0]
+    cap = max(st.idx.shape[0], s1.idx.shape[0])
+    t0, keep0 = _tape(st, cap)
+    t1, keep1 = _tape(s1, cap)
+    mass = torch.from_numpy(np.asarray(w.mass_mp, np.float64)).cuda()
+    pp = make_params(p)
+    ws_bytes = int(L.otm_adjoint_workspace_bytes(nn, nm))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    diag = new_diag(torch.device("cuda"))
+    rng = np.random.default_rng(2)
+    P1 = s1.idx.shape[0]
+    worst = 0.0
+    for o in OG.STEP_FIELDS:
+        nxt, cur = Bars(nn, nm, cap, "cuda"), Bars(nn, nm, cap, "cuda")
+        ref = _tangent_layout(o, jvp[o][o])          # shape of the stored output field
+        sbar = rng.standard_normal(ref.shape)        # pairs of step n+1 only
+        tgt = getattr(nxt, BAR_OF[o])
+        if o in ("N", "dN"):
+            tgt[..., :P1].copy_(torch.from_numpy(np.ascontiguousarray(sbar[..., :P1])))
+        else:
+            tgt.copy_(torch.from_numpy(sbar))
+        theta = torch.zeros(3, dtype=torch.float64, device="cuda")
+        bn, bc = nxt.struct(), cur.struct()
+        _lib.check(L.otm_step_adjoint(C.byref(t0), C.byref(t1), C.byref(pp), p["dt"], _ptr(mass),
+                                      C.byref(bn), C.byref(bc), _ptr(theta), _ptr(ws), ws_bytes,
+                                      _ptr(diag), _stream()), "otm_step_adjoint")
+        torch.cuda.synchronize()
+        P0 = st.idx.shape[0]
+        scales, rows = [], []
+        for i in OG.STEP_FIELDS:
+            bar_i = getattr(cur, BAR_OF[i]).cpu().numpy()
+            if i in ("N", "dN"):
+                bar_i = bar_i[..., :P0]
+            delta = _tangent_layout(i, dirs[i])
+            lhs = float((bar_i * delta).sum())
+            jo = _tangent_layout(o, jvp[i][o])
+            rhs = float((sbar * jo).sum())
+            scale = float(np.abs(sbar * jo).sum())
+            rows.append((i, lhs, rhs, scale))
+            scales.append(scale)
+        top = max(scales)
+        for i, lhs, rhs, scale in rows:
+            tol = 1e-8 * scale + 1e-12 * top
+            assert abs(lhs - rhs) <= tol, (o, i, lhs, rhs, scale)
+            if scale > 0:
+                worst = max(worst, abs(lhs - rhs) / scale)
+        th = theta.cpu().numpy()
+        for k, name in enumerate(("A", "B", "n")):
+            jo = _tangent_layout(o, jvp_th[name][o])
+            rhs = float((sbar * jo).sum())
+            scale = float(np.abs(sbar * jo).sum())
+            assert abs(th[k] - rhs) <= 1e-8 * scale, (o, name, th[k], rhs, scale)
+    code, _ = read_diag(diag)
+    assert code == _lib.OTM_OK
+    print(f"adjoint dot products: worst |<bar_n, d> - <bar_n+1, J d>| / scale = {worst:.2e}")

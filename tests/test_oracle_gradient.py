@@ -49,3 +49,45 @@ def test_complex_step_matches_central_differences(setup):
                             steps, lists), target)
     fd = (lp - lm) / (2 * e)
     assert abs(g["speed"] - fd) <= 1e-4 * abs(fd), (g["speed"], fd)
+
+
+@pytest.fixture(scope="module")
+def one_step():
+    """State of the tiny rod after 4 steps (plastic flow and heating under way)
+    and the nominal lists of step 5."""
+    w = W.taylor_rod(h=0.8e-3, seed=5, radius=2.4e-3, length=6.4e-3, steps=8, name="tiny_rod")
+    p = W.params_from_workload(w)
+    lists, _ = OG.nominal_lists(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, 5)
+    st = OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, 4, lists)
+    return st, p, lists[5]
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+@pytest.mark.parametrize("field", OG.STEP_FIELDS + ("A", "B", "n"))
+def test_step_jvp_matches_central_differences(one_step, field):
+    """The complex-step derivative of the one-step map along a seeded direction
+    of each state field (and by each hardening constant) against central
+    differences of the real map, relative step 1e-4 (no branch changes; the
+    differences' own error is at most 2.5e-6 here), for every output field."""
+    from tests.helpers import rel_err, step_directions
+    st, p, nxt = one_step
+    assert st.epsbar.max() > 0 and st.T.max() > st.T.min()
+    if field in OG.STEP_FIELDS:
+        d = step_directions(st, np.random.default_rng(1))[field]
+        jvp = OG.step_jvp(st, p, nxt, direction={field: d})
+        e = 1e-4
+
+        def G(sgn):
+            s = st.copy()
+            setattr(s, field, getattr(s, field) + sgn * e * d)
+            return OG.step_map(s, p, nxt)
+    else:
+        jvp = OG.step_jvp(st, p, nxt, param=field)
+        e = 1e-4 * abs(p[field])
+
+        def G(sgn):
+            return OG.step_map(st, dict(p, **{field: p[field] + sgn * e}), nxt)
+    a, b = G(1), G(-1)
+    errs = {o: rel_err(jvp[o], (getattr(a, o) - getattr(b, o)) / (2 * e)) for o in OG.STEP_FIELDS}
+    bad = {o: v for o, v in errs.items() if not v < 2e-5}
+    assert not bad, bad
