@@ -227,3 +227,29 @@ def j2_update(p, dF, be_n, epsbar_n, T_n, J_new, dt, spectral="eigh", polish=0):
     else:
         T_new = T_n + 0.0 * deps
     return sigma, be_new, epsbar_new, T_new, deps
+
+
+# ------------------------------------------------------- ductile fracture
+def triaxiality(sigma):
+    """Stress triaxiality eta = sigma_m / sigma_v of Cauchy stresses (n,3,3):
+    mean stress over the von Mises stress (Sec. 4.2, fracture criterion; the
+    printed p = lambda tr(eps^e) is read as the mean stress, K tr(eps^e) / J
+    for the Hencky law).  0 where the stress deviator vanishes."""
+    sm = np.trace(sigma, axis1=-2, axis2=-1) / 3.0
+    dev = sigma - sm[..., None, None] * np.eye(3)
+    sv = np.sqrt(1.5 * (dev * dev).sum(axis=(-1, -2)))
+    return np.where(sv > 0, sm / np.where(sv > 0, sv, 1.0), 0.0)
+
+
+def jc_fracture_strain(p, eta, deps, dt, T):
+    """Critical equivalent plastic strain of the Johnson-Cook fracture
+    criterion (Sec. 4.2): [d1 + d2 exp(d3 eta)] [1 + d4 ln(rate*)]
+    [1 + d5 T*], rate* = max(deps / (dt rate0), 1) as in the flow stress and
+    T* the homologous temperature clamped to [0, 1]."""
+    d1, d2, d3, d4, d5 = (float(v) for v in p["jc_d"])
+    ratio = deps / (dt * p["eps_dot0"])
+    rate = np.log(np.where(ratio > 1.0, ratio, 1.0))
+    ts = (T - p["T_r"]) / (p["T_m"] - p["T_r"])
+    ts = np.clip(ts, 0.0, 1.0)
+    with np.errstate(over="ignore"):   # near-hydrostatic compression: eps_f = inf
+        return (d1 + d2 * np.exp(d3 * eta)) * (1.0 + d4 * rate) * (1.0 + d5 * ts)

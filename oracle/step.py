@@ -43,7 +43,7 @@ import dataclasses
 
 import numpy as np
 
-from . import lme, material, search
+from . import contact, lme, material, search
 
 
 @dataclasses.dataclass
@@ -70,6 +70,12 @@ class State:
     # MP update (None before the first step)
     xp_prev: np.ndarray = None
     dF: np.ndarray = None
+    # chip formation (Sec. 4.2): MPs that met the fracture criterion (carry
+    # no stress from then on), tangential contact gaps of the nodes and the
+    # time of the state (moves the tool)
+    failed: np.ndarray = None
+    gT: np.ndarray = None
+    clock: float = 0.0
 
     def copy(self):
         return State(**{k: (v.copy() if isinstance(v, np.ndarray) else v)
@@ -114,11 +120,17 @@ def underintegration_error(st, mp_of_pair):
 def node_update(st, p):
     """Central difference with lumped mass, then the rigid-wall projection."""
     dt = p["dt"]
+    f = st.f
+    if p.get("tool"):
+        # rigid tool: penalty contact force at x_n, tool at t_n
+        fc, st.gT = contact.tool_forces(st.x, st.du, st.gT, st.clock, p)
+        f = f + fc
+        st.clock = st.clock + dt
     # a node outside every support has no lumped mass and no force: it keeps
     # its increment (the central difference applies to nodes with mass)
     has_mass = st.m.real > 0
     m_safe = np.where(has_mass, st.m, 1.0)
-    du = st.du + np.where(has_mass[:, None], dt * dt * st.f / m_safe[:, None], 0.0)
+    du = st.du + np.where(has_mass[:, None], dt * dt * f / m_safe[:, None], 0.0)
     xs = st.x + du
     if p["wall"]:
         nrm = np.asarray(p["wall_n"], float)
@@ -145,21 +157,53 @@ def mp_update(st, p):
             dF[:, i, j] = dF[:, i, j] + _segsum(duI[:, i] * st.dN[:, j], st.offsets)
     F_new = dF @ st.F
     J_dF = material.det3(dF)
-    if np.any(J_dF.real <= 0):
+    # failed MPs carry nothing, so their inversion does not matter
+    bad = (J_dF.real <= 0) if st.failed is None else (J_dF.real <= 0) & ~st.failed
+    if np.any(bad):
         raise FloatingPointError("inverted material point (det dF <= 0) at "
-                                 f"{int(np.nonzero(J_dF.real <= 0)[0][0])}")
+                                 f"{int(np.nonzero(bad)[0][0])}")
     st.vol = J_dF * st.vol
     st.xp_prev, st.dF = st.xp, dF
     st.xp = xp
     J_new = material.det3(F_new)
     if p["model"] == material.NEOHOOKE:
         st.sigma = material.neo_hooke_cauchy(F_new, p["E"], p["nu"])
-    else:
+    elif st.failed is None:
         sig, be, eb, T, _ = material.j2_update(p, dF, st.be, st.epsbar, st.T, J_new, p["dt"],
                                                spectral=p.get("spectral", "eigh"),
                                                polish=p.get("polish", 0))
         st.sigma, st.be, st.epsbar, st.T = sig, be, eb, T
+    else:
+        _update_with_fracture(st, p, dF, J_new)
     st.F = F_new
+
+
+def _update_with_fracture(st, p, dF, J_new):
+    """The J2 update of the MPs that have not failed, then the Johnson-Cook
+    fracture criterion (Sec. 4.2): an MP whose equivalent plastic strain is
+    positive and at least the critical strain at its stress triaxiality, rate
+    and temperature fails.  Readings: an MP that never yielded does not
+    fracture (ductile fracture follows plastic flow); a failed MP carries no
+    stress from then on (it is eroded) but keeps its mass, so the lumped mass
+    is conserved, and its b^e, epsbar and T stay as they were."""
+    alive = np.nonzero(~st.failed)[0]
+    sigma = np.zeros_like(st.sigma, dtype=np.result_type(st.sigma, dF))
+    be = st.be.astype(sigma.dtype)
+    eb = st.epsbar.astype(sigma.dtype)
+    T = st.T.astype(sigma.dtype)
+    if alive.size:
+        s_a, be_a, eb_a, T_a, de_a = material.j2_update(
+            p, dF[alive], st.be[alive], st.epsbar[alive], st.T[alive], J_new[alive], p["dt"],
+            spectral=p.get("spectral", "eigh"), polish=p.get("polish", 0))
+        eta = material.triaxiality(s_a.real)
+        ef = material.jc_fracture_strain(p, eta, de_a.real, p["dt"], T_a.real)
+        newly = (eb_a.real > 0) & (eb_a.real >= ef)
+        s_a = np.where(newly[:, None, None], 0.0, s_a)
+        sigma[alive], be[alive], eb[alive], T[alive] = s_a, be_a, eb_a, T_a
+        failed = st.failed.copy()
+        failed[alive[newly]] = True
+        st.failed = failed
+    st.sigma, st.be, st.epsbar, st.T = sigma, be, eb, T
 
 
 def _segsum(vals, offsets):
@@ -198,7 +242,9 @@ def init_state(x_nodes, x_mp, vol, mass, v0_nodes, p, lists=None):
                mass=np.array(mass, dtype=np.float64), lam=np.zeros((n_mp, 3)),
                F=np.tile(I, (n_mp, 1, 1)), be=np.tile(I, (n_mp, 1, 1)),
                epsbar=np.zeros(n_mp), T=np.full(n_mp, float(p["T_r"])),
-               sigma=np.zeros((n_mp, 3, 3)), offsets=None, idx=None, N=None, dN=None)
+               sigma=np.zeros((n_mp, 3, 3)), offsets=None, idx=None, N=None, dN=None,
+               failed=np.zeros(n_mp, bool) if p.get("fracture") else None,
+               gT=np.zeros((n_nodes, 3)) if p.get("tool") else None)
     if lists is None:
         rebuild_lists(st, p)
     else:

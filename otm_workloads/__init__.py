@@ -89,6 +89,13 @@ class Workload:
     wall: bool = False
     wall_x: tuple = (0.0, 0.0, 0.0)
     wall_n: tuple = (0.0, 0.0, 1.0)
+    # Johnson-Cook fracture constants d1..d5 (chip formation, fracture
+    # criterion), or None
+    fracture: tuple = None
+    # rigid cutting tool (chip formation, contact): dict with c0 (centre of the
+    # tip circle at t = 0), v (velocity), r (tip radius), clearance (rad),
+    # cN, cT (penalty stiffnesses, N/m), mu (Coulomb coefficient), or None
+    tool: dict = None
 
     @property
     def n_nodes(self):
@@ -114,7 +121,7 @@ class Workload:
         return self.r_cut + self.skin
 
 
-def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False):
+def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False, clamp_x0=False):
     """Lattice nodes inside a body, their jitter, the hex cells and tets.
 
     ``inside(i, j, k)`` receives integer index arrays and returns a mask.
@@ -135,6 +142,8 @@ def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False):
     x = X + jit
     if clamp_z0:
         x[:, 2] = np.maximum(x[:, 2], 0.0)
+    if clamp_x0:
+        x[:, 0] = np.maximum(x[:, 0], 0.0)
 
     # hex cells with all 8 corners present, in (k, j, i) order
     corners = []
@@ -210,6 +219,48 @@ def taylor_rod(h, seed, radius=3.2e-3, length=21.12e-3, speed=190.0, steps=100,
                     skin=skin_h * h, rebuild_every=rebuild_every, wall=True)
 
 
+def ti_params(seed):
+    """Ti-alloy-like Johnson-Cook flow and fracture constants drawn from
+    ``seed`` (Pa, SI units): the chip-formation study takes its values from a
+    reference that is not published with it."""
+    rng = np.random.default_rng(seed)
+    flow = dict(A=rng.uniform(860e6, 1100e6), B=rng.uniform(330e6, 700e6),
+                n=rng.uniform(0.30, 0.60), C=rng.uniform(0.012, 0.035),
+                m=rng.uniform(0.8, 1.1))
+    frac = (rng.uniform(-0.09, 0.05), rng.uniform(0.25, 0.35), rng.uniform(-0.5, -0.45),
+            rng.uniform(0.014, 0.03), rng.uniform(3.5, 3.9))
+    return flow, frac
+
+
+def cutting_slab(h=2e-6, seed=7, length=300e-6, height=120e-6, layers=3, depth=100e-6,
+                 speed=5.0, tip_radius=2e-6, clearance_deg=7.0, engage=0.0, steps=2000,
+                 dt=1e-10, name="cutting_slab", fracture=None):
+    """Orthogonal cutting (Sec. 4.2): a workpiece of length x height
+    (x, y) and ``layers`` node layers through the thickness (z), a rigid tool
+    of tip radius 2 um and rake angle 0 moving at -speed along x with the
+    cutting depth ``depth`` below the top face, the workpiece held at x = 0
+    by the frictionless wall.  Ti-alloy-like elastic constants and
+    Taylor-Quinney coefficient, the paper's T_m = 1630 C and T_r = 25 C,
+    Johnson-Cook flow and fracture constants from ``seed``; Coulomb
+    friction 0.8; normal and tangential penalties E h.  ``engage`` moves the
+    tool that far into the workpiece at t = 0."""
+    ni = int(round(length / h))
+    nj = int(round(height / h))
+    x, X, x_mp, vol = _lattice_body(((0, ni), (0, nj), (0, layers - 1)),
+                                    lambda i, j, k: np.ones(i.shape, bool), h, seed,
+                                    clamp_x0=True)
+    flow, frac = ti_params(seed)
+    mat = Material(MODEL_J2_JC, E=113.8e9, nu=0.342, rho0=4430.0, chi=0.9,
+                   T_r=298.15, T_m=1903.15, Cp=580.0, eps_dot0=1.0, **flow)
+    v0 = np.zeros_like(x)
+    tool = dict(c0=(length + tip_radius - engage, height - depth + tip_radius, 0.0),
+                v=(-speed, 0.0, 0.0), r=tip_radius, clearance=math.radians(clearance_deg),
+                cN=mat.E * h, cT=mat.E * h, mu=0.8)
+    return Workload(name, h, x, X, x_mp, vol, mat.rho0 * vol, v0, mat, dt, steps,
+                    wall=True, wall_x=(0.0, 0.0, 0.0), wall_n=(1.0, 0.0, 0.0),
+                    fracture=tuple(frac) if fracture is None else tuple(fracture), tool=tool)
+
+
 def config_by_name(name):
     """The named workloads.
 
@@ -223,6 +274,14 @@ def config_by_name(name):
                    R = 3.2 mm, 227 m/s, linear hardening Y0 = 400 MPa,
                    H = 100 MPa, dt = 4e-9 s, 2000 steps; h = 0.55 mm gives
                    5,959 nodes / 27,840 MPs (the paper's mesh: 5,966 / 28,423)
+    cutting_slab   the chip-formation workpiece of Sec. 4.2 at the paper's size:
+                   300 x 120 um, h = 2 um, 3 node layers: 27,633 nodes /
+                   108,000 MPs (the paper's model: 27,417 / 107,975), rigid
+                   tool with 2 um tip radius, 0 rake, 100 um depth of cut,
+                   JC flow and fracture, dt = 1e-10 s, 2000 steps
+    small_cut      a 40 x 24 um piece of the same slab (h = 2 um) with the tool
+                   0.2 um clear of it, at 50 m/s, and a low fracture strain
+                   (parity tests: contact, friction and fracture within steps)
     """
     if name == "elastic_cube":
         return elastic_cube()
@@ -239,6 +298,12 @@ def config_by_name(name):
     if name == "paper_rod":
         return taylor_rod(h=0.55e-3, seed=6, radius=3.2e-3, length=32.4e-3, speed=227.0,
                           steps=2000, model=MODEL_J2_LINEAR, name="paper_rod", dt=4e-9)
+    if name == "cutting_slab":
+        return cutting_slab()
+    if name == "small_cut":
+        return cutting_slab(length=40e-6, height=24e-6, depth=16e-6, speed=50.0,
+                            engage=-0.2e-6, steps=60, name="small_cut",
+                            fracture=(0.0, 0.005, -0.5, 0.014, 3.7))
     raise KeyError(name)
 
 
@@ -259,6 +324,14 @@ def params_from_workload(w, **over):
              beta=w.beta, r_list=w.r_list, cell_size=w.r_list * 1.0001,
              lme_tol=1e-14 * w.h, lme_max_iter=50, rm_tol=1e-14, rm_max_iter=60,
              wall=bool(w.wall), wall_x=np.array(w.wall_x, float),
-             wall_n=np.array(w.wall_n, float), dt=w.dt, rebuild_every=w.rebuild_every)
+             wall_n=np.array(w.wall_n, float), dt=w.dt, rebuild_every=w.rebuild_every,
+             fracture=w.fracture is not None,
+             jc_d=np.array(w.fracture if w.fracture is not None else (0.0,) * 5, float),
+             tool=w.tool is not None)
+    if w.tool is not None:
+        t = w.tool
+        p.update(tool_c=np.array(t["c0"], float), tool_v=np.array(t["v"], float),
+                 tool_r=float(t["r"]), tool_clearance=float(t["clearance"]),
+                 tool_cN=float(t["cN"]), tool_cT=float(t["cT"]), tool_mu=float(t["mu"]))
     p.update(over)
     return p
