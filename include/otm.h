@@ -102,6 +102,32 @@ typedef struct otm_params {
                              otm_refresh (no previous configuration) add no
                              term; otm_step_adjoint rejects eps > 0 */
   double body_force[3];   /* specific body force: must be 0 */
+  /* Chip formation (Sec. 4.2).  Johnson-Cook fracture: after the return map
+     an MP whose equivalent plastic strain is positive and at least
+     [d1 + d2 exp(d3 eta)] [1 + d4 ln max(rate / eps_dot0, 1)] [1 + d5 T*]
+     (eta = mean / von Mises stress, T* the clamped homologous temperature)
+     fails: from then on it carries no stress (it keeps its mass, F and
+     position; its b^e, epsbar and T stay as they were).  Needs model
+     OTM_J2_JC and st->failed. */
+  int32_t fracture;       /* fracture criterion on (1) / off (0) */
+  int32_t tool_enabled;   /* rigid cutting tool on (1) / off (0) */
+  double jc_d[5];         /* fracture constants d1..d5 */
+  /* Rigid tool: a wedge rounded by the tip radius and extruded along z.  Its
+     tip circle is centred at tool_c + t tool_v at time t; the rake face runs
+     from the tip along +y (rake angle 0), the flank face along
+     (cos a, sin a, 0), a = tool_clearance.  Each step the nodes inside it
+     (normal gap g < 0 at x_n and the tool at t_n) get the penalty force
+     tool_cN |g| along the outward normal plus a tangential force: the trial
+     -tool_cT g_T (g_T the node's tangential gap, see otm_state::tool_gt)
+     while it is at most tool_mu times the normal force (stick), else that
+     limit along it (Coulomb slip).  The force joins the internal force in the
+     node update.  Needs st->tool_gt and st->clock. */
+  double tool_c[3];       /* centre of the tip circle at t = 0 */
+  double tool_v[3];       /* tool velocity */
+  double tool_r;          /* tip radius > 0 */
+  double tool_clearance;  /* clearance angle in [0, pi/2) */
+  double tool_cN, tool_cT;/* normal and tangential penalty stiffness > 0 (N/m) */
+  double tool_mu;         /* Coulomb friction coefficient >= 0 */
 } otm_params;
 
 /* Device state of one simulation (host struct of device pointers). */
@@ -135,6 +161,15 @@ typedef struct otm_state {
   double* xp_prev;        /* [3][n_mp] MP positions before the last MP update */
   double* dFm1;           /* [9][n_mp] dF - 1 of the last MP update (float64 in
                              both precisions), row-major per MP */
+  /* chip formation (may be NULL when params.fracture / tool_enabled are 0) */
+  int32_t* failed;        /* [n_mp] 1 once the MP met the fracture criterion */
+  double* tool_gt;        /* [3][n_nodes] tangential contact gap of each node:
+                             each step in contact it becomes the previous gap,
+                             projected on the tangent plane, plus the tangential
+                             part of du_I - dt tool_v, cut back to the Coulomb
+                             limit (g_T = -t_T / tool_cT); 0 out of contact */
+  double* clock;          /* [1] time of the state; otm_init sets 0 and each
+                             step adds dt (moves the tool) */
 } otm_state;
 
 /* Device-side failure record (lives in device memory). */
@@ -318,8 +353,9 @@ size_t otm_adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp);
  * the Hencky stress and of the exponential map and the implicit derivative
  * of the scalar return equation; wall contact and plastic onset are
  * differentiated on their active branch.  Supports longer than 48 nodes are
- * reported as OTM_ERR_SUPPORT in diag.  The stabilisation term has no
- * adjoint: p->eps_stab > 0 returns OTM_ERR_ARG.
+ * reported as OTM_ERR_SUPPORT in diag.  The stabilisation term, fracture
+ * and the cutting tool have no adjoint: p->eps_stab > 0, p->fracture or
+ * p->tool_enabled return OTM_ERR_ARG.
  */
 otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_params* p,
                             double dt, const double* mass, otm_state_bar* bar_next,

@@ -38,6 +38,10 @@ class Params(C.Structure):
         ("lme_tol", C.c_double), ("lme_max_iter", C.c_int32), ("rm_max_iter", C.c_int32),
         ("rm_tol", C.c_double), ("wall_x", C.c_double * 3), ("wall_n", C.c_double * 3),
         ("eps_stab", C.c_double), ("body_force", C.c_double * 3),
+        ("fracture", C.c_int32), ("tool_enabled", C.c_int32), ("jc_d", C.c_double * 5),
+        ("tool_c", C.c_double * 3), ("tool_v", C.c_double * 3), ("tool_r", C.c_double),
+        ("tool_clearance", C.c_double), ("tool_cN", C.c_double), ("tool_cT", C.c_double),
+        ("tool_mu", C.c_double),
     ]
 
 
@@ -51,6 +55,7 @@ class State(C.Structure):
         ("sigma", C.c_void_p),
         ("nbr_offsets", C.c_void_p), ("nbr_idx", C.c_void_p), ("N", C.c_void_p),
         ("dN", C.c_void_p), ("xp_prev", C.c_void_p), ("dFm1", C.c_void_p),
+        ("failed", C.c_void_p), ("tool_gt", C.c_void_p), ("clock", C.c_void_p),
     ]
 
 

@@ -102,6 +102,31 @@ static otm_status check_params(const otm_params* p) {
                       p->wall_n[2] * p->wall_n[2];
     if (!(fabs(nn - 1.0) < 1e-12)) return OTM_ERR_ARG;
   }
+  if (p->fracture != 0 && p->fracture != 1) return OTM_ERR_ARG;
+  if (p->fracture) {
+    if (p->model != OTM_J2_JC) return OTM_ERR_ARG;
+    for (int k = 0; k < 5; ++k)
+      if (!isfinite(p->jc_d[k])) return OTM_ERR_ARG;
+  }
+  if (p->tool_enabled != 0 && p->tool_enabled != 1) return OTM_ERR_ARG;
+  if (p->tool_enabled) {
+    for (int k = 0; k < 3; ++k)
+      if (!isfinite(p->tool_c[k]) || !isfinite(p->tool_v[k])) return OTM_ERR_ARG;
+    if (!(p->tool_r > 0) || !isfinite(p->tool_r)) return OTM_ERR_ARG;
+    if (!(p->tool_clearance >= 0.0 && p->tool_clearance < 1.5707963267948966))
+      return OTM_ERR_ARG;
+    if (!(p->tool_cN > 0) || !(p->tool_cT > 0) || !isfinite(p->tool_cN) ||
+        !isfinite(p->tool_cT) || !(p->tool_mu >= 0) || !isfinite(p->tool_mu))
+      return OTM_ERR_ARG;
+  }
+  return OTM_OK;
+}
+
+// The chip-formation arrays a state needs for these parameters.
+static otm_status check_cut_state(const otm_state* st, const otm_params* p) {
+  if (p->fracture && st->n_mp > 0 && !dev_ok(st->failed, 4)) return OTM_ERR_ARG;
+  if (p->tool_enabled && (!dev_ok(st->clock, 8) || (st->n_nodes > 0 && !dev_ok(st->tool_gt, 8))))
+    return OTM_ERR_ARG;
   return OTM_OK;
 }
 
@@ -294,6 +319,7 @@ otm_status otm_init(otm_state* st, const otm_params* p, double dt, const double*
   otm_status e;
   if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
   if (!(dt > 0) || (st->n_nodes > 0 && !dev_ok(v0, 8))) return OTM_ERR_ARG;
+  if ((e = check_cut_state(st, p)) != OTM_OK) return e;
   launch_init_fields(*st, *p, dt, v0, s);
   return otm_refresh(st, p, 1, scatter_mode, ws, ws_bytes, diag, s);
 }
@@ -318,6 +344,7 @@ static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32
   if (!dev_ok(diag, 8)) return OTM_ERR_ARG;
   const bool stab = p->eps_stab > 0.0;
   if (stab && (!dev_ok(st->xp_prev, 8) || !dev_ok(st->dFm1, 8))) return OTM_ERR_ARG;
+  if ((e = check_cut_state(st, p)) != OTM_OK) return e;
   Workspace w;
   if (check_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &w) != OTM_OK)
     return OTM_ERR_ARG;
@@ -400,6 +427,7 @@ otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_p
   if ((e = check_params(p)) != OTM_OK) return e;
   if (p->model == OTM_NEOHOOKE) return OTM_ERR_ARG;  // adjoint covers the J2 models
   if (p->eps_stab != 0.0) return OTM_ERR_ARG;        // no adjoint of the stabilisation
+  if (p->fracture || p->tool_enabled) return OTM_ERR_ARG;  // nor of fracture and the tool
   if (!tape_ok(tn) || !tape_ok(tn1) || !bar_ok(bar_next) || !bar_ok(bar)) return OTM_ERR_ARG;
   if (tn->n_nodes != tn1->n_nodes || tn->n_mp != tn1->n_mp) return OTM_ERR_ARG;
   if (!(dt > 0) || !dev_ok(mass, 8) || !dev_ok(theta_bar, 8) || !dev_ok(diag, 8))

@@ -33,6 +33,8 @@ struct Mat {
   R A, B, n, C, m, rate0dt, Tr, Tm, rhoCp, chi, Y0, H;
   R tol;
   int max_iter;
+  double jd[5];      // Johnson-Cook fracture constants d1..d5 (float64)
+  double rate0dt_d;  // dt * eps_dot0 in float64 (fracture rate term)
 };
 
 // Thermal softening factor 1 - T*^m of the Johnson-Cook law (1 below T_r).
@@ -117,6 +119,8 @@ inline Mat<R> make_mat(const otm_params& p, double dt) {
   const double eps = sizeof(R) == 8 ? 2.2e-16 : 1.2e-7;
   M.tol = (R)(p.rm_tol > 4 * eps ? p.rm_tol : 4 * eps);
   M.max_iter = p.rm_max_iter;
+  for (int k = 0; k < 5; ++k) M.jd[k] = p.jc_d[k];
+  M.rate0dt_d = dt * p.eps_dot0;
   return M;
 }
 

@@ -23,6 +23,72 @@
 namespace otm {
 
 // ------------------------------------------------------------------- nodes
+// Rigid cutting tool (Sec. 4.2 contact): a wedge rounded by the tip radius,
+// extruded along z, centre of the tip circle c + t v.  The core wedge has the
+// rake face along +y from c (outward normal (-1, 0)) and the flank face along
+// (ca, sa) (outward normal (sa, -ca)); the gap is the signed distance to the
+// core minus the tip radius.
+struct ToolArgs {
+  int on;
+  double cx, cy, vx, vy, vz, r, sa, ca, cN, cT, mu, dt;
+  const double* clock;  // [1] time of the state
+  double* gt;           // [3][n] tangential gaps
+};
+
+// Contact force on node i at position xo with last increment du_old; updates
+// its tangential gap.
+OTM_DEV void tool_contact(const ToolArgs& t, int64_t n, int64_t i, const double xo[3],
+                          const double du_old[3], double fc[3]) {
+  const double tm = t.clock[0];
+  const double dx = xo[0] - (t.cx + tm * t.vx), dy = xo[1] - (t.cy + tm * t.vy);
+  const double a = -dx, b = t.sa * dx - t.ca * dy;  // n1 . d, n2 . d
+  const double s1 = dy > 0.0 ? dy : 0.0;
+  const double q1x = dx, q1y = dy - s1;
+  const double pr2 = t.ca * dx + t.sa * dy;
+  const double s2 = pr2 > 0.0 ? pr2 : 0.0;
+  const double q2x = dx - s2 * t.ca, q2y = dy - s2 * t.sa;
+  const double l1 = sqrt(q1x * q1x + q1y * q1y), l2 = sqrt(q2x * q2x + q2y * q2y);
+  double sd, nx, ny;
+  if (a <= 0.0 && b <= 0.0) {  // inside the core: nearer face
+    sd = a >= b ? a : b;
+    nx = a >= b ? -1.0 : t.sa;
+    ny = a >= b ? 0.0 : -t.ca;
+  } else {
+    const bool first = l1 <= l2;
+    sd = first ? l1 : l2;
+    const double inv = 1.0 / (sd > 0.0 ? sd : 1.0);
+    nx = (first ? q1x : q2x) * inv;
+    ny = (first ? q1y : q2y) * inv;
+  }
+  const double g = sd - t.r;
+  if (!(g < 0.0)) {
+    fc[0] = fc[1] = fc[2] = 0.0;
+    t.gt[i] = 0.0; t.gt[n + i] = 0.0; t.gt[2 * n + i] = 0.0;
+    return;
+  }
+  const double nrm[3] = {nx, ny, 0.0};
+  const double tn = t.cN * -g;
+  const double rel[3] = {du_old[0] - t.dt * t.vx, du_old[1] - t.dt * t.vy,
+                         du_old[2] - t.dt * t.vz};
+  const double go[3] = {t.gt[i], t.gt[n + i], t.gt[2 * n + i]};
+  const double rn = rel[0] * nrm[0] + rel[1] * nrm[1] + rel[2] * nrm[2];
+  const double gn = go[0] * nrm[0] + go[1] * nrm[1] + go[2] * nrm[2];
+  double tt[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) tt[c] = -t.cT * ((go[c] - gn * nrm[c]) + (rel[c] - rn * nrm[c]));
+  const double mag = sqrt(tt[0] * tt[0] + tt[1] * tt[1] + tt[2] * tt[2]);
+  const double lim = t.mu * tn;
+  const double scale = mag > lim ? lim / (mag > 0.0 ? mag : 1.0) : 1.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    tt[c] *= scale;
+    fc[c] = tn * nrm[c] + tt[c];
+    t.gt[c * n + i] = -tt[c] / t.cT;
+  }
+}
+
+__global__ void k_clock_advance(double* clock, double dt) { clock[0] += dt; }
+
 __global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restrict__ x,
                                                      double* __restrict__ du,
                                                      double* __restrict__ m,
@@ -31,16 +97,28 @@ __global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restri
                                                      double wx2, double wn0, double wn1,
                                                      double wn2, int zero_mf,
                                                      double4* __restrict__ packed,
-                                                     int64_t n_mp, otm_diag* diag) {
+                                                     int64_t n_mp, otm_diag* diag,
+                                                     ToolArgs tool) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double mi = m[i];
-  double u[3], xs[3], xo[3];
+  double u[3], xs[3], xo[3], fi[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     xo[c] = x[c * n + i];
+    u[c] = du[c * n + i];
+    fi[c] = f[c * n + i];
+  }
+  if (tool.on) {
+    double fc[3];
+    tool_contact(tool, n, i, xo, u, fc);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fi[c] += fc[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
     // a node outside every support (no mass, no force) keeps its increment
-    u[c] = du[c * n + i] + (mi > 0.0 ? dt2 * f[c * n + i] / mi : 0.0);
+    u[c] = u[c] + (mi > 0.0 ? dt2 * fi[c] / mi : 0.0);
     xs[c] = xo[c] + u[c];
   }
   if (wall) {
@@ -85,10 +163,24 @@ void launch_node_update(const otm_state& st, const otm_params& p, double dt, boo
                         double4* packed, otm_diag* diag, hipStream_t s) {
   const int64_t n = st.n_nodes;
   if (n <= 0) return;
+  ToolArgs t{};
+  if (p.tool_enabled) {
+    t.on = 1;
+    t.cx = p.tool_c[0]; t.cy = p.tool_c[1];
+    t.vx = p.tool_v[0]; t.vy = p.tool_v[1]; t.vz = p.tool_v[2];
+    t.r = p.tool_r;
+    t.sa = std::sin(p.tool_clearance);
+    t.ca = std::cos(p.tool_clearance);
+    t.cN = p.tool_cN; t.cT = p.tool_cT; t.mu = p.tool_mu;
+    t.dt = dt;
+    t.clock = st.clock;
+    t.gt = st.tool_gt;
+  }
   k_node_update<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
       n, st.x, st.du, st.m, st.f, dt * dt, p.wall_enabled, p.wall_x[0], p.wall_x[1],
       p.wall_x[2], p.wall_n[0], p.wall_n[1], p.wall_n[2], zero_mf ? 1 : 0, packed, st.n_mp,
-      diag);
+      diag, t);
+  if (p.tool_enabled) k_clock_advance<<<1, 1, 0, s>>>(st.clock, dt);
 }
 
 // ----------------------------------------------------- material-point pass
@@ -103,7 +195,8 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     int64_t cap, const double* __restrict__ N, const R* __restrict__ dN,
     double* __restrict__ xp, double* __restrict__ vol, R* __restrict__ Fd, R* __restrict__ bed,
     double* __restrict__ epsbar, double* __restrict__ T, R* __restrict__ sigma, Mat<R> M,
-    double* __restrict__ xp_prev, double* __restrict__ dFm1, otm_diag* diag) {
+    double* __restrict__ xp_prev, double* __restrict__ dFm1, int32_t* __restrict__ failed,
+    otm_diag* diag) {
   // phase 1: the 12 gathered sums of each MP; phase 2: the MP's eigenvectors,
   // logarithmic strains and J parked over the return-map solve (each lane
   // only touches its own column)
@@ -269,7 +362,9 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   const double xnew[3] = {sums[0][tid], sums[1][tid], sums[2][tid]};
   bool finite = isfinite(xnew[0]) && isfinite(xnew[1]) && isfinite(xnew[2]);
   const double detdF = 1.0 + det_one_plus_minus_one(H);
-  if (!(detdF > 0.0)) diag_fail(diag, OTM_ERR_INVERTED, (uint64_t)p);
+  // a failed MP (fracture) carries nothing, so its inversion does not matter
+  const bool was_failed = failed != nullptr && failed[p] != 0;
+  if (!(detdF > 0.0) && !was_failed) diag_fail(diag, OTM_ERR_INVERTED, (uint64_t)p);
   vol[p] = detdF * vol[p];
   if (dFm1 != nullptr) {  // history of the stabilisation term
 #pragma unroll
@@ -316,6 +411,10 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
                     (fn.a[i][0] * fn.a[j][0] + fn.a[i][1] * fn.a[j][1] + fn.a[i][2] * fn.a[j][2]);
       sig.v[c] = M.mu / J * bm1 + (c < 3 ? M.lamL * lnJ / J : R(0));
     }
+  } else if (was_failed) {
+    // eroded: no stress; b^e, epsbar and T stay as they were
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sig.v[c] = R(0);
   } else {
     // trial elastic left Cauchy-Green tensor, as a deviation from 1:
     // b_tr - 1 = H + H^T + H H^T + (1+H) Bd (1+H)^T
@@ -394,9 +493,33 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     sig = spectral_compose(V, tau);
 #pragma unroll
     for (int k = 0; k < 6; ++k) bed[k * n_mp + p] = bn.v[k];
-    epsbar[p] = ebn + (double)deps;
-    if (M.model == OTM_J2_JC)
-      T[p] = Tn + (double)(M.chi * (R(1) - c) * q_tr * deps / M.rhoCp);
+    const double eb_new = ebn + (double)deps;
+    epsbar[p] = eb_new;
+    double T_new = Tn;
+    if (M.model == OTM_J2_JC) {
+      T_new = Tn + (double)(M.chi * (R(1) - c) * q_tr * deps / M.rhoCp);
+      T[p] = T_new;
+    }
+    if (failed != nullptr && eb_new > 0.0) {
+      // Johnson-Cook fracture criterion (Sec. 4.2) on the principal Cauchy
+      // stresses: triaxiality = mean / von Mises stress
+      const double s0 = tau[0], s1 = tau[1], s2 = tau[2];
+      const double sm = (s0 + s1 + s2) / 3.0;
+      const double e0 = s0 - sm, e1 = s1 - sm, e2 = s2 - sm;
+      const double sv = sqrt(1.5 * (e0 * e0 + e1 * e1 + e2 * e2));
+      const double eta = sv > 0.0 ? sm / sv : 0.0;
+      const double ratio = (double)deps / M.rate0dt_d;
+      const double lr = ratio > 1.0 ? log(ratio) : 0.0;
+      double ts = (T_new - (double)M.Tr) / ((double)M.Tm - (double)M.Tr);
+      ts = ts < 0.0 ? 0.0 : (ts > 1.0 ? 1.0 : ts);
+      const double ef = (M.jd[0] + M.jd[1] * exp(M.jd[2] * eta)) * (1.0 + M.jd[3] * lr) *
+                        (1.0 + M.jd[4] * ts);
+      if (eb_new >= ef) {
+        failed[p] = 1;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sig.v[k] = R(0);
+      }
+    }
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -413,14 +536,15 @@ void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
   const unsigned nb = (unsigned)((n + kMpBlock - 1) / kMpBlock);
   double* hist_x = p.eps_stab > 0.0 ? st.xp_prev : nullptr;
   double* hist_f = p.eps_stab > 0.0 ? st.dFm1 : nullptr;
+  int32_t* frac = p.fracture ? st.failed : nullptr;
   if (st.precision == OTM_FP64)
     k_mp_update<double><<<nb, kMpBlock, 0, s>>>(
         packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const double*)st.dN, st.xp, st.vol, (double*)st.Fd, (double*)st.bed, st.epsbar, st.T,
-        (double*)st.sigma, make_mat<double>(p, dt), hist_x, hist_f, diag);
+        (double*)st.sigma, make_mat<double>(p, dt), hist_x, hist_f, frac, diag);
   else
     k_mp_update<float><<<nb, kMpBlock, 0, s>>>(
         packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const float*)st.dN, st.xp, st.vol, (float*)st.Fd, (float*)st.bed, st.epsbar, st.T,
-        (float*)st.sigma, make_mat<float>(p, dt), hist_x, hist_f, diag);
+        (float*)st.sigma, make_mat<float>(p, dt), hist_x, hist_f, frac, diag);
 }
 
 // ------------------------------------------------------------------- t = 0
@@ -436,10 +560,19 @@ __global__ void k_init_mp(int64_t n, R* Fd, R* bed, R* sigma, double* epsbar, do
   lam[p] = 0.0; lam[n + p] = 0.0; lam[2 * n + p] = 0.0;
 }
 
-__global__ void k_init_nodes(int64_t n, double* du, const double* v0, double dt) {
+__global__ void k_init_nodes(int64_t n, double* du, const double* v0, double dt, double* gt,
+                             double* clock) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && clock != nullptr) clock[0] = 0.0;
   if (i >= n) return;
   for (int c = 0; c < 3; ++c) du[c * n + i] = dt * v0[c * n + i];
+  if (gt != nullptr)
+    for (int c = 0; c < 3; ++c) gt[c * n + i] = 0.0;
+}
+
+__global__ void k_init_failed(int64_t n, int32_t* failed) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) failed[p] = 0;
 }
 
 void launch_init_fields(const otm_state& st, const otm_params& p, double dt, const double* v0,
@@ -453,8 +586,14 @@ void launch_init_fields(const otm_state& st, const otm_params& p, double dt, con
       k_init_mp<float><<<nb, 256, 0, s>>>(st.n_mp, (float*)st.Fd, (float*)st.bed,
                                           (float*)st.sigma, st.epsbar, st.T, st.lam, p.T_r);
   }
-  if (st.n_nodes > 0)
-    k_init_nodes<<<(unsigned)((st.n_nodes + 255) / 256), 256, 0, s>>>(st.n_nodes, st.du, v0, dt);
+  if (p.fracture && st.n_mp > 0)
+    k_init_failed<<<(unsigned)((st.n_mp + 255) / 256), 256, 0, s>>>(st.n_mp, st.failed);
+  double* gt = p.tool_enabled ? st.tool_gt : nullptr;
+  double* clock = p.tool_enabled ? st.clock : nullptr;
+  if (st.n_nodes > 0 || clock != nullptr) {  // one workgroup at least: it sets the clock
+    const unsigned nb = st.n_nodes > 0 ? (unsigned)((st.n_nodes + 255) / 256) : 1u;
+    k_init_nodes<<<nb, 256, 0, s>>>(st.n_nodes, st.du, v0, dt, gt, clock);
+  }
 }
 
 }  // namespace otm

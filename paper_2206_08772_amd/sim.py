@@ -48,6 +48,17 @@ def make_params(p):
         q.wall_n[i] = float(wn[i])
         q.body_force[i] = 0.0
     q.eps_stab = float(p.get("eps_stab", 0.0))
+    q.fracture = 1 if p.get("fracture", False) else 0
+    q.tool_enabled = 1 if p.get("tool", False) else 0
+    d = p.get("jc_d", (0.0,) * 5)
+    for k in range(5):
+        q.jc_d[k] = float(d[k])
+    if q.tool_enabled:
+        for i in range(3):
+            q.tool_c[i] = float(p["tool_c"][i])
+            q.tool_v[i] = float(p["tool_v"][i])
+        for k in ("tool_r", "tool_clearance", "tool_cN", "tool_cT", "tool_mu"):
+            setattr(q, k, float(p[k]))
     return q
 
 
@@ -153,6 +164,12 @@ class Sim:
         self.stab = float(params.get("eps_stab", 0.0)) > 0.0
         self.xp_prev = torch.zeros(3, nm, dtype=torch.float64, device=dev) if self.stab else None
         self.dFm1 = torch.zeros(9, nm, dtype=torch.float64, device=dev) if self.stab else None
+        # chip formation: fracture flags, tangential contact gaps, the clock
+        self.fracture = bool(params.get("fracture", False))
+        self.tool = bool(params.get("tool", False))
+        self.failed = torch.zeros(nm, dtype=torch.int32, device=dev) if self.fracture else None
+        self.tool_gt = torch.zeros(3, nn, dtype=torch.float64, device=dev) if self.tool else None
+        self.clock = torch.zeros(1, dtype=torch.float64, device=dev) if self.tool else None
         self.offsets = torch.zeros(nm + 1, dtype=torch.int64, device=dev)
         self.v0 = soa(v0_nodes, dev)
         if pair_capacity is None:
@@ -190,6 +207,9 @@ class Sim:
         s.dN = _ptr(self.dN).value
         s.xp_prev = _ptr(self.xp_prev).value if self.stab else None
         s.dFm1 = _ptr(self.dFm1).value if self.stab else None
+        s.failed = _ptr(self.failed).value if self.fracture else None
+        s.tool_gt = _ptr(self.tool_gt).value if self.tool else None
+        s.clock = _ptr(self.clock).value if self.tool else None
 
     # ---------------------------------------------------------------- calls
     def init(self):
@@ -291,6 +311,11 @@ class Sim:
         out["idx"] = self.idx[:P].cpu().numpy()
         out["N"] = g(self.N[:P])
         out["dN"] = g(self.dN[:, :P]).T.copy()
+        if self.fracture:
+            out["failed"] = self.failed.cpu().numpy().astype(bool)
+        if self.tool:
+            out["gT"] = g(self.tool_gt).T.copy()
+            out["clock"] = float(self.clock.cpu()[0])
         return out
 
 

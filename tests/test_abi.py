@@ -165,3 +165,35 @@ def test_step_into_rejects_missing_misaligned_or_aliased_lists(L):
     assert (st.nbr_offsets, st.nbr_idx, st.N, st.dN) == before
     nxt.N, nxt.nbr_offsets = 2 << 20, 0                 # missing offsets
     assert call(C.byref(nxt)) == L.OTM_ERR_ARG
+
+
+@pytest.mark.parametrize("bad", [
+    dict(fracture=True, model=W.MODEL_J2_LINEAR),     # fracture needs the JC model
+    dict(tool_r=0.0),
+    dict(tool_clearance=1.6),
+    dict(tool_mu=-0.1),
+    dict(tool_cN=0.0),
+])
+def test_bad_cutting_params_are_rejected(L, bad):
+    from paper_2206_08772_amd.sim import make_params
+    lib = L.lib()
+    w = W.config_by_name("small_cut")
+    p = make_params(W.params_from_workload(w, **bad))
+    st = _fake_state(L)
+    assert lib.otm_step(C.byref(st), C.byref(p), 1e-10, 1, 0, C.c_void_p(1 << 20), 1 << 30,
+                        C.c_void_p(1 << 20), None) == L.OTM_ERR_ARG
+
+
+def test_cutting_needs_its_state_arrays(L):
+    from paper_2206_08772_amd.sim import make_params
+    lib = L.lib()
+    w = W.config_by_name("small_cut")
+    p = make_params(W.params_from_workload(w))
+    for missing in ("failed", "tool_gt", "clock"):
+        st = _fake_state(L)
+        setattr(st, missing, 0)
+        assert lib.otm_step(C.byref(st), C.byref(p), 1e-10, 1, 0, C.c_void_p(1 << 20), 1 << 30,
+                            C.c_void_p(1 << 20), None) == L.OTM_ERR_ARG, missing
+        assert lib.otm_init(C.byref(st), C.byref(p), 1e-10, C.c_void_p(1 << 20), 0,
+                            C.c_void_p(1 << 20), 1 << 30, C.c_void_p(1 << 20),
+                            None) == L.OTM_ERR_ARG, missing
