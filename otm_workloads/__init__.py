@@ -278,7 +278,9 @@ def config_by_name(name):
                    300 x 120 um, h = 2 um, 3 node layers: 27,633 nodes /
                    108,000 MPs (the paper's model: 27,417 / 107,975), rigid
                    tool with 2 um tip radius, 0 rake, 100 um depth of cut,
-                   JC flow and fracture, dt = 1e-10 s, 2000 steps
+                   starting 0.25 um clear of the face at 20 m/s (the paper
+                   gives no cutting speed), JC flow and fracture,
+                   dt = 1e-10 s, 2000 steps
     small_cut      a 40 x 24 um piece of the same slab (h = 2 um) with the tool
                    0.2 um clear of it, at 50 m/s, and a low fracture strain
                    (parity tests: contact, friction and fracture within steps)
@@ -299,7 +301,7 @@ def config_by_name(name):
         return taylor_rod(h=0.55e-3, seed=6, radius=3.2e-3, length=32.4e-3, speed=227.0,
                           steps=2000, model=MODEL_J2_LINEAR, name="paper_rod", dt=4e-9)
     if name == "cutting_slab":
-        return cutting_slab()
+        return cutting_slab(speed=20.0, engage=-0.25e-6)
     if name == "small_cut":
         return cutting_slab(length=40e-6, height=24e-6, depth=16e-6, speed=50.0,
                             engage=-0.2e-6, steps=60, name="small_cut",
