@@ -106,7 +106,8 @@ def rollout_backward(sim, ckpt, steps, every, xbar_final, rebuild_every=1):
     # re-run; their tape (every - 1 states) is allocated once and refilled.
     # Each re-run step writes its lists and shape functions straight into its
     # tape entry (otm_step_into), so only node and MP fields are copied.
-    tape = [snapshot(sim) for _ in range(max(min(every, steps) - 1, 0))]
+    tape = [{k: torch.empty_like(getattr(sim, k)) for k in STATE_FIELDS}
+            for _ in range(max(min(every, steps) - 1, 0))]
     own_lists = {k: getattr(sim, k) for k in LIST_FIELDS}
     for s0 in reversed(starts):
         s1 = min(s0 + every, steps)
