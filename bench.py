@@ -420,6 +420,14 @@ def main():
     for k in phases:
         phases[k]["ms"] = round(ph["lme"] + ph["assembly"] if k == "lme_assembly" else ph[k], 4)
     phases["mp_update"] = dict(roof, ms=round(ph["mp_update"], 4))
+    # `roofline` is the MP pass (the kernel the HBM target is set on); the
+    # longest kernel is the shape functions with the fused assembly
+    longest = dict(kernel="k_lme_asm<4, 10, double> (LME Newton + fused atomic assembly)",
+                   ms=phases["lme_assembly"]["ms"],
+                   share_of_step=round(phases["lme_assembly"]["ms"] / main_run["ms_per_step"], 3),
+                   hbm_frac=phases["lme_assembly"]["frac"],
+                   bound="latency of the per-MP Newton chain at two waves per SIMD; FP64 VALU "
+                         "issue ~15 % of peak (profiles/valu_taylor_rod_fp64_mixed.md)")
 
     line = {
         "metric": "material-point steps/s (FP64 vs mixed, 1 GPU) + adjoint/forward time ratio",
@@ -440,6 +448,7 @@ def main():
                    "mean_support": round(main_run["kbar"], 3),
                    "max_support": main_run["max_support"], "parallelism": "single GPU"},
         "roofline": roof,
+        "longest_kernel": longest,
         "phases": phases,
         "variants": variants,
         "adjoint_forward_ratio": None,
