@@ -33,6 +33,24 @@ def snapshot(sim):
     return {k: getattr(sim, k).clone() for k in STATE_FIELDS}
 
 
+def empty_tape(sim, n):
+    """``n`` uninitialised state snapshots carved out of one device buffer
+    (one allocation instead of one per field and entry)."""
+    fields = [(k, getattr(sim, k)) for k in STATE_FIELDS]
+    al = lambda b: (b + 255) // 256 * 256
+    per = sum(al(t.numel() * t.element_size()) for _, t in fields)
+    buf = torch.empty(max(n * per, 1), dtype=torch.uint8, device=sim.device)
+    tape, off = [], 0
+    for _ in range(n):
+        entry = {}
+        for k, t in fields:
+            nb = t.numel() * t.element_size()
+            entry[k] = buf[off:off + nb].view(t.dtype).view(t.shape)
+            off += al(nb)
+        tape.append(entry)
+    return tape
+
+
 def snapshot_into(sim, snap, fields=STATE_FIELDS):
     """Copy state fields into preallocated tensors."""
     torch._foreach_copy_([snap[k] for k in fields], [getattr(sim, k) for k in fields])
@@ -106,8 +124,7 @@ def rollout_backward(sim, ckpt, steps, every, xbar_final, rebuild_every=1):
     # re-run; their tape (every - 1 states) is allocated once and refilled.
     # Each re-run step writes its lists and shape functions straight into its
     # tape entry (otm_step_into), so only node and MP fields are copied.
-    tape = [{k: torch.empty_like(getattr(sim, k)) for k in STATE_FIELDS}
-            for _ in range(max(min(every, steps) - 1, 0))]
+    tape = empty_tape(sim, max(min(every, steps) - 1, 0))
     own_lists = {k: getattr(sim, k) for k in LIST_FIELDS}
     for s0 in reversed(starts):
         s1 = min(s0 + every, steps)

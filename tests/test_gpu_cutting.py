@@ -55,6 +55,24 @@ def test_small_cut_60_steps_fp64(small_cut, scatter):
     assert abs(g["clock"] - st.clock) <= 1e-15 * st.clock
 
 
+def test_small_cut_60_steps_mixed(small_cut):
+    """Mixed precision (stress, F, b^e in float32; the fracture test in
+    float64 on the float32 stresses): every field within the mixed bound of
+    the float64 oracle (measured: 2e-6) and the same MPs failed."""
+    w, p, st = small_cut
+    sim, _ = make_sim(w, precision="mixed")
+    sim.init()
+    sim.run(w.steps)
+    sim.check_diag()
+    g = sim.fields()
+    assert np.array_equal(g["failed"], st.failed)
+    errs = compare(gpu_fields(g, w.x_nodes, w.x_mp, p["T_r"]),
+                   oracle_fields(st, w.x_nodes, w.x_mp, p["T_r"]))
+    print("small cut, mixed, 60 steps:", json.dumps({k: float(v) for k, v in errs.items()}))
+    bad = {k: v for k, v in errs.items() if not v < 1e-5}
+    assert not bad, bad
+
+
 def test_cutting_slab_runs_at_full_size():
     """The paper-size slab: 20 steps without a device failure; the clock and
     the lumped mass (failed MPs keep theirs) behave."""
