@@ -442,8 +442,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: J2/Johnson-Cook rod, {w.n_nodes} nodes, "
-                               f"{w.n_mp} MPs, rebuild every step, atomic assembly",
+        "config": {"workload": f"{w.name}: J2/Johnson-Cook "
+                               f"{'workpiece with fracture and tool contact' if w.tool else 'rod'}, "
+                               f"{w.n_nodes} nodes, {w.n_mp} MPs, rebuild every step, "
+                               "atomic assembly",
                    "n_nodes": w.n_nodes, "n_mp": w.n_mp, "pairs": P,
                    "mean_support": round(main_run["kbar"], 3),
                    "max_support": main_run["max_support"], "parallelism": "single GPU"},
