@@ -88,34 +88,33 @@ OTM_DEV double group_max(double v) {
 }
 
 // Active lanes of a wave that count into the same slot share one atomic: the
-// lanes of each distinct slot id are found by ballot, the lowest of them adds
-// the group's size, and each lane takes its rank inside the group.
-// Spatially ordered items (lattice nodes, MPs in hex order, the pairs of
-// neighbouring MPs) put few distinct slots in a wave.  Returns the value the
-// atomic returned for the lane's group plus the lane's rank in it.
+// lanes of each distinct slot id are found by ballot (a wave-uniform loop of
+// register operations only), then the lowest lane of every id adds its
+// group's size, all ids in one atomic instruction (no chain of returning
+// atomics), and each lane takes the value its group's atomic returned plus
+// its rank in the group.  Spatially ordered items (lattice nodes, MPs in hex
+// order) put few distinct slots in a wave.
 template <typename C>
 OTM_DEV C grouped_atomic_add(C* counters, int32_t cid) {
-  C out = 0;
+  const int lane = (int)__lane_id();
   uint64_t todo = __ballot(true);
+  int leader = lane;
+  C rank = 0, count = 0;
   while (todo) {
-    const int leader = __builtin_ctzll(todo);
-    const int32_t lc = __builtin_amdgcn_readlane(cid, leader);
+    const int l = __builtin_ctzll(todo);
+    const int32_t lc = __builtin_amdgcn_readlane(cid, l);
     const uint64_t same = __ballot(cid == lc);
-    C base = 0;
-    if ((int)__lane_id() == leader) base = atomicAdd(&counters[lc], (C)__popcll(same));
-    if constexpr (sizeof(C) == 8) {
-      const uint64_t u = (uint64_t)base;
-      base = (C)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(u >> 32), leader) << 32) |
-                 __builtin_amdgcn_readlane((uint32_t)u, leader));
-    } else {
-      base = (C)__builtin_amdgcn_readlane((int32_t)base, leader);
+    if (cid == lc) {
+      leader = l;
+      rank = (C)__builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
     }
-    if (cid == lc)
-      out = base + (C)__builtin_amdgcn_mbcnt_hi(
-                       (uint32_t)(same >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+    if (lane == l) count = (C)__popcll(same);
     todo &= ~same;
   }
-  return out;
+  C base = 0;
+  if (lane == leader) base = atomicAdd(&counters[cid], count);
+  return __shfl(base, leader) + rank;
 }
 
 // ------------------------------------------------------------- 3x3 algebra
