@@ -180,7 +180,6 @@ void launch_node_update(const otm_state& st, const otm_params& p, double dt, boo
       n, st.x, st.du, st.m, st.f, dt * dt, p.wall_enabled, p.wall_x[0], p.wall_x[1],
       p.wall_x[2], p.wall_n[0], p.wall_n[1], p.wall_n[2], zero_mf ? 1 : 0, packed, st.n_mp,
       diag, t);
-  if (p.tool_enabled) k_clock_advance<<<1, 1, 0, s>>>(st.clock, dt);
 }
 
 // ----------------------------------------------------- material-point pass
@@ -196,7 +195,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     double* __restrict__ xp, double* __restrict__ vol, R* __restrict__ Fd, R* __restrict__ bed,
     double* __restrict__ epsbar, double* __restrict__ T, R* __restrict__ sigma, Mat<R> M,
     double* __restrict__ xp_prev, double* __restrict__ dFm1, int32_t* __restrict__ failed,
-    otm_diag* diag) {
+    double* __restrict__ clock, double dt, otm_diag* diag) {
   // phase 1: the 12 gathered sums of each MP; phase 2: the MP's eigenvectors,
   // logarithmic strains and J parked over the return-map solve (each lane
   // only touches its own column)
@@ -204,6 +203,9 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   __shared__ int64_t row[kMpBlock + 1];
   const int64_t base = (int64_t)xcd_block() * kMpBlock;
   const int tid = threadIdx.x;
+  // the tool's clock moves on here: the node update before has read it and
+  // the next one comes after this kernel
+  if (clock != nullptr && blockIdx.x == 0 && tid == 0) clock[0] += dt;
   const bool lists_ok = offsets[n_mp] <= cap;
   const bool have_nodes = n_nodes > 0 && cap > 0;
   // the block's row offsets, read once (rows past the end are empty)
@@ -532,19 +534,23 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
 void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
                       const double4* packed, otm_diag* diag, hipStream_t s) {
   const int64_t n = st.n_mp;
-  if (n <= 0) return;
+  if (n <= 0) {
+    if (p.tool_enabled) k_clock_advance<<<1, 1, 0, s>>>(st.clock, dt);
+    return;
+  }
   const unsigned nb = (unsigned)((n + kMpBlock - 1) / kMpBlock);
   double* hist_x = p.eps_stab > 0.0 ? st.xp_prev : nullptr;
   double* hist_f = p.eps_stab > 0.0 ? st.dFm1 : nullptr;
   int32_t* frac = p.fracture ? st.failed : nullptr;
+  double* clock = p.tool_enabled ? st.clock : nullptr;
   if (st.precision == OTM_FP64)
     k_mp_update<double><<<nb, kMpBlock, 0, s>>>(
         packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const double*)st.dN, st.xp, st.vol, (double*)st.Fd, (double*)st.bed, st.epsbar, st.T,
-        (double*)st.sigma, make_mat<double>(p, dt), hist_x, hist_f, frac, diag);
+        (double*)st.sigma, make_mat<double>(p, dt), hist_x, hist_f, frac, clock, dt, diag);
   else
     k_mp_update<float><<<nb, kMpBlock, 0, s>>>(
         packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const float*)st.dN, st.xp, st.vol, (float*)st.Fd, (float*)st.bed, st.epsbar, st.T,
-        (float*)st.sigma, make_mat<float>(p, dt), hist_x, hist_f, frac, diag);
+        (float*)st.sigma, make_mat<float>(p, dt), hist_x, hist_f, frac, clock, dt, diag);
 }
 
 // ------------------------------------------------------------------- t = 0
