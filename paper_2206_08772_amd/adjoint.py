@@ -105,9 +105,32 @@ def rollout_forward(sim, steps, every, rebuild_every=1):
     return ckpt
 
 
+def _replay(sim, ckpt, s0, s1, tape, rebuild_every):
+    """Re-run the interior steps of segment [s0, s1] from checkpoint s0 into
+    ``tape``; returns the segment's states s0..s1 (both ends checkpoints).
+    Each re-run step writes its lists and shape functions straight into its
+    tape entry (otm_step_into), so only node and MP fields are copied."""
+    states = [ckpt[s0]]
+    if s1 - s0 > 1:
+        restore(sim, ckpt[s0], POINT_FIELDS)
+        sim.use_lists(ckpt[s0])          # read by the first step's MP update only
+        for n in range(s0 + 1, s1):
+            entry = tape[n - s0 - 1]
+            sim.step_into(entry, rebuild=(n % rebuild_every == 0))
+            snapshot_into(sim, entry, POINT_FIELDS)
+            states.append(entry)
+    states.append(ckpt[s1])
+    return states
+
+
 def rollout_backward(sim, ckpt, steps, every, xbar_final, rebuild_every=1):
     """Adjoint sweep.  ``xbar_final`` is dL/dx at the last step ([3][n_nodes]).
-    Returns (theta_bar (3,), bars of state 0)."""
+    Returns (theta_bar (3,), bars of state 0).
+
+    Segments are taken from the last to the first.  A segment's two ends are
+    checkpoints, so only its interior states are re-run, into a tape of
+    every - 1 states allocated once and refilled.  The simulation's state is
+    overwritten."""
     L = lib()
     dev = sim.device
     nn, nm, cap = sim.n_nodes, sim.n_mp, sim.cap
@@ -120,26 +143,13 @@ def rollout_backward(sim, ckpt, steps, every, xbar_final, rebuild_every=1):
     starts = sorted(k for k in ckpt if k < steps)
     if not starts or starts[0] != 0 or steps not in ckpt:
         raise ValueError("checkpoints must include step 0 and the last step")
-    # A segment's two ends are checkpoints, so only its interior states are
-    # re-run; their tape (every - 1 states) is allocated once and refilled.
-    # Each re-run step writes its lists and shape functions straight into its
-    # tape entry (otm_step_into), so only node and MP fields are copied.
     tape = empty_tape(sim, max(min(every, steps) - 1, 0))
     own_lists = {k: getattr(sim, k) for k in LIST_FIELDS}
     for s0 in reversed(starts):
         s1 = min(s0 + every, steps)
         if s1 not in ckpt:
             raise ValueError(f"missing checkpoint at step {s1}")
-        states = [ckpt[s0]]
-        if s1 - s0 > 1:
-            restore(sim, ckpt[s0], POINT_FIELDS)
-            sim.use_lists(ckpt[s0])          # read by the first step's MP update only
-            for n in range(s0 + 1, s1):
-                entry = tape[n - s0 - 1]
-                sim.step_into(entry, rebuild=(n % rebuild_every == 0))
-                snapshot_into(sim, entry, POINT_FIELDS)
-                states.append(entry)
-        states.append(ckpt[s1])
+        states = _replay(sim, ckpt, s0, s1, tape, rebuild_every)
         for j in range(s1 - s0 - 1, -1, -1):
             t0 = tape_struct(states[j], nn, nm, cap)
             t1 = tape_struct(states[j + 1], nn, nm, cap)

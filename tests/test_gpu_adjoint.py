@@ -264,3 +264,4 @@ def test_adjoint_step_dot_products_against_oracle_jvp():
     code, _ = read_diag(diag)
     assert code == _lib.OTM_OK
     print(f"adjoint dot products: worst |<bar_n, d> - <bar_n+1, J d>| / scale = {worst:.2e}")
+
