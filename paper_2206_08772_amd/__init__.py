@@ -1,8 +1,19 @@
 """MI355X-native explicit step of the Optimal Transportation Meshfree method.
 
 The compute path is libotm.so (hand-written HIP for gfx950) behind the C ABI
-in include/otm.h.  ``_lib`` is the ctypes view of that ABI and ``sim`` keeps
-the device state in torch tensors.
+in include/otm.h.  ``_lib`` is the ctypes view of that ABI, ``sim`` keeps
+the device state in torch tensors (``Sim``) and ``adjoint`` holds the
+checkpointed reverse-mode rollout (``OTMRollout``).
 Importing the package loads nothing; the library is loaded on first use.
 """
-__all__ = []
+__all__ = ["Sim", "OTMRollout"]
+
+
+def __getattr__(name):
+    if name == "Sim":
+        from .sim import Sim
+        return Sim
+    if name == "OTMRollout":
+        from .adjoint import OTMRollout
+        return OTMRollout
+    raise AttributeError(name)

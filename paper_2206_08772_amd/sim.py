@@ -133,6 +133,20 @@ class Sim:
 
     x_nodes (nn,3), x_mp (np,3), vol_mp, mass_mp (np,), v0_nodes (nn,3) are
     host arrays; ``params`` is a flat dict (oracle keys, including ``dt``).
+    ``precision`` is "fp64" or "mixed"; ``scatter`` "atomic" or "segmented"
+    (bit-reproducible).  The pair buffer is sized from a first search times
+    ``capacity_margin``.  Optional parts follow ``params``: ``eps_stab`` > 0
+    (stabilisation term), ``fracture`` with ``jc_d`` (Johnson-Cook fracture)
+    and ``tool`` with the ``tool_*`` keys (rigid cutting tool).
+
+        import otm_workloads as W
+        w = W.config_by_name("taylor_rod")
+        sim = Sim(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes,
+                  W.params_from_workload(w))
+        sim.init()                    # search, shape functions, assembly at t = 0
+        sim.run(100)                  # otm_step x 100 on the current stream
+        sim.check_diag()              # raises on any device-side failure
+        f = sim.fields()              # host copies in (n, 3) / (n, 3, 3) layouts
     """
 
     def __init__(self, x_nodes, x_mp, vol_mp, mass_mp, v0_nodes, params, precision="fp64",
