@@ -197,3 +197,44 @@ def test_cutting_needs_its_state_arrays(L):
         assert lib.otm_init(C.byref(st), C.byref(p), 1e-10, C.c_void_p(1 << 20), 0,
                             C.c_void_p(1 << 20), 1 << 30, C.c_void_p(1 << 20),
                             None) == L.OTM_ERR_ARG, missing
+
+
+def test_header_compiles_as_c_and_links(L, tmp_path):
+    """include/otm.h is a C header: a C program that includes it, fills the
+    structs and calls two host-only entry points compiles, links against
+    libotm.so and runs (no device work)."""
+    import shutil
+    import subprocess
+    from paper_2206_08772_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text("""
+#include <stdio.h>
+#include <string.h>
+#include "otm.h"
+int main(void) {
+  otm_params p; otm_state st; otm_lists l; otm_tape t; otm_state_bar b; otm_diag d;
+  memset(&p, 0, sizeof p); memset(&st, 0, sizeof st); memset(&l, 0, sizeof l);
+  memset(&t, 0, sizeof t); memset(&b, 0, sizeof b); memset(&d, 0, sizeof d);
+  size_t ws = otm_workspace_bytes(1000, 4000, 100000);
+  const char* s = otm_status_string(OTM_ERR_CAPACITY);
+  printf("%zu %zu %zu %s\\n", ws, sizeof(otm_params), sizeof(otm_state), s);
+  return ws > 0 && s != NULL ? 0 : 1;
+}
+""")
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    cmd = [gcc, "-std=c99", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", "/opt/rocm/include", str(src), "-o", str(exe), "-L", libdir, "-lotm",
+           f"-Wl,-rpath,{libdir}"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    ws, sp, ss, status = r.stdout.split(maxsplit=3)
+    assert int(ws) == L.lib().otm_workspace_bytes(1000, 4000, 100000)
+    assert status.startswith("OTM_ERR_CAPACITY")
+    # the ctypes mirrors have the C layout
+    assert int(sp) == C.sizeof(L.Params) and int(ss) == C.sizeof(L.State)
