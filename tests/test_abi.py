@@ -220,7 +220,8 @@ int main(void) {
   memset(&t, 0, sizeof t); memset(&b, 0, sizeof b); memset(&d, 0, sizeof d);
   size_t ws = otm_workspace_bytes(1000, 4000, 100000);
   const char* s = otm_status_string(OTM_ERR_CAPACITY);
-  printf("%zu %zu %zu %s\\n", ws, sizeof(otm_params), sizeof(otm_state), s);
+  printf("%zu %zu %zu %zu %zu %zu %zu %s\\n", ws, sizeof(otm_params), sizeof(otm_state),
+         sizeof(otm_lists), sizeof(otm_tape), sizeof(otm_state_bar), sizeof(otm_diag), s);
   return ws > 0 && s != NULL ? 0 : 1;
 }
 """)
@@ -233,8 +234,10 @@ int main(void) {
     assert r.returncode == 0, r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stderr
-    ws, sp, ss, status = r.stdout.split(maxsplit=3)
-    assert int(ws) == L.lib().otm_workspace_bytes(1000, 4000, 100000)
+    *sizes, status = r.stdout.split(maxsplit=7)
+    ws, sizes = int(sizes[0]), [int(v) for v in sizes[1:]]
+    assert ws == L.lib().otm_workspace_bytes(1000, 4000, 100000)
     assert status.startswith("OTM_ERR_CAPACITY")
-    # the ctypes mirrors have the C layout
-    assert int(sp) == C.sizeof(L.Params) and int(ss) == C.sizeof(L.State)
+    # the ctypes mirrors have the C sizes
+    assert sizes == [C.sizeof(t) for t in (L.Params, L.State, L.Lists, L.Tape, L.StateBar,
+                                            L.Diag)]
