@@ -53,3 +53,23 @@ def test_step_graph_replays_match_eager_steps(scatter):
                 assert err < 1e-11, (r, k, err)
     eager.check_diag()
     graphed.check_diag()
+
+
+def test_cutting_step_graph_replays_match_eager_steps():
+    """The chip-formation step (tool contact, its device clock, fracture) in a
+    captured graph: 5 replays of 6 steps of the small cut against eager steps,
+    bit for bit with the segmented assembly, failure flags, tangential gaps
+    and clock included."""
+    w = W.config_by_name("small_cut")
+    eager, graphed = _pair(w, "segmented")
+    g = graphed.capture(steps=6)
+    for r in range(5):
+        g.replay()
+        eager.run(6)
+        a, b = eager.fields(), graphed.fields()
+        for k in FIELDS + ("failed", "gT"):
+            assert np.array_equal(a[k], b[k]), (r, k)
+        assert a["clock"] == b["clock"]
+    assert b["failed"].sum() > 0 or (np.abs(b["gT"]).sum() > 0)
+    eager.check_diag()
+    graphed.check_diag()
