@@ -293,6 +293,48 @@ class Sim:
                                 self.ws.ptr, self.ws.nbytes, _ptr(self.diag), _stream()),
               "otm_refresh")
 
+    # ------------------------------------------------------- save / resume
+    _SAVED = ("x", "du", "m", "f", "xp", "vol", "mass", "lam", "Fd", "bed", "epsbar", "T",
+              "sigma", "offsets", "idx", "N", "dN", "xp_prev", "dFm1", "failed", "tool_gt",
+              "clock", "v0")
+
+    def state_dict(self):
+        """Host copies of every state array and the step count: what a later
+        ``load_state_dict`` (on a Sim of the same workload, parameters,
+        precision and pair capacity) needs to resume the run exactly."""
+        torch.cuda.synchronize(self.device)
+        d = {k: getattr(self, k).detach().cpu().clone() for k in self._SAVED
+             if getattr(self, k) is not None}
+        d["n"] = int(self.n)
+        return d
+
+    def load_state_dict(self, d):
+        """Resume from ``state_dict()``.  The lists are searched again (the
+        search is exact, so they come out the same) so that workspace data
+        derived from them (the segmented mode's influence lists) is rebuilt;
+        then every saved array, mass and force included, is put back."""
+        for k in self._SAVED:
+            t = getattr(self, k)
+            if t is None:
+                continue
+            if k not in d or tuple(d[k].shape) != tuple(t.shape) or d[k].dtype != t.dtype:
+                raise ValueError(f"saved {k!r} does not match this simulation")
+        for k in self._SAVED:
+            if getattr(self, k) is not None:
+                getattr(self, k).copy_(d[k])
+        self.refresh(rebuild=True)
+        for k in self._SAVED:
+            if getattr(self, k) is not None:
+                getattr(self, k).copy_(d[k])
+        self.n = int(d["n"])
+        return self
+
+    def save(self, path):
+        torch.save(self.state_dict(), path)
+
+    def load(self, path):
+        return self.load_state_dict(torch.load(path, weights_only=True))
+
     def check_diag(self, raise_on_error=True):
         code, d = read_diag(self.diag)
         if raise_on_error and code != _lib.OTM_OK:
