@@ -17,8 +17,9 @@ published with it, so every workload here is a same-shape stand-in:
   around its (0,0,0)-(1,1,1) diagonal; lattice points that are the corner of
   no such cell are dropped (they would be nodes without mass);
 * one MP per tet at the centroid, volume |det| / 6, mass rho0 * volume,
-  ordered hex-cell-major then by tet index (so MPs that are close in space are
-  close in memory).
+  ordered by hex cell, the hex cells in Z-order (Morton order) of their
+  lattice index, then by tet index (so any run of consecutive MPs is a compact
+  brick of the body).
 """
 from __future__ import annotations
 
@@ -121,7 +122,22 @@ class Workload:
         return self.r_cut + self.skin
 
 
-def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False, clamp_x0=False):
+def _morton3(i, j, k):
+    """Morton (Z-order) code of non-negative integer lattice indices: their
+    bits interleaved, 21 bits each."""
+    def spread(v):
+        v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
+        v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+        v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+        v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+        v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+        v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
+        return v
+    return spread(i) | (spread(j) << np.uint64(1)) | (spread(k) << np.uint64(2))
+
+
+def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False, clamp_x0=False,
+                  hex_order="morton"):
     """Lattice nodes inside a body, their jitter, the hex cells and tets.
 
     ``inside(i, j, k)`` receives integer index arrays and returns a mask.
@@ -153,6 +169,13 @@ def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False, clamp_x0=False):
     corners = np.stack(corners, axis=1)
     full = (corners >= 0).all(axis=1)
     corners = corners[full]
+    if hex_order == "morton":
+        # hexes (and so their MPs) in Z-order of their lattice index: any run
+        # of consecutive MPs is a compact brick of the body
+        kk, jj, ii = np.meshgrid(np.arange(nk - 1), np.arange(nj - 1), np.arange(ni - 1),
+                                 indexing="ij")
+        code = _morton3(ii.ravel()[full], jj.ravel()[full], kk.ravel()[full])
+        corners = corners[np.argsort(code, kind="stable")]
     tet_nodes = corners[:, np.array(KUHN_TETS)]          # (n_hex, 6, 4)
     tet_nodes = tet_nodes.reshape(-1, 4)
     # lattice points that belong to no complete hex cell would carry no mass
@@ -192,7 +215,7 @@ def jc_params(seed):
 
 def taylor_rod(h, seed, radius=3.2e-3, length=21.12e-3, speed=190.0, steps=100,
                model=MODEL_J2_JC, skin_h=0.0, rebuild_every=1, name="taylor_rod",
-               material=None, dt=None):
+               material=None, dt=None, hex_order="morton"):
     """Cylinder of radius R and length L (z axis) on a jittered lattice,
     flying at -speed along z into a rigid frictionless wall z = 0.
 
@@ -206,7 +229,7 @@ def taylor_rod(h, seed, radius=3.2e-3, length=21.12e-3, speed=190.0, steps=100,
         return (i * h) ** 2 + (j * h) ** 2 <= radius ** 2
 
     x, X, x_mp, vol = _lattice_body(((-nr, nr), (-nr, nr), (0, nz)), inside, h, seed,
-                                    clamp_z0=True)
+                                    clamp_z0=True, hex_order=hex_order)
     if material is None:
         material = Material(model, E=117e9, nu=0.35, rho0=8930.0, chi=0.9,
                             T_r=293.0, T_m=1356.0, Cp=385.0, eps_dot0=1.0,
