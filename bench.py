@@ -264,6 +264,15 @@ def _run_paper_size(w, label, paper_s, warmup, graph_steps):
             out["failed_mps_at_end"] = int(sim.failed.sum())
         if mode == "eager" and sim.tool:
             out["nodes_with_tangential_gap_at_end"] = int((sim.tool_gt.abs().sum(0) > 0).sum())
+        if mode == "eager" and sim.fracture:
+            # removal of the failed MPs and the refresh of the rest, host wall time
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            removed = sim.erode()
+            torch.cuda.synchronize()
+            sim.check_diag()
+            out["erode"] = dict(removed=removed, n_mp_after=sim.n_mp,
+                                ms=round(1e3 * (time.perf_counter() - t), 3))
         del sim, g
         torch.cuda.empty_cache()
     best = min(out["eager"]["ms_per_step"], out["graph"]["ms_per_step"]) * 1e-3

@@ -144,7 +144,7 @@ typedef struct otm_state {
   /* material points */
   double* xp;             /* [3][n_mp] positions */
   double* vol;            /* [n_mp] current volume */
-  const double* mass;     /* [n_mp] mass (constant) */
+  const double* mass;     /* [n_mp] mass (constant; otm_erode compacts it) */
   double* lam;            /* [3][n_mp] LME multiplier (warm start) */
   void* Fd;               /* [9][n_mp] F - 1 (double, or float in OTM_MIXED) */
   void* bed;              /* [6][n_mp] b^e - 1 (double / float) */
@@ -295,6 +295,27 @@ typedef struct otm_lists {
 otm_status otm_step_into(otm_state* st, const otm_lists* next, const otm_params* p, double dt,
                          int32_t rebuild, int32_t scatter_mode, void* ws, size_t ws_bytes,
                          otm_diag* diag, hipStream_t s);
+
+/*
+ * Erosion: removes from the body the material points that met the fracture
+ * criterion (Sec. 4.2, Johnson-Cook fracture separates the chip; the removal
+ * of material points from the domain is the operation of the data management
+ * in Sec. 3.3).  Requires params.fracture = 1 and params.eps_stab = 0.
+ * Every per-MP array of *st (xp, vol, mass, lam, Fd, bed, epsbar, T, sigma,
+ * failed) is compacted in place: the surviving MPs keep their order and the
+ * component stride of each [k][n_mp] array becomes the new n_mp, which is
+ * written to st->n_mp; the arrays keep their allocation.  failed is 0 for all
+ * survivors afterwards.  Then, as otm_refresh with rebuild = 1, the support
+ * lists, shape functions and the nodal mass and force of the remaining body
+ * are recomputed, so that otm_step can follow; a node no longer in any
+ * support gets zero mass and force.  *n_removed (host) receives the number
+ * of MPs removed.  ws is the step workspace for the state's size before the
+ * call.  Synchronises the stream once (to read the survivor count), so it
+ * cannot be captured in a graph.  Errors: OTM_ERR_ARG for invalid arguments
+ * (state unchanged), OTM_ERR_HIP; the refresh's errors appear in diag.
+ */
+otm_status otm_erode(otm_state* st, const otm_params* p, int32_t scatter_mode, void* ws,
+                     size_t ws_bytes, otm_diag* diag, int64_t* n_removed, hipStream_t s);
 
 /* One stored step of a forward trajectory (host struct of device pointers,
  * float64 state as in otm_state with precision OTM_FP64).  Pair arrays N and

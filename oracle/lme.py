@@ -124,6 +124,9 @@ def lme_shape(x_nodes, x_mp, offsets, idx, beta, tol, max_iter=50, lam0=None,
     x_nodes = np.asarray(x_nodes)
     x_mp = np.asarray(x_mp)
     n_mp = x_mp.shape[0]
+    if n_mp == 0:                       # no material points: nothing to solve
+        lam = np.zeros((0, 3)) if lam0 is None else np.asarray(lam0)
+        return lam, np.zeros(0), np.zeros((0, 3))
     pair, mask = padded_pairs(offsets, idx)
     nodes = np.asarray(idx)[pair]
     d = x_mp[:, None, :] - x_nodes[nodes]

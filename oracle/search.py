@@ -75,6 +75,8 @@ def neighbors_linked_cell(x_nodes, x_mp, r, cell_size):
     x_nodes = np.asarray(x_nodes, np.float64)
     x_mp = np.asarray(x_mp, np.float64)
     n_mp = x_mp.shape[0]
+    if n_mp == 0:                       # no material points: no supports
+        return np.zeros(1, np.int64), np.zeros(0, np.int32)
     lo, dims = cell_grid(x_nodes, cell_size)
     cn = cell_coords(x_nodes, lo, cell_size, dims)
     cid = (cn[:, 2] * dims[1] + cn[:, 1]) * dims[0] + cn[:, 0]

@@ -254,6 +254,28 @@ def init_state(x_nodes, x_mp, vol, mass, v0_nodes, p, lists=None):
     return st
 
 
+MP_FIELDS = ("xp", "vol", "mass", "lam", "F", "be", "epsbar", "T", "sigma", "failed")
+
+
+def erode(st, p):
+    """Erosion: the MPs that met the fracture criterion leave the body.
+
+    Reading: Johnson-Cook fracture separates material (Sec. 4.2) and the
+    data management of Sec. 3.3 removes material points from the domain; a
+    removed MP takes its mass and volume with it.  The survivors keep their
+    order.  The support lists, shape functions and the lumped mass and force
+    of what remains are then recomputed, as at the end of a step.  Returns
+    the number of MPs removed."""
+    keep = ~st.failed
+    for k in MP_FIELDS + ("xp_prev", "dF"):
+        if getattr(st, k) is not None:
+            setattr(st, k, getattr(st, k)[keep])
+    rebuild_lists(st, p)
+    shape(st, p)
+    assemble(st, p)
+    return int((~keep).sum())
+
+
 def step(st, p, lists=None):
     """One step n -> n+1 in place.  ``lists`` (offsets, idx) forces the
     support lists (frozen-list runs); otherwise they are rebuilt every

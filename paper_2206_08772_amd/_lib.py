@@ -112,6 +112,8 @@ _SIGS = {
     "otm_step_into": (C.c_int32, [C.POINTER(State), C.POINTER(Lists), C.POINTER(Params),
                                   C.c_double, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
                                   C.c_void_p, C.c_void_p]),
+    "otm_erode": (C.c_int32, [C.POINTER(State), C.POINTER(Params), C.c_int32, C.c_void_p,
+                              C.c_size_t, C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
     "otm_step_profiled": (C.c_int32, [C.POINTER(State), C.POINTER(Params), C.c_double,
                                       C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                       C.c_void_p, C.c_void_p]),

@@ -397,6 +397,27 @@ otm_status otm_step_profiled(otm_state* st, const otm_params* p, double dt, int3
   return step_impl(st, p, dt, rebuild, scatter_mode, ws, ws_bytes, diag, events, s);
 }
 
+otm_status otm_erode(otm_state* st, const otm_params* p, int32_t scatter_mode, void* ws,
+                     size_t ws_bytes, otm_diag* diag, int64_t* n_removed, hipStream_t s) {
+  otm_status e;
+  if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
+  if (n_removed == nullptr || !p->fracture || p->eps_stab > 0.0) return OTM_ERR_ARG;
+  if (scatter_mode != OTM_SCATTER_ATOMIC && scatter_mode != OTM_SCATTER_SEGMENTED)
+    return OTM_ERR_ARG;
+  if (!dev_ok(diag, 8)) return OTM_ERR_ARG;
+  if ((e = check_cut_state(st, p)) != OTM_OK) return e;
+  Workspace w;
+  if (check_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &w) != OTM_OK)
+    return OTM_ERR_ARG;
+  const int64_t n0 = st->n_mp;
+  otm_state to = *st;
+  if ((e = launch_erode(to, w, s)) != OTM_OK) return e;
+  st->n_mp = to.n_mp;
+  *n_removed = n0 - to.n_mp;
+  // lists, shape functions, mass and force of the remaining body
+  return otm_refresh(st, p, 1, scatter_mode, ws, ws_bytes, diag, s);
+}
+
 size_t otm_adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp) {
   if (n_nodes < 0 || n_mp < 0) return 0;
   return adjoint_workspace_bytes(n_nodes, n_mp);

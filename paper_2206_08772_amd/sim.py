@@ -21,6 +21,14 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
 
 
+def _addr(t):
+    """Device address of a state array: an empty view (a body whose MPs were
+    all removed) still names its allocation, which the state checks want."""
+    if t is None:
+        return C.c_void_p(0)
+    return C.c_void_p(t.untyped_storage().data_ptr() + t.storage_offset() * t.element_size())
+
+
 def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -214,16 +222,16 @@ class Sim:
         s.n_nodes, s.n_mp, s.pair_capacity, s.precision = self.n_nodes, self.n_mp, self.cap, self.prec
         for k in ("x", "du", "m", "f", "xp", "vol", "mass", "lam", "Fd", "bed", "epsbar", "T",
                   "sigma"):
-            setattr(s, k, _ptr(getattr(self, k)).value)
-        s.nbr_offsets = _ptr(self.offsets).value
-        s.nbr_idx = _ptr(self.idx).value
-        s.N = _ptr(self.N).value
-        s.dN = _ptr(self.dN).value
-        s.xp_prev = _ptr(self.xp_prev).value if self.stab else None
-        s.dFm1 = _ptr(self.dFm1).value if self.stab else None
-        s.failed = _ptr(self.failed).value if self.fracture else None
-        s.tool_gt = _ptr(self.tool_gt).value if self.tool else None
-        s.clock = _ptr(self.clock).value if self.tool else None
+            setattr(s, k, _addr(getattr(self, k)).value)
+        s.nbr_offsets = _addr(self.offsets).value
+        s.nbr_idx = _addr(self.idx).value
+        s.N = _addr(self.N).value
+        s.dN = _addr(self.dN).value
+        s.xp_prev = _addr(self.xp_prev).value if self.stab else None
+        s.dFm1 = _addr(self.dFm1).value if self.stab else None
+        s.failed = _addr(self.failed).value if self.fracture else None
+        s.tool_gt = _addr(self.tool_gt).value if self.tool else None
+        s.clock = _addr(self.clock).value if self.tool else None
 
     # ---------------------------------------------------------------- calls
     def init(self):
@@ -292,6 +300,26 @@ class Sim:
         check(lib().otm_refresh(C.byref(self.st), C.byref(self.p), 1 if rebuild else 0, self.mode,
                                 self.ws.ptr, self.ws.nbytes, _ptr(self.diag), _stream()),
               "otm_refresh")
+
+    def erode(self):
+        """Remove the failed MPs from the body (otm_erode) and recompute the
+        lists, shape functions, mass and force of the rest.  The per-MP
+        tensors become views of their first n_mp entries per component (the
+        memory stays allocated).  Returns the number of MPs removed."""
+        removed = C.c_int64(0)
+        check(lib().otm_erode(C.byref(self.st), C.byref(self.p), self.mode, self.ws.ptr,
+                              self.ws.nbytes, _ptr(self.diag), C.byref(removed), _stream()),
+              "otm_erode")
+        n = int(self.st.n_mp)
+        for k in ("xp", "lam", "Fd", "bed", "sigma"):
+            t = getattr(self, k)
+            setattr(self, k, t.reshape(-1)[: t.shape[0] * n].view(t.shape[0], n))
+        for k in ("vol", "mass", "epsbar", "T", "failed"):
+            setattr(self, k, getattr(self, k)[:n])
+        self.offsets = self.offsets[: n + 1]
+        self.n_mp = n
+        self._fill_state()
+        return int(removed.value)
 
     # ------------------------------------------------------- save / resume
     _SAVED = ("x", "du", "m", "f", "xp", "vol", "mass", "lam", "Fd", "bed", "epsbar", "T",

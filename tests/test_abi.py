@@ -241,3 +241,29 @@ int main(void) {
     # the ctypes mirrors have the C sizes
     assert sizes == [C.sizeof(t) for t in (L.Params, L.State, L.Lists, L.Tape, L.StateBar,
                                             L.Diag)]
+
+
+def test_erode_argument_checks(L):
+    """otm_erode needs the fracture model, no stabilisation term, a place for
+    the count and a known assembly; it rejects before enqueuing anything and
+    leaves the state as it was."""
+    from paper_2206_08772_amd.sim import make_params
+    lib = L.lib()
+    w = W.config_by_name("small_cut")
+    ws, diag = C.c_void_p(1 << 20), C.c_void_p(1 << 20)
+    n = C.c_int64(-1)
+
+    def call(p, st, out=C.byref(n), mode=0):
+        return lib.otm_erode(C.byref(st), C.byref(p), mode, ws, 1 << 30, diag, out, None)
+
+    st = _fake_state(L)
+    ok = make_params(W.params_from_workload(w))
+    assert call(make_params(W.params_from_workload(w, fracture=False)), st) == L.OTM_ERR_ARG
+    assert call(make_params(W.params_from_workload(w, eps_stab=1.0)), st) == L.OTM_ERR_ARG
+    assert call(ok, st, out=None) == L.OTM_ERR_ARG
+    assert call(ok, st, mode=7) == L.OTM_ERR_ARG
+    assert lib.otm_erode(C.byref(st), C.byref(ok), 0, ws, 1 << 30, C.c_void_p(0), C.byref(n),
+                         None) == L.OTM_ERR_ARG
+    st.failed = 0
+    assert call(ok, st) == L.OTM_ERR_ARG
+    assert n.value == -1 and st.n_mp == 20

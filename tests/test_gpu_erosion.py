@@ -1,0 +1,95 @@
+"""Erosion (otm_erode) on the GPU against the oracle's erode: the small cut
+with the failed MPs removed after steps 30, 45 and 60 and five more steps
+after the last removal, float64, both assemblies; then the degenerate
+removals (nothing failed, everything failed) on the same state."""
+import json
+
+import numpy as np
+import pytest
+
+import otm_workloads as W
+from oracle import step as OST
+from tests.gpu_common import make_sim, require_gpu
+from tests.helpers import compare, gpu_fields, oracle_fields
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+ERODE_AT = (30, 45, 60)
+STEPS = 65
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.fixture(scope="module")
+def eroded_cut():
+    w = W.config_by_name("small_cut")
+    p = W.params_from_workload(w)
+    st = OST.init_state(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p)
+    orig = np.arange(w.x_mp.shape[0])
+    removed = []
+    for s in range(1, STEPS + 1):
+        OST.step(st, p)
+        if s in ERODE_AT:
+            orig = orig[~st.failed]
+            removed.append(OST.erode(st, p))
+    assert all(r > 0 for r in removed)
+    return w, p, st, orig, removed
+
+
+def _run_gpu(w, scatter):
+    sim, _ = make_sim(w, scatter=scatter)
+    sim.init()
+    removed = []
+    for s in range(1, STEPS + 1):
+        sim.step()
+        if s in ERODE_AT:
+            removed.append(sim.erode())
+    sim.check_diag()
+    return sim, removed
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "segmented"])
+def test_eroded_small_cut_fp64(eroded_cut, scatter):
+    w, p, st, orig, removed = eroded_cut
+    print(f"eroded small cut, {scatter}: removals at {ERODE_AT}", flush=True)
+    sim, got = _run_gpu(w, scatter)
+    assert got == removed and sim.n_mp == st.xp.shape[0]
+    g = sim.fields()
+    assert np.array_equal(g["offsets"], st.offsets) and np.array_equal(g["idx"], st.idx)
+    assert np.array_equal(g["failed"], st.failed)
+    assert np.array_equal(sim.mass.cpu().numpy(), st.mass)
+    errs = compare(gpu_fields(g, w.x_nodes, w.x_mp[orig], p["T_r"]),
+                   oracle_fields(st, w.x_nodes, w.x_mp[orig], p["T_r"]))
+    print("removed", removed, json.dumps({k: float(v) for k, v in errs.items()}))
+    bad = {k: v for k, v in errs.items() if not v < FP64_TOL}
+    assert not bad, bad
+
+
+def test_erode_nothing_then_everything():
+    """Nothing failed: the lists come out as the step left them and the MP
+    count is unchanged.  Every MP failed: an empty body with zero mass and
+    force, which still steps (the nodes coast)."""
+    w = W.config_by_name("small_cut")
+    sim, _ = make_sim(w)
+    sim.init()
+    for _ in range(5):
+        sim.step()
+    sim.check_diag()
+    before = sim.fields()
+    assert not before["failed"].any()
+    assert sim.erode() == 0
+    after = sim.fields()
+    assert np.array_equal(after["offsets"], before["offsets"])
+    assert np.array_equal(after["idx"], before["idx"])
+    assert np.array_equal(after["xp"], before["xp"])
+    n = sim.n_mp
+    sim.failed.fill_(1)
+    assert sim.erode() == n and sim.n_mp == 0
+    sim.step()
+    sim.check_diag()
+    g = sim.fields()
+    assert g["offsets"].tolist() == [0] and not g["m"].any() and not g["f"].any()
