@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libotm.so")
-SOURCES = ["api.hip", "search.hip", "lme.hip", "mp_update.hip", "scatter.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "search.hip", "lme.hip", "mp_update.hip", "scatter.hip", "adjoint.hip",
+           "erode.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

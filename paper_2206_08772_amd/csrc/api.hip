@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include "erode.h"
 #include "launch.h"
 #include "otm_common.h"
 

@@ -104,10 +104,6 @@ void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
                       const double4* packed, otm_diag* diag, hipStream_t s);
 void launch_init_fields(const otm_state& st, const otm_params& p, double dt, const double* v0,
                         hipStream_t s);
-// Removes the MPs flagged in st.failed from every per-MP array (stable
-// order; component stride becomes the survivor count) and sets st.n_mp.
-// Synchronises the stream once, to read the survivor count.
-otm_status launch_erode(otm_state& st, const Workspace& w, hipStream_t s);
 void launch_zero(double* a, int64_t n, hipStream_t s);
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_i64(int64_t* a, int64_t n, int64_t v, hipStream_t s);
