@@ -119,9 +119,10 @@ def flow_stress(p, epsbar, deps, dt, Tstar):
         return p["Y0"] + p["H"] * (epsbar + deps), p["H"] + 0 * deps
     A, B, n, C, m = p["A"], p["B"], p["n"], p["C"], p["m"]
     e = epsbar + deps
-    e_pos = np.where(e.real > 0, e, 1.0)
-    hard = A + B * np.where(e.real > 0, e_pos ** n, 0.0)
-    dhard = np.where(e.real > 0, B * n * e_pos ** (n - 1), np.inf)
+    pos = e.real > 0
+    e_pos = np.where(pos, e, 1.0)
+    hard = A + B * np.where(pos, e_pos ** n, 0.0)
+    dhard = np.where(pos, B * n * e_pos ** (n - 1), 0.0)
     ratio = deps / (dt * p["eps_dot0"])
     above = ratio.real > 1.0
     ratio_safe = np.where(above, ratio, 1.0)
@@ -131,7 +132,9 @@ def flow_stress(p, epsbar, deps, dt, Tstar):
     Ts = np.where(Tstar.real > 0, Tstar, 1.0)
     therm = 1.0 - np.where(Tstar.real > 0, Ts ** m, 0.0)
     sy = hard * rate * therm
-    dsy = (dhard * rate + hard * drate) * therm
+    # at epsbar + deps = 0 the slope is infinite for n < 1; callers ask for it
+    # there only to discard it, and it is set to inf without forming inf * 0
+    dsy = np.where(pos, (dhard * rate + hard * drate) * therm, np.inf)
     return sy, dsy
 
 
