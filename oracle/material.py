@@ -187,11 +187,14 @@ def solve_return(p, q_tr, epsbar, Tstar, dt, mu, tol=1e-14, max_iter=60, polish=
     return x, sy
 
 
-def j2_update(p, dF, be_n, epsbar_n, T_n, J_new, dt, spectral="eigh", polish=0):
+def j2_update(p, dF, be_n, epsbar_n, T_n, J_new, dt, spectral="eigh", polish=0, dT_extra=0.0):
     """Elastic predictor / radial return (Sec. 4.1, Sec. 4.2).
 
     dF: (n,3,3) incremental deformation gradient, be_n: (n,3,3) elastic left
     Cauchy-Green tensor, epsbar_n, T_n: (n,), J_new = det F_{n+1}.
+    ``dT_extra`` (JC only): a temperature increment from elsewhere (heat
+    conduction) added to T_{n+1} with the plastic heating; the flow stress
+    still softens with T_n.
     Returns sigma, be_new, epsbar_new, T_new, deps.
     """
     lam, mu = lame(p["E"], p["nu"])
@@ -226,7 +229,7 @@ def j2_update(p, dF, be_n, epsbar_n, T_n, J_new, dt, spectral="eigh", polish=0):
     epsbar_new = epsbar_n + deps
     if p["model"] == J2_JC:
         q_new = scale * q_tr
-        T_new = T_n + p["chi"] * q_new * deps / (p["rho0"] * p["Cp"])
+        T_new = T_n + dT_extra + p["chi"] * q_new * deps / (p["rho0"] * p["Cp"])
     else:
         T_new = T_n + 0.0 * deps
     return sigma, be_new, epsbar_new, T_new, deps

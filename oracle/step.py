@@ -43,7 +43,7 @@ import dataclasses
 
 import numpy as np
 
-from . import contact, lme, material, search
+from . import conduction, contact, lme, material, search
 
 
 @dataclasses.dataclass
@@ -76,6 +76,14 @@ class State:
     failed: np.ndarray = None
     gT: np.ndarray = None
     clock: float = 0.0
+    # heat conduction (kappa > 0): MP heat flux of the last MP update, the
+    # nodal sums h_I, Q_I of the last assembly and the nodal temperature and
+    # rate formed from them by the node update
+    q: np.ndarray = None
+    heat_h: np.ndarray = None
+    heat_Q: np.ndarray = None
+    T_nodes: np.ndarray = None
+    rate_nodes: np.ndarray = None
 
     def copy(self):
         return State(**{k: (v.copy() if isinstance(v, np.ndarray) else v)
@@ -104,6 +112,8 @@ def assemble(st, p):
             f[:, i] = f[:, i] + 1j * np.bincount(st.idx, weights=contrib[:, i].imag,
                                                  minlength=n_nodes)
     st.m, st.f = m, f
+    if st.q is not None:
+        st.heat_h, st.heat_Q = conduction.assemble_heat(st, mp_of_pair, n_nodes)
 
 
 def underintegration_error(st, mp_of_pair):
@@ -140,6 +150,8 @@ def node_update(st, p):
         du = np.where(hit[:, None], xs - st.x, du)
     st.du = du
     st.x = xs
+    if st.q is not None:
+        st.T_nodes, st.rate_nodes = conduction.nodal_fields(st.m, st.heat_h, st.heat_Q, p["Cp"])
 
 
 def mp_update(st, p):
@@ -166,35 +178,47 @@ def mp_update(st, p):
     st.xp_prev, st.dF = st.xp, dF
     st.xp = xp
     J_new = material.det3(F_new)
+    dTc, grad = 0.0, None
+    if st.q is not None:
+        # conduction with the shape functions of step n and the nodal field
+        # of the node update
+        grad, dTc = conduction.mp_terms(st.offsets, st.idx, st.N, st.dN, st.T_nodes,
+                                        st.rate_nodes, p["dt"], _segsum)
     if p["model"] == material.NEOHOOKE:
         st.sigma = material.neo_hooke_cauchy(F_new, p["E"], p["nu"])
     elif st.failed is None:
         sig, be, eb, T, _ = material.j2_update(p, dF, st.be, st.epsbar, st.T, J_new, p["dt"],
                                                spectral=p.get("spectral", "eigh"),
-                                               polish=p.get("polish", 0))
+                                               polish=p.get("polish", 0), dT_extra=dTc)
         st.sigma, st.be, st.epsbar, st.T = sig, be, eb, T
     else:
-        _update_with_fracture(st, p, dF, J_new)
+        _update_with_fracture(st, p, dF, J_new, dTc)
+    if grad is not None:
+        st.q = -p["kappa"] * grad
     st.F = F_new
 
 
-def _update_with_fracture(st, p, dF, J_new):
+def _update_with_fracture(st, p, dF, J_new, dTc=0.0):
     """The J2 update of the MPs that have not failed, then the Johnson-Cook
     fracture criterion (Sec. 4.2): an MP whose equivalent plastic strain is
     positive and at least the critical strain at its stress triaxiality, rate
     and temperature fails.  Readings: an MP that never yielded does not
     fracture (ductile fracture follows plastic flow); a failed MP carries no
     stress from then on (it is eroded) but keeps its mass, so the lumped mass
-    is conserved, and its b^e, epsbar and T stay as they were."""
+    is conserved, and its b^e, epsbar and T stay as they were (but for the
+    conduction increment dTc, which every MP takes: a failed MP still holds
+    heat)."""
     alive = np.nonzero(~st.failed)[0]
     sigma = np.zeros_like(st.sigma, dtype=np.result_type(st.sigma, dF))
     be = st.be.astype(sigma.dtype)
     eb = st.epsbar.astype(sigma.dtype)
-    T = st.T.astype(sigma.dtype)
+    dTc = np.broadcast_to(np.asarray(dTc), st.T.shape)
+    T = (st.T + dTc).astype(sigma.dtype)
     if alive.size:
         s_a, be_a, eb_a, T_a, de_a = material.j2_update(
             p, dF[alive], st.be[alive], st.epsbar[alive], st.T[alive], J_new[alive], p["dt"],
-            spectral=p.get("spectral", "eigh"), polish=p.get("polish", 0))
+            spectral=p.get("spectral", "eigh"), polish=p.get("polish", 0),
+            dT_extra=dTc[alive])
         eta = material.triaxiality(s_a.real)
         ef = material.jc_fracture_strain(p, eta, de_a.real, p["dt"], T_a.real)
         newly = (eb_a.real > 0) & (eb_a.real >= ef)
@@ -244,7 +268,8 @@ def init_state(x_nodes, x_mp, vol, mass, v0_nodes, p, lists=None):
                epsbar=np.zeros(n_mp), T=np.full(n_mp, float(p["T_r"])),
                sigma=np.zeros((n_mp, 3, 3)), offsets=None, idx=None, N=None, dN=None,
                failed=np.zeros(n_mp, bool) if p.get("fracture") else None,
-               gT=np.zeros((n_nodes, 3)) if p.get("tool") else None)
+               gT=np.zeros((n_nodes, 3)) if p.get("tool") else None,
+               q=np.zeros((n_mp, 3)) if p.get("kappa", 0.0) > 0 else None)
     if lists is None:
         rebuild_lists(st, p)
     else:
@@ -254,7 +279,7 @@ def init_state(x_nodes, x_mp, vol, mass, v0_nodes, p, lists=None):
     return st
 
 
-MP_FIELDS = ("xp", "vol", "mass", "lam", "F", "be", "epsbar", "T", "sigma", "failed")
+MP_FIELDS = ("xp", "vol", "mass", "lam", "F", "be", "epsbar", "T", "sigma", "failed", "q")
 
 
 def erode(st, p):

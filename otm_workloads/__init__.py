@@ -57,6 +57,8 @@ class Material:
     # linear isotropic hardening (Sec. 4.1 yield function)
     Y0: float = 0.0
     H: float = 0.0
+    # thermal conductivity (W / (m K)); 0: adiabatic, no conduction
+    kappa: float = 0.0
 
     @property
     def lame(self):
@@ -205,6 +207,21 @@ def elastic_cube(n=10, h=1.0, seed=0, steps=10):
     return Workload("elastic_cube", h, x, X, x_mp, vol, mat.rho0 * vol, v0, mat, dt, steps)
 
 
+def heat_bar(n=(21, 3, 3), h=1.0, seed=0, kappa=1.0, rho0=1.0, Cp=1.0, dt=0.02, steps=500):
+    """A bar at rest for heat conduction: an (nx, ny, nz) node lattice of
+    spacing h, a J2/JC material that never yields (A far above any stress;
+    nothing moves, so the stress stays 0), thermal conductivity kappa,
+    density rho0 and heat capacity Cp (diffusivity kappa / (rho0 Cp)), no
+    velocity.  The initial temperature field is the caller's."""
+    nx, ny, nz = n
+    x, X, x_mp, vol = _lattice_body(((0, nx - 1), (0, ny - 1), (0, nz - 1)),
+                                    lambda i, j, k: np.ones(i.shape, bool), h, seed)
+    mat = Material(MODEL_J2_JC, E=200.0, nu=0.3, rho0=rho0, A=1e30, B=0.0, n=1.0, C=0.0,
+                   m=1.0, T_r=0.0, T_m=1e6, Cp=Cp, chi=0.0, kappa=kappa)
+    return Workload("heat_bar", h, x, X, x_mp, vol, rho0 * vol, np.zeros_like(x), mat, dt,
+                    steps)
+
+
 def jc_params(seed):
     """Johnson-Cook constants drawn from copper-like ranges (Pa, SI units)."""
     rng = np.random.default_rng(seed)
@@ -345,7 +362,7 @@ def params_from_workload(w, **over):
     mat = w.material
     p = dict(model=mat.model, E=mat.E, nu=mat.nu, rho0=mat.rho0, A=mat.A, B=mat.B,
              n=mat.n, C=mat.C, m=mat.m, eps_dot0=mat.eps_dot0, T_r=mat.T_r, T_m=mat.T_m,
-             Cp=mat.Cp, chi=mat.chi, Y0=mat.Y0, H=mat.H,
+             Cp=mat.Cp, chi=mat.chi, Y0=mat.Y0, H=mat.H, kappa=mat.kappa,
              beta=w.beta, r_list=w.r_list, cell_size=w.r_list * 1.0001,
              lme_tol=1e-14 * w.h, lme_max_iter=50, rm_tol=1e-14, rm_max_iter=60,
              wall=bool(w.wall), wall_x=np.array(w.wall_x, float),
