@@ -80,6 +80,7 @@ class State:
     # nodal sums h_I, Q_I of the last assembly and the nodal temperature and
     # rate formed from them by the node update
     q: np.ndarray = None
+    node_events: tuple = (0, 0)
     heat_h: np.ndarray = None
     heat_Q: np.ndarray = None
     T_nodes: np.ndarray = None
@@ -280,6 +281,50 @@ def init_state(x_nodes, x_mp, vol, mass, v0_nodes, p, lists=None):
 
 
 MP_FIELDS = ("xp", "vol", "mass", "lam", "F", "be", "epsbar", "T", "sigma", "failed", "q")
+NODE_FIELDS = ("x", "du", "m", "f", "gT", "heat_h", "heat_Q")
+
+
+def freed_surface_nodes(st, removed, delta):
+    """Nodes inserted where material was removed (the data management of
+    Sec. 3.3 adds nodes; the chip-formation workload adds them at the freed
+    surfaces).  Reading: a removed MP p leaves a node at x_p when every node
+    of its support is farther than ``delta`` from x_p and no removed MP of
+    smaller index lies within ``delta`` of it (one node where several removed
+    MPs crowd together).  The node takes the MP's interpolated increment
+    sum_I N_Ip du_I, so it moves on with the material it replaces.
+    Distances as in the search: ((dx*dx + dy*dy) + dz*dz), compared with
+    delta^2.  Returns (positions, increments) in ascending MP order."""
+    d2 = delta * delta
+    xs, dus = [], []
+    for k, p in enumerate(removed):
+        lo, hi = st.offsets[p], st.offsets[p + 1]
+        nodes = st.idx[lo:hi]
+        if hi > lo and search._sqdist(st.xp[p][None, :], st.x[nodes]).min() <= d2:
+            continue
+        if k > 0 and search._sqdist(st.xp[p][None, :], st.xp[removed[:k]]).min() <= d2:
+            continue
+        xs.append(st.xp[p].copy())
+        du = np.zeros(3)
+        for q in range(lo, hi):
+            du = du + st.N[q] * st.du[st.idx[q]]
+        dus.append(du)
+    return np.array(xs).reshape(-1, 3), np.array(dus).reshape(-1, 3)
+
+
+def delete_orphan_nodes(st):
+    """Nodes in no support (after the removal of MPs no remaining MP holds
+    them) leave the node set (Sec. 3.3 deletes nodes); the others keep their
+    order and the support lists are renumbered.  Returns the count."""
+    n = st.x.shape[0]
+    keep = np.bincount(st.idx, minlength=n) > 0
+    if keep.all():
+        return 0
+    new_id = np.cumsum(keep) - 1
+    st.idx = new_id[st.idx].astype(np.int32)
+    for k in NODE_FIELDS:
+        if getattr(st, k) is not None:
+            setattr(st, k, getattr(st, k)[keep])
+    return int((~keep).sum())
 
 
 def erode(st, p):
@@ -288,16 +333,38 @@ def erode(st, p):
     Reading: Johnson-Cook fracture separates material (Sec. 4.2) and the
     data management of Sec. 3.3 removes material points from the domain; a
     removed MP takes its mass and volume with it.  The survivors keep their
-    order.  The support lists, shape functions and the lumped mass and force
-    of what remains are then recomputed, as at the end of a step.  Returns
-    the number of MPs removed."""
+    order.  With ``insert_dist`` > 0 nodes are first added at the freed
+    surface (``freed_surface_nodes``, appended after the existing nodes).
+    The support lists, shape functions and the lumped mass and force of what
+    remains are then recomputed, as at the end of a step; with
+    ``delete_orphans`` the nodes left in no support are then removed
+    (``delete_orphan_nodes``).  Returns the number of MPs removed; the node
+    counts go to st.node_events = (inserted, deleted)."""
     keep = ~st.failed
+    removed = np.nonzero(~keep)[0]
+    inserted = deleted = 0
+    delta = float(p.get("insert_dist", 0.0))
+    if delta > 0 and removed.size:
+        xn, dun = freed_surface_nodes(st, removed, delta)
+        inserted = xn.shape[0]
+        if inserted:
+            st.x = np.concatenate([st.x, xn])
+            st.du = np.concatenate([st.du, dun])
+            for k in ("m", "heat_h", "heat_Q"):
+                if getattr(st, k) is not None:
+                    setattr(st, k, np.concatenate([getattr(st, k), np.zeros(inserted)]))
+            for k in ("f", "gT"):
+                if getattr(st, k) is not None:
+                    setattr(st, k, np.concatenate([getattr(st, k), np.zeros((inserted, 3))]))
     for k in MP_FIELDS + ("xp_prev", "dF"):
         if getattr(st, k) is not None:
             setattr(st, k, getattr(st, k)[keep])
     rebuild_lists(st, p)
     shape(st, p)
     assemble(st, p)
+    if p.get("delete_orphans", False):
+        deleted = delete_orphan_nodes(st)
+    st.node_events = (inserted, deleted)
     return int((~keep).sum())
 
 
