@@ -39,18 +39,21 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mp_update_taylor_rod.
 
 
 # ------------------------------------------------------- algorithmic bytes
-def mp_pass_bytes(n_mp, n_nodes, P, precision, model):
+def mp_pass_bytes(n_mp, n_nodes, P, precision, model, conduction=False):
     """Minimum HBM bytes of one MP-pass launch (each array read or written
     once).  Per pair: idx 4 + N 8 + grad N 24 (12 in mixed).  Per MP: read
     offsets 8, vol 8, F-1 72 (36), b^e-1 48 (24), epsbar 8, T 8; write x_p 24,
     vol 8, F-1, b^e-1, epsbar, T, sigma 48 (24).  Per node: x and du gathered
-    once, 48."""
+    once, 48.  With conduction: per node the temperature and its rate, 16;
+    per MP the heat flux written, 24."""
     r = 8 if precision == "fp64" else 4
     pair = 4 + 8 + 3 * r
     plastic = model != 0
     read = 8 + 8 + 9 * r + (6 * r + 8 + 8 if plastic else 0)
     write = 24 + 8 + 9 * r + 6 * r + (6 * r + 8 + 8 if plastic else 0)
-    return pair * P + (read + write) * n_mp + 48 * n_nodes
+    if conduction:
+        write += 24
+    return pair * P + (read + write) * n_mp + (64 if conduction else 48) * n_nodes
 
 
 def lme_bytes(n_mp, n_nodes, P, precision):
@@ -281,6 +284,100 @@ def _run_paper_size(w, label, paper_s, warmup, graph_steps):
     return out
 
 
+def run_cutting_5m(erode_every=50):
+    """Orthogonal cutting at production scale (cutting_slab_5m: 2 x 1 x
+    0.05 mm, ~1.1M nodes, ~6.1M MPs): mixed precision, atomic assembly,
+    lists rebuilt every step, JC flow and fracture, tool contact, heat
+    conduction, and every ``erode_every`` steps the failed MPs removed with
+    nodes added at the freed surface and orphan nodes deleted.  Steps are
+    timed with HIP events (per phase through otm_step_profiled); each
+    erosion (which synchronises) is timed on the host."""
+    import ctypes as C
+    import torch
+    import otm_workloads as W
+    from paper_2206_08772_amd import _lib
+    from paper_2206_08772_amd.sim import Sim, _ptr, _stream
+    w = W.config_by_name("cutting_slab_5m")
+    p = W.params_from_workload(w)
+    # kernels of these switches loaded on the small cut first
+    ws_ = W.config_by_name("small_cut")
+    warm = Sim(ws_.x_nodes, ws_.x_mp, ws_.vol_mp, ws_.mass_mp, ws_.v0_nodes,
+               W.params_from_workload(ws_, kappa=p["kappa"], insert_dist=0.5 * ws_.h,
+                                      delete_orphans=True), precision="mixed")
+    warm.init()
+    warm.run(3)
+    warm.erode()
+    warm.check_diag()
+    del warm
+    sim = Sim(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, precision="mixed")
+    sim.init()
+    sim.check_diag()
+    lib = _lib.lib()
+    rt = hip_runtime()
+    stream = _stream()
+    steps = w.steps
+    used = [k for k, n in enumerate(PHASES) if n != "segmented"]
+    ev = []
+    for _ in range(steps):
+        a = (C.c_void_p * len(PHASES))()
+        for k in used:
+            e = C.c_void_p()
+            assert rt.hipEventCreate(C.byref(e)) == 0
+            a[k] = e
+        ev.append(a)
+    ms = C.c_float()
+    step_ms, mp_ms, mp_bytes, mp_steps = 0.0, 0.0, 0.0, 0
+    phase_acc = {PHASES[k]: 0.0 for k in used[:-1]}
+    erode_ms, removed, inserted, deleted = [], 0, 0, 0
+    torch.cuda.synchronize()
+    for s0 in range(0, steps, erode_every):
+        n_seg = min(erode_every, steps - s0)
+        n_mp, n_nodes = sim.n_mp, sim.n_nodes
+        for k in range(s0, s0 + n_seg):
+            _lib.check(lib.otm_step_profiled(C.byref(sim.st), C.byref(sim.p), sim.dt, 1, sim.mode,
+                                             sim.ws.ptr, sim.ws.nbytes, _ptr(sim.diag), ev[k],
+                                             stream), "otm_step_profiled")
+        torch.cuda.synchronize()
+        code, d = sim.check_diag()
+        P = int(d.pairs_needed)
+        for k in range(s0, s0 + n_seg):
+            for a, b in zip(used[:-1], used[1:]):
+                assert rt.hipEventElapsedTime(C.byref(ms), ev[k][a], ev[k][b]) == 0
+                phase_acc[PHASES[a]] += ms.value
+                step_ms += ms.value
+                if PHASES[a] == "mp_update":
+                    mp_ms += ms.value
+        mp_bytes += n_seg * mp_pass_bytes(n_mp, n_nodes, P, "mixed", w.material.model, True)
+        mp_steps += n_seg * n_mp
+        t = time.perf_counter()
+        removed += sim.erode()
+        torch.cuda.synchronize()
+        erode_ms.append(1e3 * (time.perf_counter() - t))
+        inserted += sim.node_events[0]
+        deleted += sim.node_events[1]
+        sim.check_diag()
+    for a in ev:
+        for k in used:
+            rt.hipEventDestroy(a[k])
+    out = dict(
+        workload=f"{w.name}: 2 x 1 x 0.05 mm slab, {w.n_nodes} nodes, {w.n_mp} MPs, JC flow + "
+                 f"fracture, tool at 5 m/s, heat conduction (kappa {p['kappa']} W/(m K)), "
+                 f"rebuild every step, mixed precision, atomic assembly, erosion every "
+                 f"{erode_every} steps with nodes added at the freed surface and orphans "
+                 f"deleted, {steps} steps",
+        steps=steps, ms_per_step=round(step_ms / steps, 4),
+        value=round(mp_steps / (step_ms * 1e-3), 1), unit="material-point steps/s",
+        phase_ms={k: round(v / steps, 4) for k, v in phase_acc.items()},
+        mp_pass_roofline=roofline_entry(mp_bytes / steps, mp_ms / steps),
+        erosion=dict(calls=len(erode_ms), removed_mps=removed, nodes_added=inserted,
+                     nodes_deleted=deleted, ms_mean=round(sum(erode_ms) / len(erode_ms), 2)),
+        n_mp_at_end=sim.n_mp, n_nodes_at_end=sim.n_nodes,
+        max_temperature_rise=round(float((sim.T - p["T_r"]).max()), 3))
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 # ------------------------------------------------------------ adjoint ratio
 def adjoint_ratio(every=20):
     """Gradient of a rollout loss on the adjoint-rod workload (268k MPs, 200
@@ -289,7 +386,7 @@ def adjoint_ratio(every=20):
     of the plain forward rollout of the same steps."""
     import torch
     import otm_workloads as W
-    from paper_2206_08772_amd.adjoint import rollout_backward, rollout_forward
+    from paper_2206_08772_amd.adjoint import AdjointBuffers, rollout_backward, rollout_forward
     from paper_2206_08772_amd.sim import Sim
     w = W.config_by_name("adjoint_rod")
     p = W.params_from_workload(w)
@@ -307,9 +404,12 @@ def adjoint_ratio(every=20):
     sim.init()
     ckpt = rollout_forward(sim, steps, every)
     xbar = sim.x - target
+    # the sweep's buffers (tape, adjoints, workspace) are set up before the
+    # timed region, as the forward's state is
+    bufs = AdjointBuffers(sim, every, steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    theta_bar, _ = rollout_backward(sim, ckpt, steps, every, xbar)
+    theta_bar, _ = rollout_backward(sim, ckpt, steps, every, xbar, bufs=bufs)
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
     return dict(ratio=round(t_bwd / t_fwd, 3), forward_s=round(t_fwd, 4),
@@ -351,9 +451,10 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="taylor_rod")
-    ap.add_argument("--variants", default="mixed,segmented,stabilised,paper_rod,cutting",
+    ap.add_argument("--variants",
+                    default="mixed,segmented,stabilised,paper_rod,cutting,cutting_5m",
                     help="extra timed variants: mixed, segmented, stabilised, paper_rod, "
-                         "cutting (comma separated, or none)")
+                         "cutting, cutting_5m (comma separated, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -391,6 +492,9 @@ def main():
             continue
         if v == "cutting":
             variants[v] = run_cutting()
+            continue
+        if v == "cutting_5m":
+            variants[v] = run_cutting_5m()
             continue
         prec = "mixed" if v == "mixed" else "fp64"
         scat = "segmented" if v == "segmented" else "atomic"

@@ -128,6 +128,28 @@ typedef struct otm_params {
   double tool_clearance;  /* clearance angle in [0, pi/2) */
   double tool_cN, tool_cT;/* normal and tangential penalty stiffness > 0 (N/m) */
   double tool_mu;         /* Coulomb friction coefficient >= 0 */
+  /* Heat conduction (the paper's chip-formation model is adiabatic; this
+     adds Fourier conduction q = -kappa grad T through the LME gradients).
+     With kappa > 0 each MP update also adds
+       dT_p = dt sum_I N_Ip Q_I / (Cp m_I),  Q_I = sum_p v_p q_p . grad N_Ip,
+     to T_{n+1} with the plastic heating, where q_p = -kappa sum_I T_I grad N_Ip
+     is the flux of the previous MP update (st->qflux) and
+     T_I = sum_p N_Ip m_p T_p / m_I the mass-weighted nodal temperature; the
+     flow stress still softens with T_n, the fracture check sees T_{n+1}, and
+     a failed MP takes its conduction increment too.  The sums h_I and Q_I
+     are assembled with the mass and force into st->heat.  The surface is
+     insulated.  Needs model OTM_J2_JC, the atomic assembly, eps_stab = 0 and
+     st->heat, st->qflux; otm_step_adjoint rejects kappa > 0. */
+  double kappa;           /* thermal conductivity >= 0 (0: adiabatic) */
+  /* Node management at erosion (otm_erode; the data management of Sec. 3.3
+     adds and deletes nodes). */
+  double insert_dist;     /* > 0: a removed MP whose support has no node
+                             within this distance, and which has no removed
+                             MP of smaller index within it, leaves a node at
+                             its position (0: no insertion) */
+  int32_t delete_orphans; /* 1: nodes in no support after the erosion are
+                             removed from the node set (0: they stay) */
+  int32_t pad1;
 } otm_params;
 
 /* Device state of one simulation (host struct of device pointers). */
@@ -170,6 +192,15 @@ typedef struct otm_state {
                              limit (g_T = -t_T / tool_cT); 0 out of contact */
   double* clock;          /* [1] time of the state; otm_init sets 0 and each
                              step adds dt (moves the tool) */
+  /* heat conduction (may be NULL when params.kappa is 0) */
+  double* heat;           /* [2][n_nodes] h_I = sum_p N_Ip m_p T_p and
+                             Q_I = sum_p v_p q_p . grad N_Ip of the last
+                             assembly */
+  double* qflux;          /* [3][n_mp] heat flux q_p of the last MP update
+                             (otm_init sets 0; otm_erode compacts it) */
+  int64_t node_capacity;  /* entries per component the node arrays (x, du,
+                             m, f, tool_gt, heat) have room for, >= n_nodes
+                             (0: n_nodes); otm_erode adds nodes up to it */
 } otm_state;
 
 /* Device-side failure record (lives in device memory). */
@@ -302,20 +333,35 @@ otm_status otm_step_into(otm_state* st, const otm_lists* next, const otm_params*
  * of material points from the domain is the operation of the data management
  * in Sec. 3.3).  Requires params.fracture = 1 and params.eps_stab = 0.
  * Every per-MP array of *st (xp, vol, mass, lam, Fd, bed, epsbar, T, sigma,
- * failed) is compacted in place: the surviving MPs keep their order and the
- * component stride of each [k][n_mp] array becomes the new n_mp, which is
- * written to st->n_mp; the arrays keep their allocation.  failed is 0 for all
- * survivors afterwards.  Then, as otm_refresh with rebuild = 1, the support
- * lists, shape functions and the nodal mass and force of the remaining body
- * are recomputed, so that otm_step can follow; a node no longer in any
- * support gets zero mass and force.  *n_removed (host) receives the number
- * of MPs removed.  ws is the step workspace for the state's size before the
- * call.  Synchronises the stream once (to read the survivor count), so it
- * cannot be captured in a graph.  Errors: OTM_ERR_ARG for invalid arguments
- * (state unchanged), OTM_ERR_HIP; the refresh's errors appear in diag.
+ * failed, and qflux with conduction) is compacted in place: the surviving
+ * MPs keep their order and the component stride of each [k][n_mp] array
+ * becomes the new n_mp, which is written to st->n_mp; the arrays keep their
+ * allocation.  failed is 0 for all survivors afterwards.
+ * Node management (the same data management adds and deletes nodes; where
+ * is not said): with params.insert_dist > 0, before the removal, each
+ * removed MP whose support holds no node within insert_dist, and which has
+ * no removed MP of smaller index within insert_dist, adds a node at its
+ * position (a node at the freed surface) with its interpolated increment
+ * sum_I N_Ip du_I and zero contact gap; the new nodes follow the old ones
+ * in MP order, every [k][n_nodes] node array is re-strided to the new
+ * st->n_nodes (room: st->node_capacity, else OTM_ERR_CAPACITY with the
+ * state unchanged).  Then, as otm_refresh with rebuild = 1, the support
+ * lists, shape functions and the nodal mass and force (and heat sums) of the
+ * remaining body are recomputed, so that otm_step can follow.  With
+ * params.delete_orphans = 1 the nodes that no support uses afterwards are
+ * removed from every node array (stable order, stride st->n_nodes) and the
+ * lists renumbered; otherwise such a node keeps zero mass and force.
+ * *n_removed (host) receives the number of MPs removed, node_events (host,
+ * 2 entries, may be NULL) the numbers of nodes added and deleted.  ws is a
+ * workspace of otm_workspace_bytes(max(node_capacity, n_nodes), n_mp,
+ * pair_capacity) for the state's sizes before the call.  Synchronises the
+ * stream to read counts, so it cannot be captured in a graph.  Errors:
+ * OTM_ERR_ARG for invalid arguments (state unchanged), OTM_ERR_CAPACITY,
+ * OTM_ERR_HIP; the refresh's errors appear in diag.
  */
 otm_status otm_erode(otm_state* st, const otm_params* p, int32_t scatter_mode, void* ws,
-                     size_t ws_bytes, otm_diag* diag, int64_t* n_removed, hipStream_t s);
+                     size_t ws_bytes, otm_diag* diag, int64_t* n_removed, int64_t* node_events,
+                     hipStream_t s);
 
 /* One stored step of a forward trajectory (host struct of device pointers,
  * float64 state as in otm_state with precision OTM_FP64).  Pair arrays N and
@@ -366,9 +412,10 @@ size_t otm_adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp);
  * (support lists frozen to theirs).  bar_next holds the adjoint of state
  * n+1 on entry and is used as scratch (its x and du receive the
  * contributions of this step before being mapped back); bar receives the
- * adjoint of state n (every field is written).  theta_bar (device, 3
- * doubles) accumulates dL/d(A, B, n) for OTM_J2_JC or dL/d(Y0, H, -) for
- * OTM_J2_LINEAR.  The derivative of each stage is the exact derivative of the
+ * adjoint of state n (every field is written).  theta_bar (device, 5
+ * doubles) accumulates dL/d(A, B, n, C, m) of the Johnson-Cook flow stress
+ * (Sec. 4.2 hardening law) for OTM_J2_JC, or dL/d(Y0, H) in its first two
+ * entries (the other three unchanged) for OTM_J2_LINEAR.  The derivative of each stage is the exact derivative of the
  * forward arithmetic: LME through the implicit function theorem on the
  * consistency condition, the return map through the spectral derivative of
  * the Hencky stress and of the exponential map and the implicit derivative
@@ -382,6 +429,24 @@ otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_p
                             double dt, const double* mass, otm_state_bar* bar_next,
                             otm_state_bar* bar, double* theta_bar, void* ws, size_t ws_bytes,
                             otm_diag* diag, hipStream_t s);
+
+/*
+ * Adjoint of the start of the central difference.  otm_init sets
+ * du_0 = dt v0 from the nodal initial velocity v0 (the increment that starts
+ * the central-difference update of the nodes, Alg. 1), and nothing else of
+ * state 0 depends on v0.  Given du_bar [3][n_nodes], the adjoint of state 0's
+ * du (what otm_step_adjoint wrote to bar->du for the first step of a
+ * rollout), writes v0_bar [3][n_nodes] = dt du_bar: the gradient of the loss
+ * with respect to every nodal initial velocity.  If dir is not NULL
+ * ([3][n_nodes], a direction in the space of initial velocity fields, such
+ * as the fixed field that a scalar impact speed scales), *dir_bar (device,
+ * one double) receives sum_I v0_bar_I . dir_I, the loss's derivative along
+ * dir, summed in a fixed order (the same bits on every run).  dir and
+ * dir_bar are both NULL or both set; v0_bar must not alias du_bar or dir.
+ * Enqueued on s; errors: OTM_ERR_ARG (host checks), OTM_ERR_HIP.
+ */
+otm_status otm_init_adjoint(int64_t n_nodes, double dt, const double* du_bar, double* v0_bar,
+                            const double* dir, double* dir_bar, hipStream_t s);
 
 /*
  * otm_step with phase markers: events[k] (host array of 7 caller-created

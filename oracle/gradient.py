@@ -2,8 +2,9 @@
 
 The loss is L = 1/2 sum_I |x_I(N) - x_I^target|^2 over the node positions
 after N explicit steps (Alg. 1).  Its derivatives with respect to the
-Johnson-Cook constants A, B, n (Sec. 4.2 hardening law) and to the initial
-speed are taken by the complex-step method: a parameter is given an
+Johnson-Cook constants A, B, n, C, m (Sec. 4.2 hardening law), to the initial
+speed and along directions of the nodal initial velocity field are taken by
+the complex-step method: a parameter is given an
 imaginary part i*h (h ~ 1e-20 of its size), the whole rollout runs in complex
 arithmetic, and dL/dtheta = Im L / h, exact up to round-off (no subtractive
 cancellation).  The holomorphic form of the oracle is used for this: tensor
@@ -59,10 +60,18 @@ def loss(st, x_target):
 
 
 def complex_step_gradient(x_nodes, x_mp, vol, mass, v0, p, steps, lists, x_target,
-                          params=("A", "B", "n")):
-    """dL/dtheta for the named material constants and dL/d(speed), where the
-    initial nodal velocity is v0 = speed * v0_unit."""
+                          params=("A", "B", "n"), v0_dirs=()):
+    """dL/dtheta for the named material constants, dL/d(speed), where the
+    initial nodal velocity is v0 = speed * v0_unit, and for each field d in
+    ``v0_dirs`` (an (n_nodes, 3) array) the derivative of L along the initial
+    velocity field d, under grads[("v0", k)]."""
     grads = {}
+    for k, d in enumerate(v0_dirs):
+        d = np.asarray(d, float)
+        h = 1e-20 * np.abs(v0).max() / np.abs(d).max()
+        st = rollout(x_nodes, x_mp, vol, mass, np.asarray(v0, complex) + 1j * h * d, p, steps,
+                     lists, complex_step=True)
+        grads[("v0", k)] = loss(st, x_target).imag / h
     for name in params:
         h = 1e-20 * abs(p[name])
         pc = dict(p)

@@ -10,9 +10,10 @@ The paper's two benchmarks (Taylor rod impact, Sec. 4.1; serrated chip
 formation, Sec. 4.2) come with meshes and parameter tables that are not
 published with it, so every workload here is a same-shape stand-in:
 
-* nodes on the lattice (i h, j h, k h) inside the body, enumerated with z
-  slowest and x fastest, each coordinate jittered by U(-0.1 h, 0.1 h) in one
-  seeded draw of shape (n_nodes, 3);
+* nodes on the lattice (i h, j h, k h) inside the body, each coordinate
+  jittered by U(-0.1 h, 0.1 h) in one seeded draw of shape (n_nodes, 3) in
+  (k, j, i) order (z slowest), then numbered in Z-order (Morton order) of
+  their lattice index;
 * every hex cell whose 8 corners are present is split into the 6 Kuhn tets
   around its (0,0,0)-(1,1,1) diagonal; lattice points that are the corner of
   no such cell are dropped (they would be nodes without mass);
@@ -99,6 +100,10 @@ class Workload:
     # tip circle at t = 0), v (velocity), r (tip radius), clearance (rad),
     # cN, cT (penalty stiffnesses, N/m), mu (Coulomb coefficient), or None
     tool: dict = None
+    # node management at erosion: nodes added at the freed surface within
+    # this distance rule (0: none) and nodes in no support deleted
+    insert_dist: float = 0.0
+    delete_orphans: bool = False
 
     @property
     def n_nodes(self):
@@ -139,7 +144,7 @@ def _morton3(i, j, k):
 
 
 def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False, clamp_x0=False,
-                  hex_order="morton"):
+                  hex_order="morton", node_order="morton"):
     """Lattice nodes inside a body, their jitter, the hex cells and tets.
 
     ``inside(i, j, k)`` receives integer index arrays and returns a mask.
@@ -151,12 +156,21 @@ def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False, clamp_x0=False,
                              np.arange(i0, i1 + 1), indexing="ij")
     ii, jj, kk = ii.ravel(), jj.ravel(), kk.ravel()
     mask = inside(ii, jj, kk)
-    node_id = np.full(mask.shape[0], -1, dtype=np.int64)
-    node_id[mask] = np.arange(int(mask.sum()))
-    node_id = node_id.reshape(nk, nj, ni)
     X = np.stack([ii[mask], jj[mask], kk[mask]], axis=1).astype(np.float64) * h
     rng = np.random.default_rng(seed)
-    jit = rng.uniform(-0.1 * h, 0.1 * h, size=X.shape)
+    jit = rng.uniform(-0.1 * h, 0.1 * h, size=X.shape)   # drawn in (k, j, i) order
+    if node_order == "morton":
+        # nodes numbered in Z-order of their lattice index, like the hexes:
+        # the nodes a run of consecutive MPs touches sit close together
+        order = np.argsort(_morton3(ii[mask] - i0, jj[mask] - j0, kk[mask] - k0), kind="stable")
+    else:
+        order = np.arange(X.shape[0])
+    X, jit = X[order], jit[order]
+    rank = np.empty(order.size, dtype=np.int64)
+    rank[order] = np.arange(order.size)
+    node_id = np.full(mask.shape[0], -1, dtype=np.int64)
+    node_id[mask] = rank
+    node_id = node_id.reshape(nk, nj, ni)
     x = X + jit
     if clamp_z0:
         x[:, 2] = np.maximum(x[:, 2], 0.0)
@@ -301,6 +315,26 @@ def cutting_slab(h=2e-6, seed=7, length=300e-6, height=120e-6, layers=3, depth=1
                     fracture=tuple(frac) if fracture is None else tuple(fracture), tool=tool)
 
 
+def cutting_slab_5m(h=4.64e-6, seed=11, steps=500):
+    """Orthogonal cutting at the scale of a production run: a 2 x 1 x 0.05 mm
+    workpiece (431 x 216 x 12 node lattice, about 1.1M nodes and 5.5M MPs),
+    the rigid tool (rake angle 0, tip radius 2 um, clearance 7 deg) at 5 m/s
+    with 0.1 mm depth of cut, starting in contact with the workpiece's face,
+    dt = 1e-10 s, 500 steps, Ti-alloy-like flow constants from ``seed``, heat
+    conduction with the Ti-alloy conductivity 6.7 W/(m K), and low fracture
+    constants d = (0, 0.005, -0.5, 0.014, 3.7) so that MPs ahead of the tool
+    fail and are removed within the run (the real constants would need far
+    more steps); nodes are added at the freed surface (insert_dist = h / 2)
+    and nodes left in no support deleted."""
+    w = cutting_slab(h=h, seed=seed, length=2e-3, height=1e-3, layers=12, depth=0.1e-3,
+                     speed=5.0, steps=steps, dt=1e-10, name="cutting_slab_5m",
+                     fracture=(0.0, 0.005, -0.5, 0.014, 3.7))
+    w.material.kappa = 6.7
+    w.insert_dist = 0.5 * h
+    w.delete_orphans = True
+    return w
+
+
 def config_by_name(name):
     """The named workloads.
 
@@ -329,6 +363,8 @@ def config_by_name(name):
         return elastic_cube()
     if name == "taylor_rod":
         return taylor_rod(h=0.15033e-3, seed=1, steps=100)
+    if name == "cutting_slab_5m":
+        return cutting_slab_5m()
     if name == "taylor_rod_xl":
         return taylor_rod(h=0.06978e-3, seed=2, steps=200, skin_h=0.1, rebuild_every=10,
                           name="taylor_rod_xl")
@@ -369,7 +405,8 @@ def params_from_workload(w, **over):
              wall_n=np.array(w.wall_n, float), dt=w.dt, rebuild_every=w.rebuild_every,
              fracture=w.fracture is not None,
              jc_d=np.array(w.fracture if w.fracture is not None else (0.0,) * 5, float),
-             tool=w.tool is not None)
+             tool=w.tool is not None, insert_dist=w.insert_dist,
+             delete_orphans=w.delete_orphans)
     if w.tool is not None:
         t = w.tool
         p.update(tool_c=np.array(t["c0"], float), tool_v=np.array(t["v"], float),

@@ -41,7 +41,8 @@ class Params(C.Structure):
         ("fracture", C.c_int32), ("tool_enabled", C.c_int32), ("jc_d", C.c_double * 5),
         ("tool_c", C.c_double * 3), ("tool_v", C.c_double * 3), ("tool_r", C.c_double),
         ("tool_clearance", C.c_double), ("tool_cN", C.c_double), ("tool_cT", C.c_double),
-        ("tool_mu", C.c_double),
+        ("tool_mu", C.c_double), ("kappa", C.c_double), ("insert_dist", C.c_double),
+        ("delete_orphans", C.c_int32), ("pad1", C.c_int32),
     ]
 
 
@@ -56,6 +57,7 @@ class State(C.Structure):
         ("nbr_offsets", C.c_void_p), ("nbr_idx", C.c_void_p), ("N", C.c_void_p),
         ("dN", C.c_void_p), ("xp_prev", C.c_void_p), ("dFm1", C.c_void_p),
         ("failed", C.c_void_p), ("tool_gt", C.c_void_p), ("clock", C.c_void_p),
+        ("heat", C.c_void_p), ("qflux", C.c_void_p), ("node_capacity", C.c_int64),
     ]
 
 
@@ -113,7 +115,8 @@ _SIGS = {
                                   C.c_double, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
                                   C.c_void_p, C.c_void_p]),
     "otm_erode": (C.c_int32, [C.POINTER(State), C.POINTER(Params), C.c_int32, C.c_void_p,
-                              C.c_size_t, C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
+                              C.c_size_t, C.c_void_p, C.POINTER(C.c_int64),
+                              C.POINTER(C.c_int64), C.c_void_p]),
     "otm_step_profiled": (C.c_int32, [C.POINTER(State), C.POINTER(Params), C.c_double,
                                       C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                       C.c_void_p, C.c_void_p]),
@@ -121,6 +124,8 @@ _SIGS = {
 
 _OPTIONAL = {
     "otm_adjoint_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int64]),
+    "otm_init_adjoint": (C.c_int32, [C.c_int64, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
     "otm_step_adjoint": (C.c_int32, [C.POINTER(Tape), C.POINTER(Tape), C.POINTER(Params),
                                      C.c_double, C.c_void_p, C.POINTER(StateBar),
                                      C.POINTER(StateBar), C.c_void_p, C.c_void_p, C.c_size_t,

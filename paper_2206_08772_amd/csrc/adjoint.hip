@@ -121,12 +121,15 @@ OTM_HD double ratio_expm1(double a, double u) {
   return fabs(u) < 1e-8 ? a * (1.0 + 0.5 * (a - 1.0) * u) : expm1(a * u) / expm1(u);
 }
 
-// Partial derivatives of the flow stress at (eb + x, x/dt, T*).
+// Partial derivatives of the flow stress at (eb + x, x/dt, T*): by epsbar,
+// by T* and by the kTheta hardening constants (A, B, n, C, m of Johnson-Cook;
+// Y0, H of linear hardening, the other three 0).
+constexpr int kTheta = 5;
 struct FlowPartials {
-  double s_eb, s_T, s_th[3];
+  double s_eb, s_T, s_th[kTheta];
 };
 OTM_DEV FlowPartials flow_partials(const Mat<double>& M, double eb, double x, double Ts) {
-  FlowPartials P{0.0, 0.0, {0.0, 0.0, 0.0}};
+  FlowPartials P{0.0, 0.0, {0.0, 0.0, 0.0, 0.0, 0.0}};
   if (M.model == OTM_J2_LINEAR) {
     P.s_eb = M.H;
     P.s_th[0] = 1.0;       // d/dY0
@@ -142,18 +145,22 @@ OTM_DEV FlowPartials flow_partials(const Mat<double>& M, double eb, double x, do
     dhard = M.B * M.n * en / e;
   }
   const double ratio = x / M.rate0dt;
-  const double rate = ratio > 1.0 ? 1.0 + M.C * log(ratio) : 1.0;
-  double therm = 1.0, dtherm = 0.0;
+  const double lrate = ratio > 1.0 ? log(ratio) : 0.0;
+  const double rate = 1.0 + M.C * lrate;
+  double therm = 1.0, dtherm = 0.0, dtherm_m = 0.0;
   if (Ts > 0.0) {
     const double tm = m_pow(Ts, M.m);
     therm = 1.0 - tm;
     dtherm = -M.m * tm / Ts;
+    dtherm_m = -tm * log(Ts);
   }
   P.s_eb = dhard * rate * therm;
   P.s_T = hard * rate * dtherm;
   P.s_th[0] = rate * therm;                 // d/dA
   P.s_th[1] = en * rate * therm;            // d/dB
   P.s_th[2] = M.B * en * lne * rate * therm;  // d/dn
+  P.s_th[3] = hard * lrate * therm;         // d/dC
+  P.s_th[4] = hard * rate * dtherm_m;       // d/dm
   return P;
 }
 
@@ -373,7 +380,7 @@ struct AdjMpArgs {
   double* epsb;
   double* Tb;
   double* dfb;     // adjoint of dF per MP [9][n_mp] (written, workspace)
-  double* theta_part;  // [gridDim][3]
+  double* theta_part;  // [gridDim][kTheta]
   Mat<double> M;
   double dt;
   otm_diag* diag;
@@ -392,7 +399,7 @@ struct AdjMpArgs {
 // restore at the end of a divergent branch, leaving stale values in the lanes
 // that skipped the branch.
 OTM_DEV void mp_adjoint(const AdjMpArgs& a, int64_t p, const double dF[3][3], double dFb[3][3],
-                        double thb[3], bool& ok) {
+                        double thb[kTheta], bool& ok) {
   const Mat<double>& M = a.M;
   const int64_t n = a.n_mp;
   // ---- stage 1: forward recomputation (the same arithmetic as the MP pass)
@@ -517,7 +524,7 @@ OTM_DEV void mp_adjoint(const AdjMpArgs& a, int64_t p, const double dF[3][3], do
       depsb += M.chi * (1.0 - c) * q / M.rhoCp * Tb1;
       qb += M.chi * (1.0 - c) * deps / M.rhoCp * Tb1;
     }
-    thb[0] = thb[1] = thb[2] = 0.0;
+    for (int k = 0; k < kTheta; ++k) thb[k] = 0.0;
     if (plastic) {
       // c = 3 mu deps / q
       depsb += cb * 3.0 * M.mu / q;
@@ -527,7 +534,7 @@ OTM_DEV void mp_adjoint(const AdjMpArgs& a, int64_t p, const double dF[3][3], do
       ebnb += depsb * P.s_eb / gx;
       if (M.model == OTM_J2_JC && tunc > 0.0 && tunc < 1.0)
         Tnb += depsb * P.s_T / gx / (M.Tm - M.Tr);
-      for (int k = 0; k < 3; ++k) thb[k] = depsb * P.s_th[k] / gx;
+      for (int k = 0; k < kTheta; ++k) thb[k] = depsb * P.s_th[k] / gx;
     }
     a.epsb[p] = ebnb;
     a.Tb[p] = Tnb;
@@ -602,7 +609,7 @@ OTM_DEV void mp_adjoint(const AdjMpArgs& a, int64_t p, const double dF[3][3], do
 
 __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
   __shared__ double sums[9][kAdjMpBlock];   // dF - 1 of the workgroup's MPs
-  __shared__ double thred[3][kAdjMpBlock];
+  __shared__ double thred[kTheta][kAdjMpBlock];
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)xcd_block() * kAdjMpBlock;
   const int lane = tid % kAdjGather;
@@ -651,7 +658,7 @@ __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
   }
   __syncthreads();
   // phase 2: one lane per MP
-  double th[3] = {0, 0, 0};
+  double th[kTheta] = {0, 0, 0, 0, 0};
   {
     const int64_t p = base + tid;
     if (p < a.n_mp) {
@@ -674,16 +681,16 @@ __global__ __launch_bounds__(kAdjMpBlock) void k_adj_mp(AdjMpArgs a) {
         for (int j = 0; j < 3; ++j) a.dfb[(3 * i + j) * a.n_mp + p] = dFb[i][j];
     }
   }
-  for (int k = 0; k < 3; ++k) thred[k][tid] = th[k];
+  for (int k = 0; k < kTheta; ++k) thred[k][tid] = th[k];
   __syncthreads();
   // parameter gradient: one partial per workgroup
   for (int o = kAdjMpBlock / 2; o > 0; o >>= 1) {
     if (tid < o)
-      for (int k = 0; k < 3; ++k) thred[k][tid] += thred[k][tid + o];
+      for (int k = 0; k < kTheta; ++k) thred[k][tid] += thred[k][tid + o];
     __syncthreads();
   }
   if (tid == 0)
-    for (int k = 0; k < 3; ++k) a.theta_part[blockIdx.x * 3 + k] = thred[k][0];
+    for (int k = 0; k < kTheta; ++k) a.theta_part[blockIdx.x * kTheta + k] = thred[k][0];
 }
 
 // ------------------------------------------- K3b: MP update, node adjoints
@@ -917,19 +924,52 @@ __global__ __launch_bounds__(256) void k_adj_assembly(AdjAsmArgs a) {
 
 __global__ __launch_bounds__(256) void k_adj_theta(const double* part, int64_t nb,
                                                    double* theta_bar) {
-  __shared__ double red[3][256];
-  double s[3] = {0, 0, 0};
+  __shared__ double red[kTheta][256];
+  double s[kTheta] = {0, 0, 0, 0, 0};
   for (int64_t b = threadIdx.x; b < nb; b += 256)
-    for (int k = 0; k < 3; ++k) s[k] += part[b * 3 + k];
-  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
+    for (int k = 0; k < kTheta; ++k) s[k] += part[b * kTheta + k];
+  for (int k = 0; k < kTheta; ++k) red[k][threadIdx.x] = s[k];
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o)
-      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+      for (int k = 0; k < kTheta; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int k = 0; k < 3; ++k) theta_bar[k] += red[k][0];
+    for (int k = 0; k < kTheta; ++k) theta_bar[k] += red[k][0];
+}
+
+// ------------------------------------------ start of the central difference
+// du_0 = dt v0: v0_bar = dt du_bar per node and component.
+__global__ __launch_bounds__(256) void k_v0_bar(int64_t n3, double dt,
+                                                const double* __restrict__ dub,
+                                                double* __restrict__ v0b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) v0b[i] = dt * dub[i];
+}
+
+// sum_i v0b_i dir_i by one workgroup: each thread sums a fixed strided set,
+// then a fixed tree, so the result does not depend on scheduling.
+__global__ __launch_bounds__(1024) void k_dir_dot(int64_t n3, const double* __restrict__ v0b,
+                                                  const double* __restrict__ dir,
+                                                  double* __restrict__ out) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n3; i += 1024) acc += v0b[i] * dir[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+void launch_init_adjoint(int64_t n_nodes, double dt, const double* du_bar, double* v0_bar,
+                         const double* dir, double* dir_bar, hipStream_t s) {
+  const int64_t n3 = 3 * n_nodes;
+  if (n3 > 0) k_v0_bar<<<(unsigned)((n3 + 255) / 256), 256, 0, s>>>(n3, dt, du_bar, v0_bar);
+  if (dir_bar != nullptr) k_dir_dot<<<1, 1024, 0, s>>>(n3, v0_bar, dir, dir_bar);
 }
 
 // ------------------------------------------------------------ host side
@@ -937,7 +977,7 @@ size_t adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp) {
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
   const int64_t nb = (n_mp + kAdjMpBlock - 1) / kAdjMpBlock + 1;
   return al(sizeof(double) * 3 * (size_t)n_mp) + al(sizeof(double4) * (size_t)n_nodes) +
-         al(sizeof(double) * 3 * (size_t)nb) + al(sizeof(double) * 9 * (size_t)n_mp) +
+         al(sizeof(double) * kTheta * (size_t)nb) + al(sizeof(double) * 9 * (size_t)n_mp) +
          al(sizeof(double4) * 2 * (size_t)n_nodes);
 }
 
@@ -952,7 +992,7 @@ void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_param
   double4* fmb = (double4*)c;
   c += al(sizeof(double4) * (size_t)nn);
   double* theta_part = (double*)c;
-  c += al(sizeof(double) * 3 * (size_t)((nm + kAdjMpBlock - 1) / kAdjMpBlock + 1));
+  c += al(sizeof(double) * kTheta * (size_t)((nm + kAdjMpBlock - 1) / kAdjMpBlock + 1));
   double* dfb = (double*)c;
   c += al(sizeof(double) * 9 * (size_t)nm);
   double4* nrec = (double4*)c;

@@ -109,6 +109,10 @@ static otm_status check_params(const otm_params* p) {
     for (int k = 0; k < 5; ++k)
       if (!isfinite(p->jc_d[k])) return OTM_ERR_ARG;
   }
+  if (!(p->kappa >= 0.0) || !isfinite(p->kappa)) return OTM_ERR_ARG;
+  if (!(p->insert_dist >= 0.0) || !isfinite(p->insert_dist)) return OTM_ERR_ARG;
+  if (p->delete_orphans != 0 && p->delete_orphans != 1) return OTM_ERR_ARG;
+  if (p->kappa > 0.0 && (p->model != OTM_J2_JC || p->eps_stab > 0.0)) return OTM_ERR_ARG;
   if (p->tool_enabled != 0 && p->tool_enabled != 1) return OTM_ERR_ARG;
   if (p->tool_enabled) {
     for (int k = 0; k < 3; ++k)
@@ -123,11 +127,18 @@ static otm_status check_params(const otm_params* p) {
   return OTM_OK;
 }
 
-// The chip-formation arrays a state needs for these parameters.
-static otm_status check_cut_state(const otm_state* st, const otm_params* p) {
+// The chip-formation and conduction arrays a state needs for these
+// parameters (conduction also needs the atomic assembly).
+static otm_status check_cut_state(const otm_state* st, const otm_params* p,
+                                  int32_t scatter_mode) {
   if (p->fracture && st->n_mp > 0 && !dev_ok(st->failed, 4)) return OTM_ERR_ARG;
   if (p->tool_enabled && (!dev_ok(st->clock, 8) || (st->n_nodes > 0 && !dev_ok(st->tool_gt, 8))))
     return OTM_ERR_ARG;
+  if (p->kappa > 0.0) {
+    if (scatter_mode != OTM_SCATTER_ATOMIC) return OTM_ERR_ARG;
+    if (st->n_nodes > 0 && !dev_ok(st->heat, 8)) return OTM_ERR_ARG;
+    if (st->n_mp > 0 && !dev_ok(st->qflux, 8)) return OTM_ERR_ARG;
+  }
   return OTM_OK;
 }
 
@@ -157,10 +168,13 @@ static void mark(hipEvent_t* ev, int k, hipStream_t s) {
 
 // search (optional) + shape functions + mass/force assembly
 // (packed: the node records in the workspace are current; stab: add the
-// stabilisation term, which needs the history the MP update just wrote)
+// stabilisation term, which needs the history the MP update just wrote;
+// tr: build the segmented mode's influence lists from the current support
+// lists even without a search, when the workspace does not hold them)
 static void refresh_impl(otm_state& st, const otm_params& p, bool rebuild, int32_t mode,
                          const Workspace& w, otm_diag* diag, hipStream_t s,
-                         hipEvent_t* ev = nullptr, bool packed = false, bool stab = false) {
+                         hipEvent_t* ev = nullptr, bool packed = false, bool stab = false,
+                         bool tr = false) {
   const Stab sb = stab ? Stab{p.eps_stab, w.nodes, st.xp, st.xp_prev, st.dFm1}
                        : Stab{0.0, nullptr, nullptr, nullptr, nullptr};
   if (!packed) launch_pack_nodes(st, w.nodes, s);
@@ -179,11 +193,14 @@ static void refresh_impl(otm_state& st, const otm_params& p, bool rebuild, int32
   // 4 | assembly (atomic), or 4 | lists | 5 | contributions + sums (segmented) | 6.
   const bool fuse_atomic = mode == OTM_SCATTER_ATOMIC && !stab;
   const bool fuse_seg = mode == OTM_SCATTER_SEGMENTED && !stab;
+  // with conduction (atomic mode only) the fused assembly also sums h_I, Q_I
+  const bool heat = p.kappa > 0.0;
   if (fuse_seg) {
-    if (rebuild) launch_influence_lists(st, w, s);
+    if (rebuild || tr) launch_influence_lists(st, w, s);
     mark(ev, 4, s);
   }
-  const AsmIn fused{st.vol, st.mass, st.sigma, st.m, st.f, st.n_nodes};
+  const AsmIn fused{st.vol, st.mass, st.sigma, st.m, st.f, st.n_nodes,
+                    heat ? st.T : nullptr, heat ? st.qflux : nullptr, heat ? st.heat : nullptr};
   const SegIn seg{st.vol, st.mass, st.sigma, w.tr_pos, w.contrib};
   launch_lme(st.n_nodes, st.x, st.n_mp, st.xp, st.nbr_offsets, st.nbr_idx, st.pair_capacity,
              p.beta, p.lme_tol, p.lme_max_iter, st.lam, st.N, st.dN, st.precision, w.nodes, diag,
@@ -196,7 +213,7 @@ static void refresh_impl(otm_state& st, const otm_params& p, bool rebuild, int32
     if (mode == OTM_SCATTER_ATOMIC) {
       if (!fuse_atomic) launch_assemble_atomic(st, sb, s);
     } else {
-      if (rebuild) launch_influence_lists(st, w, s);
+      if (rebuild || tr) launch_influence_lists(st, w, s);
       mark(ev, 5, s);
       launch_scatter_segmented(st, w, sb, s);
     }
@@ -306,11 +323,15 @@ otm_status otm_refresh(otm_state* st, const otm_params* p, int32_t rebuild, int3
   Workspace w;
   if (check_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &w) != OTM_OK)
     return OTM_ERR_ARG;
+  if ((e = check_cut_state(st, p, scatter_mode)) != OTM_OK) return e;
   if (scatter_mode == OTM_SCATTER_ATOMIC) {
     launch_zero(st->m, st->n_nodes, s);
     launch_zero(st->f, 3 * st->n_nodes, s);
+    if (p->kappa > 0.0) launch_zero(st->heat, 2 * st->n_nodes, s);
   }
-  refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s);
+  // the influence lists are rebuilt from the lists as they are: a caller
+  // may have replaced them (a resumed run) since the workspace last saw them
+  refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s, nullptr, false, false, true);
   return hip_status();
 }
 
@@ -320,14 +341,15 @@ otm_status otm_init(otm_state* st, const otm_params* p, double dt, const double*
   otm_status e;
   if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
   if (!(dt > 0) || (st->n_nodes > 0 && !dev_ok(v0, 8))) return OTM_ERR_ARG;
-  if ((e = check_cut_state(st, p)) != OTM_OK) return e;
+  if ((e = check_cut_state(st, p, scatter_mode)) != OTM_OK) return e;
   launch_init_fields(*st, *p, dt, v0, s);
   return otm_refresh(st, p, 1, scatter_mode, ws, ws_bytes, diag, s);
 }
 
 static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
                             int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
-                            hipEvent_t* ev, hipStream_t s, const otm_lists* next = nullptr) {
+                            hipEvent_t* ev, hipStream_t s, const otm_lists* next = nullptr,
+                            bool tr = false) {
   otm_status e;
   if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
   if (next != nullptr) {
@@ -345,7 +367,7 @@ static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32
   if (!dev_ok(diag, 8)) return OTM_ERR_ARG;
   const bool stab = p->eps_stab > 0.0;
   if (stab && (!dev_ok(st->xp_prev, 8) || !dev_ok(st->dFm1, 8))) return OTM_ERR_ARG;
-  if ((e = check_cut_state(st, p)) != OTM_OK) return e;
+  if ((e = check_cut_state(st, p, scatter_mode)) != OTM_OK) return e;
   Workspace w;
   if (check_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &w) != OTM_OK)
     return OTM_ERR_ARG;
@@ -355,7 +377,7 @@ static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32
   launch_mp_update(*st, *p, dt, w.nodes, diag, s);
   mark(ev, 2, s);
   if (next == nullptr) {
-    refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true, stab);
+    refresh_impl(*st, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true, stab, tr);
     return hip_status();
   }
   otm_state to = *st;
@@ -372,7 +394,7 @@ static otm_status step_impl(otm_state* st, const otm_params* p, double dt, int32
                        hipMemcpyDeviceToDevice, s) != hipSuccess)
       return OTM_ERR_HIP;
   }
-  refresh_impl(to, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true, stab);
+  refresh_impl(to, *p, rebuild != 0, scatter_mode, w, diag, s, ev, true, stab, tr);
   if ((e = hip_status()) != OTM_OK) return e;
   *st = to;
   return OTM_OK;
@@ -398,25 +420,46 @@ otm_status otm_step_profiled(otm_state* st, const otm_params* p, double dt, int3
   return step_impl(st, p, dt, rebuild, scatter_mode, ws, ws_bytes, diag, events, s);
 }
 
+
 otm_status otm_erode(otm_state* st, const otm_params* p, int32_t scatter_mode, void* ws,
-                     size_t ws_bytes, otm_diag* diag, int64_t* n_removed, hipStream_t s) {
+                     size_t ws_bytes, otm_diag* diag, int64_t* n_removed, int64_t* node_events,
+                     hipStream_t s) {
   otm_status e;
   if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
   if (n_removed == nullptr || !p->fracture || p->eps_stab > 0.0) return OTM_ERR_ARG;
   if (scatter_mode != OTM_SCATTER_ATOMIC && scatter_mode != OTM_SCATTER_SEGMENTED)
     return OTM_ERR_ARG;
   if (!dev_ok(diag, 8)) return OTM_ERR_ARG;
-  if ((e = check_cut_state(st, p)) != OTM_OK) return e;
+  if ((e = check_cut_state(st, p, scatter_mode)) != OTM_OK) return e;
+  if (st->node_capacity < 0 || st->node_capacity >= (int64_t(1) << 31)) return OTM_ERR_ARG;
+  // nodes may be added up to the capacity: the workspace is laid out for it
+  const int64_t ncap = st->node_capacity > st->n_nodes ? st->node_capacity : st->n_nodes;
   Workspace w;
-  if (check_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &w) != OTM_OK)
+  if (check_workspace(ws, ws_bytes, ncap, st->n_mp, st->pair_capacity, &w) != OTM_OK)
     return OTM_ERR_ARG;
   const int64_t n0 = st->n_mp;
+  int64_t inserted = 0, deleted = 0;
   otm_state to = *st;
-  if ((e = launch_erode(to, w, s)) != OTM_OK) return e;
+  if ((e = launch_erode(to, *p, w, s, &inserted)) != OTM_OK) return e;
   st->n_mp = to.n_mp;
+  st->n_nodes = to.n_nodes;
   *n_removed = n0 - to.n_mp;
   // lists, shape functions, mass and force of the remaining body
-  return otm_refresh(st, p, 1, scatter_mode, ws, ws_bytes, diag, s);
+  if ((e = otm_refresh(st, p, 1, scatter_mode, ws, ws_bytes, diag, s)) != OTM_OK) return e;
+  if (p->delete_orphans) {
+    if ((e = launch_delete_orphans(*st, *p, w, s, &deleted)) != OTM_OK) return e;
+    if (deleted > 0 && scatter_mode == OTM_SCATTER_SEGMENTED) {
+      // the next step's influence lists, in the layout of its workspace
+      Workspace wn;
+      carve_workspace(ws, ws_bytes, st->n_nodes, st->n_mp, st->pair_capacity, &wn);
+      launch_influence_lists(*st, wn, s);
+    }
+  }
+  if (node_events != nullptr) {
+    node_events[0] = inserted;
+    node_events[1] = deleted;
+  }
+  return hip_status();
 }
 
 size_t otm_adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp) {
@@ -441,6 +484,18 @@ static bool bar_ok(const otm_state_bar* b) {
   return true;
 }
 
+otm_status otm_init_adjoint(int64_t n_nodes, double dt, const double* du_bar, double* v0_bar,
+                            const double* dir, double* dir_bar, hipStream_t s) {
+  if (n_nodes < 0 || !(dt > 0) || !isfinite(dt)) return OTM_ERR_ARG;
+  if (n_nodes > 0 && (!dev_ok(du_bar, 8) || !dev_ok(v0_bar, 8))) return OTM_ERR_ARG;
+  if ((dir == nullptr) != (dir_bar == nullptr)) return OTM_ERR_ARG;
+  if (dir_bar != nullptr && (!dev_ok(dir_bar, 8) || (n_nodes > 0 && !dev_ok(dir, 8))))
+    return OTM_ERR_ARG;
+  if (n_nodes > 0 && (du_bar == v0_bar || (dir != nullptr && dir == v0_bar))) return OTM_ERR_ARG;
+  launch_init_adjoint(n_nodes, dt, du_bar, v0_bar, dir, dir_bar, s);
+  return hip_status();
+}
+
 otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_params* p,
                             double dt, const double* mass, otm_state_bar* bar_next,
                             otm_state_bar* bar, double* theta_bar, void* ws, size_t ws_bytes,
@@ -450,6 +505,7 @@ otm_status otm_step_adjoint(const otm_tape* tn, const otm_tape* tn1, const otm_p
   if (p->model == OTM_NEOHOOKE) return OTM_ERR_ARG;  // adjoint covers the J2 models
   if (p->eps_stab != 0.0) return OTM_ERR_ARG;        // no adjoint of the stabilisation
   if (p->fracture || p->tool_enabled) return OTM_ERR_ARG;  // nor of fracture and the tool
+  if (p->kappa > 0.0) return OTM_ERR_ARG;                  // nor of heat conduction
   if (!tape_ok(tn) || !tape_ok(tn1) || !bar_ok(bar_next) || !bar_ok(bar)) return OTM_ERR_ARG;
   if (tn->n_nodes != tn1->n_nodes || tn->n_mp != tn1->n_mp) return OTM_ERR_ARG;
   if (!(dt > 0) || !dev_ok(mass, 8) || !dev_ok(theta_bar, 8) || !dev_ok(diag, 8))

@@ -63,7 +63,8 @@ void launch_search(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const d
 
 // Inputs of the atomic assembly when it is fused into the shape-function
 // kernel (m and f must be zero beforehand; sigma is double or float per the
-// precision).
+// precision).  With conduction (heat != nullptr, zero beforehand) it also
+// sums h_I = sum N m_p T_p and Q_I = sum v_p q_p . grad N into heat [2][n].
 struct AsmIn {
   const double* vol;
   const double* mass;
@@ -71,6 +72,9 @@ struct AsmIn {
   double* m;
   double* f;
   int64_t n_nodes;
+  const double* T = nullptr;
+  const double* q = nullptr;
+  double* heat = nullptr;
 };
 
 // Inputs of the deterministic assembly's contribution store when it is fused
@@ -94,7 +98,9 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
                 const AsmIn* fused = nullptr, const SegIn* seg = nullptr);
 
 // Nodes and material points.
-// Node records: packed[2 I] = (x, y, z, du_x), packed[2 I + 1] = (du_y, du_z, 0, 0).
+// Node records: packed[2 I] = (x, y, z, du_x), packed[2 I + 1] = (du_y, du_z,
+// T_I, T_I rate) with conduction (the nodal temperature and its rate from
+// st.heat), else (du_y, du_z, 0, 0).
 // The MP update also writes the stabilisation history (st.xp_prev, st.dFm1)
 // when p.eps_stab > 0.
 void launch_node_update(const otm_state& st, const otm_params& p, double dt, bool zero_mf,
@@ -135,5 +141,8 @@ size_t adjoint_workspace_bytes(int64_t n_nodes, int64_t n_mp);
 void launch_step_adjoint(const otm_tape& t0, const otm_tape& t1, const otm_params& p,
                          double dt, const double* mass, otm_state_bar& b1, otm_state_bar& b0,
                          double* theta_bar, void* ws, otm_diag* diag, hipStream_t s);
+// Adjoint of du_0 = dt v0 (and its dot product with a direction).
+void launch_init_adjoint(int64_t n_nodes, double dt, const double* du_bar, double* v0_bar,
+                         const double* dir, double* dir_bar, hipStream_t s);
 
 }  // namespace otm

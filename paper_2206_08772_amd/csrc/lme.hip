@@ -155,31 +155,47 @@ struct NoSink {
 // Fused nodal assembly (nodal mass and residual equations, Sec. 2.1): the
 // pair's m and f contributions, with the same arithmetic as the standalone
 // assembly kernel (grad N rounded to its stored type R first), go into the
-// workgroup's node table.  begin() loads the MP's mass, volume and stress
+// workgroup's node table.  With conduction (HEAT) the table also sums
+// N m_p T_p and v_p q_p . grad N (float64, grad N rounded the same way).
+// begin() loads the MP's mass, volume, stress (and temperature and flux)
 // once the Newton solve is done.
-template <typename R>
+template <typename R, bool HEAT>
 struct AsmSink {
-  NodeTable* t;
+  static constexpr int V = HEAT ? 6 : 4;
+  NodeTableV<V>* t;
   const int32_t* idx;
   const double* vol;
   const double* mass;
   const R* sigma;
-  double* m;
-  double* f;
-  int64_t n_nodes, n_mp;
-  double mp;
+  const double* Tmp;
+  const double* q;
+  NodeDst<V> dst;
+  int64_t n_mp;
+  double mp, vd, Tp, q0, q1, q2;
   R v, s0, s1, s2, s3, s4, s5;
   OTM_DEV void begin(int64_t p) {
     mp = mass[p];
-    v = (R)vol[p];
+    vd = vol[p];
+    v = (R)vd;
     s0 = sigma[p]; s1 = sigma[n_mp + p]; s2 = sigma[2 * n_mp + p];
     s3 = sigma[3 * n_mp + p]; s4 = sigma[4 * n_mp + p]; s5 = sigma[5 * n_mp + p];
+    if constexpr (HEAT) {
+      Tp = Tmp[p];
+      q0 = q[p]; q1 = q[n_mp + p]; q2 = q[2 * n_mp + p];
+    }
   }
-  OTM_DEV void operator()(int64_t q, double Nq, const double g[3]) {
+  OTM_DEV void operator()(int64_t q_, double Nq, const double g[3]) {
     const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
-    table_insert(*t, idx[q], Nq * mp, (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2)),
-                 (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2)),
-                 (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2)), m, f, n_nodes);
+    double c[V];
+    c[0] = Nq * mp;
+    c[1] = (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2));
+    c[2] = (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2));
+    c[3] = (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2));
+    if constexpr (HEAT) {
+      c[4] = c[0] * Tp;
+      c[5] = vd * ((q0 * (double)g0 + q1 * (double)g1) + q2 * (double)g2);
+    }
+    table_insert<V>(*t, idx[q_], c, dst);
   }
 };
 
@@ -336,7 +352,7 @@ __global__ __launch_bounds__(256) void k_lme(NodeSrc ns, int64_t n_mp, const dou
 // workgroup, so the barriers around a flush are reached by all of them.
 constexpr int kLmeAsmBlocks = 512;
 
-template <int G, int PPL, typename DN>
+template <int G, int PPL, typename DN, bool HEAT>
 __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
                                                  const double* __restrict__ xp,
                                                  const int64_t* __restrict__ offsets,
@@ -347,7 +363,8 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
                                                  otm_diag* diag, AsmIn a) {
   constexpr int per_round = 256 / G;
   constexpr int flush_rounds = 512 / per_round;
-  __shared__ NodeTable table;
+  using Sink = AsmSink<DN, HEAT>;
+  __shared__ NodeTableV<Sink::V> table;
   const int tid = threadIdx.x;
   table_clear(table, tid, 256);
   __syncthreads();
@@ -356,7 +373,16 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
   const int64_t hi = lo + chunk < n_mp ? lo + chunk : n_mp;
   const bool ok = offsets[n_mp] <= cap;  // lists were written (capacity)
   const int lane = tid % G;
-  AsmSink<DN> sink{&table, idx, a.vol, a.mass, (const DN*)a.sigma, a.m, a.f, a.n_nodes, n_mp};
+  NodeDst<Sink::V> dst;
+  dst.d[0] = a.m;
+  dst.d[1] = a.f;
+  dst.d[2] = a.f + a.n_nodes;
+  dst.d[3] = a.f + 2 * a.n_nodes;
+  if constexpr (HEAT) {
+    dst.d[4] = a.heat;
+    dst.d[5] = a.heat + a.n_nodes;
+  }
+  Sink sink{&table, idx, a.vol, a.mass, (const DN*)a.sigma, a.T, a.q, dst, n_mp};
   int r = 0;
   for (int64_t p0 = lo; p0 < hi; p0 += per_round) {
     const int64_t p = p0 + tid / G;
@@ -372,12 +398,12 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
     if (++r == flush_rounds) {
       r = 0;
       __syncthreads();
-      table_flush(table, tid, 256, a.m, a.f, a.n_nodes);
+      table_flush(table, tid, 256, dst);
       __syncthreads();
     }
   }
   __syncthreads();
-  table_flush(table, tid, 256, a.m, a.f, a.n_nodes);
+  table_flush(table, tid, 256, dst);
 }
 
 void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const double* x_mp,
@@ -389,14 +415,18 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
   const NodeSrc ns{x_nodes, packed, n_nodes};
   constexpr int G = 4, PPL = 10;
   if (fused != nullptr) {
-    if (precision == OTM_FP64)
-      k_lme_asm<G, PPL, double><<<kLmeAsmBlocks, 256, 0, s>>>(
-          ns, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity, beta, tol, max_iter, lam, N,
-          (double*)dN, diag, *fused);
-    else
-      k_lme_asm<G, PPL, float><<<kLmeAsmBlocks, 256, 0, s>>>(
-          ns, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity, beta, tol, max_iter, lam, N,
-          (float*)dN, diag, *fused);
+    auto run = [&](auto kernel, auto* dn) {
+      kernel<<<kLmeAsmBlocks, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity,
+                                           beta, tol, max_iter, lam, N, dn, diag, *fused);
+    };
+    const bool heat = fused->heat != nullptr;
+    if (precision == OTM_FP64) {
+      if (heat) run(k_lme_asm<G, PPL, double, true>, (double*)dN);
+      else run(k_lme_asm<G, PPL, double, false>, (double*)dN);
+    } else {
+      if (heat) run(k_lme_asm<G, PPL, float, true>, (float*)dN);
+      else run(k_lme_asm<G, PPL, float, false>, (float*)dN);
+    }
     return;
   }
   const unsigned nb = (unsigned)((n_mp + (256 / G) - 1) / (256 / G));

@@ -98,10 +98,18 @@ __global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restri
                                                      double wn2, int zero_mf,
                                                      double4* __restrict__ packed,
                                                      int64_t n_mp, otm_diag* diag,
-                                                     ToolArgs tool) {
+                                                     ToolArgs tool, double* __restrict__ heat,
+                                                     double cp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double mi = m[i];
+  // conduction: the nodal temperature h_I / m_I and its rate Q_I / (Cp m_I)
+  // from the sums of the last assembly (0 at a node without mass)
+  double Ti = 0.0, Ri = 0.0;
+  if (heat != nullptr && mi > 0.0) {
+    Ti = heat[i] / mi;
+    Ri = heat[n + i] / (cp * mi);
+  }
   double u[3], xs[3], xo[3], fi[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -139,9 +147,10 @@ __global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restri
   if (zero_mf) {
     m[i] = 0.0;
     f[i] = 0.0; f[n + i] = 0.0; f[2 * n + i] = 0.0;
+    if (heat != nullptr) { heat[i] = 0.0; heat[n + i] = 0.0; }
   }
   packed[2 * i] = make_double4(xs[0], xs[1], xs[2], u[0]);
-  packed[2 * i + 1] = make_double4(u[1], u[2], 0.0, 0.0);
+  packed[2 * i + 1] = make_double4(u[1], u[2], Ti, Ri);
 }
 
 __global__ __launch_bounds__(256) void k_pack_nodes(int64_t n, const double* __restrict__ x,
@@ -179,7 +188,7 @@ void launch_node_update(const otm_state& st, const otm_params& p, double dt, boo
   k_node_update<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
       n, st.x, st.du, st.m, st.f, dt * dt, p.wall_enabled, p.wall_x[0], p.wall_x[1],
       p.wall_x[2], p.wall_n[0], p.wall_n[1], p.wall_n[2], zero_mf ? 1 : 0, packed, st.n_mp,
-      diag, t);
+      diag, t, p.kappa > 0.0 ? st.heat : nullptr, p.Cp);
 }
 
 // ----------------------------------------------------- material-point pass
@@ -187,7 +196,11 @@ constexpr int kMpBlock = 256;
 constexpr int kGather = 16;            // lanes per MP in the gather phase
 constexpr int kSlots = 32 / kGather;   // pairs per lane loaded branch-free
 
-template <typename R>
+// Conduction (COND): the gather also sums grad T_p = sum_I T_I grad N_Ip and
+// sum_I N_Ip rate_I from the node records' (T_I, rate_I), kept in sums[13..16]
+// (past the slots that phase 2 parks values in); phase 2 adds
+// dt sum N rate to T_{n+1} and stores the flux -kappa grad T_p.
+template <typename R, bool COND>
 __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     const double4* __restrict__ nodes, int64_t n_nodes, int64_t n_mp,
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
@@ -195,11 +208,14 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     double* __restrict__ xp, double* __restrict__ vol, R* __restrict__ Fd, R* __restrict__ bed,
     double* __restrict__ epsbar, double* __restrict__ T, R* __restrict__ sigma, Mat<R> M,
     double* __restrict__ xp_prev, double* __restrict__ dFm1, int32_t* __restrict__ failed,
-    double* __restrict__ clock, double dt, otm_diag* diag) {
-  // phase 1: the 12 gathered sums of each MP; phase 2: the MP's eigenvectors,
-  // logarithmic strains and J parked over the return-map solve (each lane
-  // only touches its own column)
-  __shared__ double sums[13][kMpBlock];
+    double* __restrict__ clock, double dt, otm_diag* diag, double kappa,
+    double* __restrict__ qflux) {
+  // phase 1: the 12 (16 with conduction) gathered sums of each MP; phase 2:
+  // the MP's eigenvectors, logarithmic strains and J parked in sums[0..12]
+  // over the return-map solve (each lane only touches its own column)
+  constexpr int kSums = COND ? 17 : 13;
+  constexpr int kGathered = COND ? 16 : 12;
+  __shared__ double sums[kSums][kMpBlock];
   __shared__ int64_t row[kMpBlock + 1];
   const int64_t base = (int64_t)xcd_block() * kMpBlock;
   const int tid = threadIdx.x;
@@ -230,8 +246,12 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     // grad N stays in its stored type until it is used, so that no
     // conversion has to wait for a load in the round that issues it
     struct Pairs { double w[kSlots]; R g0[kSlots], g1[kSlots], g2[kSlots]; };
-    // a node record as three 16-byte pieces: (x, y), (z, du_x), (du_y, du_z)
-    struct Nodes { double2 a[kSlots], b[kSlots], c[kSlots]; bool use[kSlots]; };
+    // a node record as three 16-byte pieces: (x, y), (z, du_x), (du_y, du_z),
+    // and with conduction a fourth, (T_I, rate_I)
+    struct Nodes {
+      double2 a[kSlots], b[kSlots], c[kSlots], d[COND ? kSlots : 1];
+      bool use[kSlots];
+    };
     const double2* __restrict__ nd2 = reinterpret_cast<const double2*>(nodes);
     auto slot = [&](int r, int k, bool& use) {
       const int local = r * kPer + grp;
@@ -262,10 +282,11 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
         s.a[k] = nd2[4 * (int64_t)I];
         s.b[k] = nd2[4 * (int64_t)I + 1];
         s.c[k] = nd2[4 * (int64_t)I + 2];
+        if constexpr (COND) s.d[k] = nd2[4 * (int64_t)I + 3];
       }
     };
     auto sum_round = [&](int r, const Nodes& nd, const Pairs& pr) {
-      double a[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      double a[kGathered] = {};
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         const double wt = nd.use[k] ? pr.w[k] : 0.0;
@@ -278,12 +299,21 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
         a[3] += u0 * h0; a[4] += u0 * h1; a[5] += u0 * h2;
         a[6] += u1 * h0; a[7] += u1 * h1; a[8] += u1 * h2;
         a[9] += u2 * h0; a[10] += u2 * h1; a[11] += u2 * h2;
+        if constexpr (COND) {
+          const double tI = nd.d[k].x, rI = nd.d[k].y;
+          a[12] += tI * h0; a[13] += tI * h1; a[14] += tI * h2;
+          a[15] += wt * rI;
+        }
       }
 #pragma unroll
-      for (int c = 0; c < 12; ++c) a[c] = group_sum<kGather>(a[c]);
+      for (int c = 0; c < kGathered; ++c) a[c] = group_sum<kGather>(a[c]);
       if (lane == 0) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) sums[c][r * kPer + grp] = a[c];
+        if constexpr (COND) {
+#pragma unroll
+          for (int c = 12; c < 16; ++c) sums[c + 1][r * kPer + grp] = a[c];
+        }
       }
     };
     // rounds past the last reload the last round's rows (uniform control flow)
@@ -329,7 +359,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
       const int local = r * kPer + grp;
       const int64_t o0 = row[local], o1 = row[local + 1];
       if (o1 - o0 <= kSlots * kGather) continue;  // uniform within the group
-      double a[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      double a[kGathered] = {};
       for (int64_t q = o0 + kSlots * kGather + lane; q < o1; q += kGather) {
         const int32_t J = idx[q];
         const double wt = N[q];
@@ -340,16 +370,25 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
         a[3] += rb.y * h0; a[4] += rb.y * h1; a[5] += rb.y * h2;
         a[6] += rc.x * h0; a[7] += rc.x * h1; a[8] += rc.x * h2;
         a[9] += rc.y * h0; a[10] += rc.y * h1; a[11] += rc.y * h2;
+        if constexpr (COND) {
+          const double2 rd = nd2[4 * (int64_t)J + 3];
+          a[12] += rd.x * h0; a[13] += rd.x * h1; a[14] += rd.x * h2;
+          a[15] += wt * rd.y;
+        }
       }
 #pragma unroll
-      for (int c = 0; c < 12; ++c) a[c] = group_sum<kGather>(a[c]);
+      for (int c = 0; c < kGathered; ++c) a[c] = group_sum<kGather>(a[c]);
       if (lane == 0) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) sums[c][local] += a[c];
+        if constexpr (COND) {
+#pragma unroll
+          for (int c = 12; c < 16; ++c) sums[c + 1][local] += a[c];
+        }
       }
     }
   } else {
-    for (int i = tid; i < 12 * kMpBlock; i += kMpBlock) sums[i / kMpBlock][i % kMpBlock] = 0.0;
+    for (int i = tid; i < kSums * kMpBlock; i += kMpBlock) sums[i / kMpBlock][i % kMpBlock] = 0.0;
   }
   __syncthreads();
 
@@ -363,6 +402,14 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     for (int j = 0; j < 3; ++j) H.a[i][j] = sums[3 + 3 * i + j][tid];
   const double xnew[3] = {sums[0][tid], sums[1][tid], sums[2][tid]};
   bool finite = isfinite(xnew[0]) && isfinite(xnew[1]) && isfinite(xnew[2]);
+  // conduction: this step's increment and the new flux (with step n's
+  // shape functions and the nodal field of the node update)
+  double dTc = 0.0;
+  if constexpr (COND) {
+    dTc = dt * sums[16][tid];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) qflux[c * n_mp + p] = -kappa * sums[13 + c][tid];
+  }
   const double detdF = 1.0 + det_one_plus_minus_one(H);
   // a failed MP (fracture) carries nothing, so its inversion does not matter
   const bool was_failed = failed != nullptr && failed[p] != 0;
@@ -414,9 +461,11 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
       sig.v[c] = M.mu / J * bm1 + (c < 3 ? M.lamL * lnJ / J : R(0));
     }
   } else if (was_failed) {
-    // eroded: no stress; b^e, epsbar and T stay as they were
+    // eroded: no stress; b^e, epsbar and T stay as they were (but for the
+    // conduction increment: a failed MP still holds heat)
 #pragma unroll
     for (int c = 0; c < 6; ++c) sig.v[c] = R(0);
+    if constexpr (COND) T[p] = T[p] + dTc;
   } else {
     // trial elastic left Cauchy-Green tensor, as a deviation from 1:
     // b_tr - 1 = H + H^T + H H^T + (1+H) Bd (1+H)^T
@@ -499,7 +548,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     epsbar[p] = eb_new;
     double T_new = Tn;
     if (M.model == OTM_J2_JC) {
-      T_new = Tn + (double)(M.chi * (R(1) - c) * q_tr * deps / M.rhoCp);
+      T_new = (Tn + dTc) + (double)(M.chi * (R(1) - c) * q_tr * deps / M.rhoCp);
       T[p] = T_new;
     }
     if (failed != nullptr && eb_new > 0.0) {
@@ -543,14 +592,26 @@ void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
   double* hist_f = p.eps_stab > 0.0 ? st.dFm1 : nullptr;
   int32_t* frac = p.fracture ? st.failed : nullptr;
   double* clock = p.tool_enabled ? st.clock : nullptr;
-  if (st.precision == OTM_FP64)
-    k_mp_update<double><<<nb, kMpBlock, 0, s>>>(
-        packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const double*)st.dN, st.xp, st.vol, (double*)st.Fd, (double*)st.bed, st.epsbar, st.T,
-        (double*)st.sigma, make_mat<double>(p, dt), hist_x, hist_f, frac, clock, dt, diag);
-  else
-    k_mp_update<float><<<nb, kMpBlock, 0, s>>>(
-        packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx, st.pair_capacity, st.N, (const float*)st.dN, st.xp, st.vol, (float*)st.Fd, (float*)st.bed, st.epsbar, st.T,
-        (float*)st.sigma, make_mat<float>(p, dt), hist_x, hist_f, frac, clock, dt, diag);
+  auto run = [&](auto kernel, auto* dn, auto* fd, auto* bd, auto* sg, auto mat) {
+    kernel<<<nb, kMpBlock, 0, s>>>(packed, st.n_nodes, n, st.nbr_offsets, st.nbr_idx,
+                                   st.pair_capacity, st.N, dn, st.xp, st.vol, fd, bd, st.epsbar,
+                                   st.T, sg, mat, hist_x, hist_f, frac, clock, dt, diag, p.kappa,
+                                   st.qflux);
+  };
+  const bool cond = p.kappa > 0.0;
+  if (st.precision == OTM_FP64) {
+    auto m = make_mat<double>(p, dt);
+    double *fd = (double*)st.Fd, *bd = (double*)st.bed, *sg = (double*)st.sigma;
+    const double* dn = (const double*)st.dN;
+    if (cond) run(k_mp_update<double, true>, dn, fd, bd, sg, m);
+    else run(k_mp_update<double, false>, dn, fd, bd, sg, m);
+  } else {
+    auto m = make_mat<float>(p, dt);
+    float *fd = (float*)st.Fd, *bd = (float*)st.bed, *sg = (float*)st.sigma;
+    const float* dn = (const float*)st.dN;
+    if (cond) run(k_mp_update<float, true>, dn, fd, bd, sg, m);
+    else run(k_mp_update<float, false>, dn, fd, bd, sg, m);
+  }
 }
 
 // ------------------------------------------------------------------- t = 0
@@ -594,6 +655,7 @@ void launch_init_fields(const otm_state& st, const otm_params& p, double dt, con
   }
   if (p.fracture && st.n_mp > 0)
     k_init_failed<<<(unsigned)((st.n_mp + 255) / 256), 256, 0, s>>>(st.n_mp, st.failed);
+  if (p.kappa > 0.0 && st.n_mp > 0) launch_zero(st.qflux, 3 * st.n_mp, s);  // no flux at t = 0
   double* gt = p.tool_enabled ? st.tool_gt : nullptr;
   double* clock = p.tool_enabled ? st.clock : nullptr;
   if (st.n_nodes > 0 || clock != nullptr) {  // one workgroup at least: it sets the clock

@@ -246,28 +246,43 @@ OTM_HD void sym_mul_vec(const double M[6], const double v[3], double o[3]) {
 }
 
 // ------------------------------------------------ nodal assembly table
-// A workgroup's per-node sums of (m, f) in LDS: open addressing on the node
-// id (multiplicative hash, linear probing).  A pair whose node finds no slot
-// within 32 probes goes straight to memory with float64 atomics; flush adds
-// each occupied slot's four sums to m and f with one atomic each and clears
+// A workgroup's per-node sums of V values (m and f, plus the two heat sums
+// with conduction) in LDS: open addressing on the node id (multiplicative
+// hash, linear probing).  A pair whose node finds no slot within 32 probes
+// goes straight to memory with float64 atomics; flush adds each occupied
+// slot's sums to their destination arrays with one atomic each and clears
 // the table.  Summation order varies from run to run.
 constexpr int kTableBits = 10;
 constexpr int kTableSlots = 1 << kTableBits;
 
-struct NodeTable {
+template <int V>
+struct NodeTableV {
   int32_t keys[kTableSlots];
-  double vals[4][kTableSlots];
+  double vals[V][kTableSlots];
 };
+using NodeTable = NodeTableV<4>;
 
-OTM_DEV void table_clear(NodeTable& t, int tid, int nthreads) {
+// Destination arrays of a table's V sums, each indexed by node.
+template <int V>
+struct NodeDst {
+  double* d[V];
+};
+OTM_HD NodeDst<4> mf_dst(double* m, double* f, int64_t n_nodes) {
+  return NodeDst<4>{{m, f, f + n_nodes, f + 2 * n_nodes}};
+}
+
+template <int V>
+OTM_DEV void table_clear(NodeTableV<V>& t, int tid, int nthreads) {
   for (int s = tid; s < kTableSlots; s += nthreads) {
     t.keys[s] = -1;
-    t.vals[0][s] = t.vals[1][s] = t.vals[2][s] = t.vals[3][s] = 0.0;
+#pragma unroll
+    for (int k = 0; k < V; ++k) t.vals[k][s] = 0.0;
   }
 }
 
-OTM_DEV void table_insert(NodeTable& t, int32_t I, double c0, double c1, double c2, double c3,
-                          double* m, double* f, int64_t n_nodes) {
+template <int V>
+OTM_DEV void table_insert(NodeTableV<V>& t, int32_t I, const double (&c)[V],
+                          const NodeDst<V>& dst) {
   uint32_t h = ((uint32_t)I * 2654435761u) >> (32 - kTableBits);
   int slot = -1;
   for (int probe = 0; probe < 32; ++probe) {
@@ -276,32 +291,39 @@ OTM_DEV void table_insert(NodeTable& t, int32_t I, double c0, double c1, double 
     h = (h + 1) & (kTableSlots - 1);
   }
   if (slot >= 0) {
-    atomicAdd(&t.vals[0][slot], c0);
-    atomicAdd(&t.vals[1][slot], c1);
-    atomicAdd(&t.vals[2][slot], c2);
-    atomicAdd(&t.vals[3][slot], c3);
+#pragma unroll
+    for (int k = 0; k < V; ++k) atomicAdd(&t.vals[k][slot], c[k]);
   } else {  // crowded table: straight to memory
-    atomicAdd(&m[I], c0);
-    atomicAdd(&f[I], c1);
-    atomicAdd(&f[n_nodes + I], c2);
-    atomicAdd(&f[2 * n_nodes + I], c3);
+#pragma unroll
+    for (int k = 0; k < V; ++k) atomicAdd(&dst.d[k][I], c[k]);
   }
+}
+
+OTM_DEV void table_insert(NodeTable& t, int32_t I, double c0, double c1, double c2, double c3,
+                          double* m, double* f, int64_t n_nodes) {
+  const double c[4] = {c0, c1, c2, c3};
+  table_insert<4>(t, I, c, mf_dst(m, f, n_nodes));
 }
 
 // Every lane of the workgroup calls this after a barrier; it ends cleared
 // (a barrier is needed before the next inserts).
-OTM_DEV void table_flush(NodeTable& t, int tid, int nthreads, double* m, double* f,
-                         int64_t n_nodes) {
+template <int V>
+OTM_DEV void table_flush(NodeTableV<V>& t, int tid, int nthreads, const NodeDst<V>& dst) {
   for (int s = tid; s < kTableSlots; s += nthreads) {
     const int32_t I = t.keys[s];
     if (I < 0) continue;
-    atomicAdd(&m[I], t.vals[0][s]);
-    atomicAdd(&f[I], t.vals[1][s]);
-    atomicAdd(&f[n_nodes + I], t.vals[2][s]);
-    atomicAdd(&f[2 * n_nodes + I], t.vals[3][s]);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      atomicAdd(&dst.d[k][I], t.vals[k][s]);
+      t.vals[k][s] = 0.0;
+    }
     t.keys[s] = -1;
-    t.vals[0][s] = t.vals[1][s] = t.vals[2][s] = t.vals[3][s] = 0.0;
   }
+}
+
+OTM_DEV void table_flush(NodeTable& t, int tid, int nthreads, double* m, double* f,
+                         int64_t n_nodes) {
+  table_flush<4>(t, tid, nthreads, mf_dst(m, f, n_nodes));
 }
 
 }  // namespace otm

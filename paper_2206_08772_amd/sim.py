@@ -56,6 +56,9 @@ def make_params(p):
         q.wall_n[i] = float(wn[i])
         q.body_force[i] = 0.0
     q.eps_stab = float(p.get("eps_stab", 0.0))
+    q.kappa = float(p.get("kappa", 0.0))
+    q.insert_dist = float(p.get("insert_dist", 0.0))
+    q.delete_orphans = 1 if p.get("delete_orphans", False) else 0
     q.fracture = 1 if p.get("fracture", False) else 0
     q.tool_enabled = 1 if p.get("tool", False) else 0
     d = p.get("jc_d", (0.0,) * 5)
@@ -158,7 +161,8 @@ class Sim:
     """
 
     def __init__(self, x_nodes, x_mp, vol_mp, mass_mp, v0_nodes, params, precision="fp64",
-                 scatter="atomic", pair_capacity=None, capacity_margin=1.3, device="cuda"):
+                 scatter="atomic", pair_capacity=None, capacity_margin=1.3, device="cuda",
+                 node_capacity=None):
         self.device = torch.device(device)
         self.params = dict(params)
         self.p = make_params(params)
@@ -169,10 +173,18 @@ class Sim:
         rdt = torch.float64 if self.prec == _lib.OTM_FP64 else torch.float32
         nn, nm = len(x_nodes), len(x_mp)
         self.n_nodes, self.n_mp = nn, nm
-        self.x = soa(x_nodes, dev)
-        self.du = torch.zeros(3, nn, dtype=torch.float64, device=dev)
-        self.m = torch.zeros(nn, dtype=torch.float64, device=dev)
-        self.f = torch.zeros(3, nn, dtype=torch.float64, device=dev)
+        # node arrays: room for nodes added at erosion (insert_dist > 0); each
+        # array is a [k][n_nodes] view of the first k * n_nodes entries
+        insert = float(params.get("insert_dist", 0.0)) > 0.0
+        if node_capacity is None:
+            node_capacity = nn + (max(1024, nm // 4) if insert else 0)
+        self.ncap = max(int(node_capacity), nn)
+        self._node_bufs = {}
+        self.x = self._node_array("x", 3)
+        self.x.copy_(soa(x_nodes, dev))
+        self.du = self._node_array("du", 3)
+        self.m = self._node_array("m", 1)
+        self.f = self._node_array("f", 3)
         self.xp = soa(x_mp, dev)
         self.vol = torch.as_tensor(np.asarray(vol_mp, np.float64), device=dev).clone()
         self.mass = torch.as_tensor(np.asarray(mass_mp, np.float64), device=dev).clone()
@@ -190,8 +202,12 @@ class Sim:
         self.fracture = bool(params.get("fracture", False))
         self.tool = bool(params.get("tool", False))
         self.failed = torch.zeros(nm, dtype=torch.int32, device=dev) if self.fracture else None
-        self.tool_gt = torch.zeros(3, nn, dtype=torch.float64, device=dev) if self.tool else None
+        self.tool_gt = self._node_array("tool_gt", 3) if self.tool else None
         self.clock = torch.zeros(1, dtype=torch.float64, device=dev) if self.tool else None
+        # heat conduction: nodal sums h_I, Q_I of the assembly and MP fluxes
+        self.cond = float(params.get("kappa", 0.0)) > 0.0
+        self.heat = self._node_array("heat", 2) if self.cond else None
+        self.qflux = torch.zeros(3, nm, dtype=torch.float64, device=dev) if self.cond else None
         self.offsets = torch.zeros(nm + 1, dtype=torch.int64, device=dev)
         self.v0 = soa(v0_nodes, dev)
         if pair_capacity is None:
@@ -201,11 +217,27 @@ class Sim:
         self.idx = torch.zeros(self.cap, dtype=torch.int32, device=dev)
         self.N = torch.zeros(self.cap, dtype=torch.float64, device=dev)
         self.dN = torch.zeros(3, self.cap, dtype=rdt, device=dev)
-        self.ws = Workspace(nn, nm, self.cap, dev)
+        self.ws = Workspace(self.ncap, nm, self.cap, dev)
+        self.node_events = (0, 0)
         self.diag = new_diag(dev)
         self.st = State()
         self._fill_state()
         self.n = 0
+        # bumped whenever the state's arrays move or change shape (erosion,
+        # swapped lists): graphs captured before hold the old layout
+        self.layout = 0
+
+    def _node_array(self, name, comps):
+        """A zeroed [comps][n_nodes] float64 view into a buffer with room for
+        ``ncap`` nodes."""
+        buf = torch.zeros(comps * self.ncap, dtype=torch.float64, device=self.device)
+        self._node_bufs[name] = (buf, comps)
+        return self._node_view(name, self.n_nodes)
+
+    def _node_view(self, name, n):
+        buf, comps = self._node_bufs[name]
+        v = buf[: comps * n]
+        return v if comps == 1 else v.view(comps, n)
 
     def _count_pairs(self):
         P = C.c_int64(0)
@@ -232,6 +264,9 @@ class Sim:
         s.failed = _addr(self.failed).value if self.fracture else None
         s.tool_gt = _addr(self.tool_gt).value if self.tool else None
         s.clock = _addr(self.clock).value if self.tool else None
+        s.heat = _addr(self.heat).value if self.cond else None
+        s.qflux = _addr(self.qflux).value if self.cond else None
+        s.node_capacity = self.ncap
 
     # ---------------------------------------------------------------- calls
     def init(self):
@@ -274,6 +309,7 @@ class Sim:
         self.offsets, self.idx, self.N, self.dN = (lists["offsets"], lists["idx"], lists["N"],
                                                    lists["dN"])
         self._fill_state()
+        self.layout += 1
 
     def run(self, steps, rebuild_every=1):
         for _ in range(steps):
@@ -284,9 +320,12 @@ class Sim:
         (lists rebuilt every step if ``rebuild``).  One replay advances the
         state by ``steps`` steps with a single launch, which pays off when a
         step is short enough for kernel launches to dominate.  The graph holds
-        this Sim's device pointers and is valid for its lifetime; the step
-        path records no memset and no host synchronisation.  Take at least one
-        eager step first, so that every kernel is loaded before capture."""
+        this Sim's device pointers, sizes and component strides: it is valid
+        until ``erode`` (which shrinks the MP arrays) or ``use_lists`` (which
+        points the state at other arrays), after which replaying it raises
+        and the steps must be captured again.  The step path records no
+        memset and no host synchronisation.  Take at least one eager step
+        first, so that every kernel is loaded before capture."""
         g = torch.cuda.CUDAGraph()
         torch.cuda.synchronize(self.device)
         with torch.cuda.graph(g):
@@ -303,28 +342,38 @@ class Sim:
 
     def erode(self):
         """Remove the failed MPs from the body (otm_erode) and recompute the
-        lists, shape functions, mass and force of the rest.  The per-MP
-        tensors become views of their first n_mp entries per component (the
-        memory stays allocated).  Returns the number of MPs removed."""
+        lists, shape functions, mass and force of the rest; with
+        ``insert_dist`` nodes are first added at the freed surface and with
+        ``delete_orphans`` the nodes left in no support are removed.  The
+        per-MP and node tensors become views of their first n entries per
+        component (the memory stays allocated).  Returns the number of MPs
+        removed; ``node_events`` holds (nodes added, nodes deleted)."""
         removed = C.c_int64(0)
+        events = (C.c_int64 * 2)()
         check(lib().otm_erode(C.byref(self.st), C.byref(self.p), self.mode, self.ws.ptr,
-                              self.ws.nbytes, _ptr(self.diag), C.byref(removed), _stream()),
-              "otm_erode")
+                              self.ws.nbytes, _ptr(self.diag), C.byref(removed), events,
+                              _stream()), "otm_erode")
         n = int(self.st.n_mp)
-        for k in ("xp", "lam", "Fd", "bed", "sigma"):
+        for k in ("xp", "lam", "Fd", "bed", "sigma") + (("qflux",) if self.cond else ()):
             t = getattr(self, k)
             setattr(self, k, t.reshape(-1)[: t.shape[0] * n].view(t.shape[0], n))
         for k in ("vol", "mass", "epsbar", "T", "failed"):
             setattr(self, k, getattr(self, k)[:n])
         self.offsets = self.offsets[: n + 1]
         self.n_mp = n
+        nn = int(self.st.n_nodes)
+        for k in self._node_bufs:
+            setattr(self, k, self._node_view(k, nn))
+        self.n_nodes = nn
+        self.node_events = (int(events[0]), int(events[1]))
         self._fill_state()
+        self.layout += 1
         return int(removed.value)
 
     # ------------------------------------------------------- save / resume
     _SAVED = ("x", "du", "m", "f", "xp", "vol", "mass", "lam", "Fd", "bed", "epsbar", "T",
               "sigma", "offsets", "idx", "N", "dN", "xp_prev", "dFm1", "failed", "tool_gt",
-              "clock", "v0")
+              "clock", "v0", "heat", "qflux")
 
     def state_dict(self):
         """Host copies of every state array and the step count: what a later
@@ -337,10 +386,12 @@ class Sim:
         return d
 
     def load_state_dict(self, d):
-        """Resume from ``state_dict()``.  The lists are searched again (the
-        search is exact, so they come out the same) so that workspace data
-        derived from them (the segmented mode's influence lists) is rebuilt;
-        then every saved array, mass and force included, is put back."""
+        """Resume from ``state_dict()``.  Every saved array is put back, the
+        saved support lists included (with a list skin they are not what a
+        search at the saved positions would give); a refresh without a search
+        then rebuilds what the workspace derives from those lists (the
+        segmented mode's influence lists), and the saved arrays it recomputed
+        (shape functions, multipliers, mass, force) are put back again."""
         for k in self._SAVED:
             t = getattr(self, k)
             if t is None:
@@ -350,7 +401,7 @@ class Sim:
         for k in self._SAVED:
             if getattr(self, k) is not None:
                 getattr(self, k).copy_(d[k])
-        self.refresh(rebuild=True)
+        self.refresh(rebuild=False)
         for k in self._SAVED:
             if getattr(self, k) is not None:
                 getattr(self, k).copy_(d[k])
@@ -400,15 +451,23 @@ class Sim:
         if self.tool:
             out["gT"] = g(self.tool_gt).T.copy()
             out["clock"] = float(self.clock.cpu()[0])
+        if self.cond:
+            out["q"] = g(self.qflux).T.copy()
+            out["heat_h"], out["heat_Q"] = g(self.heat)
         return out
 
 
 class StepGraph:
-    """Replayable capture of a fixed number of steps of one Sim."""
+    """Replayable capture of a fixed number of steps of one Sim, valid while
+    the Sim's array layout is the one it was captured with."""
 
     def __init__(self, sim, graph, steps):
         self.sim, self.graph, self.steps = sim, graph, steps
+        self.layout = sim.layout
 
     def replay(self):
+        if self.sim.layout != self.layout:
+            raise RuntimeError("the simulation's arrays changed since this graph was captured "
+                               "(erosion or swapped lists): capture the steps again")
         self.graph.replay()
         self.sim.n += self.steps

@@ -254,7 +254,7 @@ def test_erode_argument_checks(L):
     n = C.c_int64(-1)
 
     def call(p, st, out=C.byref(n), mode=0):
-        return lib.otm_erode(C.byref(st), C.byref(p), mode, ws, 1 << 30, diag, out, None)
+        return lib.otm_erode(C.byref(st), C.byref(p), mode, ws, 1 << 30, diag, out, None, None)
 
     st = _fake_state(L)
     ok = make_params(W.params_from_workload(w))
@@ -263,7 +263,16 @@ def test_erode_argument_checks(L):
     assert call(ok, st, out=None) == L.OTM_ERR_ARG
     assert call(ok, st, mode=7) == L.OTM_ERR_ARG
     assert lib.otm_erode(C.byref(st), C.byref(ok), 0, ws, 1 << 30, C.c_void_p(0), C.byref(n),
-                         None) == L.OTM_ERR_ARG
+                         None, None) == L.OTM_ERR_ARG
+    # node management: a negative insertion distance, an unknown flag, a
+    # negative node capacity
+    assert call(make_params(W.params_from_workload(w, insert_dist=-1.0)), st) == L.OTM_ERR_ARG
+    bad = make_params(W.params_from_workload(w))
+    bad.delete_orphans = 2
+    assert call(bad, st) == L.OTM_ERR_ARG
+    st.node_capacity = -5
+    assert call(ok, st) == L.OTM_ERR_ARG
+    st.node_capacity = 0
     st.failed = 0
     assert call(ok, st) == L.OTM_ERR_ARG
-    assert n.value == -1 and st.n_mp == 20
+    assert n.value == -1 and st.n_mp == 20 and st.n_nodes == 10

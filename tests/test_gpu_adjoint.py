@@ -22,21 +22,25 @@ def _problem(w, p, steps, every):
                 v0_unit=w.v0_nodes / speed, params=p, steps=steps, every=every), speed
 
 
+JC = ("A", "B", "n", "C", "m")
+
+
 def _gpu_grad(problem, speed, p, target):
     from paper_2206_08772_amd.adjoint import OTMRollout
-    theta = torch.tensor([p["A"], p["B"], p["n"]], dtype=torch.float64, requires_grad=True)
+    theta = torch.tensor([p[k] for k in JC], dtype=torch.float64, requires_grad=True)
     sp = torch.tensor(speed, dtype=torch.float64, requires_grad=True)
     x = OTMRollout.apply(theta, sp, problem)
     tgt = torch.as_tensor(target, device=x.device)
     loss = 0.5 * ((x - tgt) ** 2).sum()
     loss.backward()
-    return float(loss), theta.grad.cpu().numpy(), float(sp.grad)
+    return loss.item(), theta.grad.cpu().numpy(), sp.grad.item()
 
 
 @pytest.mark.parametrize("radius_scale", [1.0, 1.15])
 def test_adjoint_matches_complex_step_oracle(radius_scale):
     """Tiny J2/JC rod, 8 steps, checkpoints every 3: gradients of the final
-    position mismatch with respect to A, B, n and the impact speed.  The wider
+    position mismatch with respect to A, B, n, C, m, the impact speed and,
+    through OTMRolloutField, along a random initial velocity field.  The wider
     search radius gives supports of 20 to 45 nodes, so the MPs above 40 go
     through the adjoint's long-support launch."""
     w = W.taylor_rod(h=0.8e-3, seed=5, radius=2.4e-3, length=6.4e-3, steps=8, name="tiny_rod")
@@ -54,13 +58,25 @@ def test_adjoint_matches_complex_step_oracle(radius_scale):
     tgt_lists, st_t = OG.nominal_lists(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, pt,
                                        steps)
     target = st_t.x
+    d = np.random.default_rng(3).standard_normal(w.v0_nodes.shape) * np.abs(w.v0_nodes).max()
     ref = OG.complex_step_gradient(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, steps,
-                                   lists, target)
+                                   lists, target, params=JC, v0_dirs=(d,))
     problem, speed = _problem(w, p, steps, every=3)
     loss, gth, gsp = _gpu_grad(problem, speed, p, target)
-    for k, name in enumerate(("A", "B", "n")):
+    for k, name in enumerate(JC):
         assert abs(gth[k] - ref[name]) <= 1e-6 * abs(ref[name]), (name, gth[k], ref[name])
     assert abs(gsp - ref["speed"]) <= 1e-6 * abs(ref["speed"]), (gsp, ref["speed"])
+    # the per-node initial-velocity gradient, along the random field d
+    from paper_2206_08772_amd.adjoint import OTMRolloutField
+    theta = torch.tensor([p[k] for k in JC], dtype=torch.float64, requires_grad=True)
+    v0 = torch.tensor(w.v0_nodes, dtype=torch.float64, requires_grad=True)
+    x = OTMRolloutField.apply(theta, v0, problem)
+    tgt = torch.as_tensor(target, device=x.device)
+    (0.5 * ((x - tgt) ** 2).sum()).backward()
+    assert v0.grad.shape == w.v0_nodes.shape
+    gdir = float((v0.grad.numpy() * d).sum())
+    assert abs(gdir - ref[("v0", 0)]) <= 1e-6 * abs(ref[("v0", 0)]), (gdir, ref[("v0", 0)])
+    assert np.allclose(theta.grad.numpy(), gth, rtol=1e-12, atol=0)
 
 
 def _run(w, p, steps, speed, unit, lists=None, record=None):
@@ -86,8 +102,9 @@ def _run(w, p, steps, speed, unit, lists=None, record=None):
 
 
 def test_adjoint_against_finite_differences_adjoint_rod():
-    """268k MPs, 200 steps, checkpoints every 20; central differences with a
-    relative step of 1e-6 on rollouts whose support lists are frozen to the
+    """268k MPs, 200 steps, checkpoints every 20: the gradients by A, B, n,
+    C, m and the impact speed against central differences (relative step
+    1e-6, 1e-4 for C and m) on rollouts whose support lists are frozen to the
     nominal trajectory; agreement to 1e-4."""
     w = W.config_by_name("adjoint_rod")
     p = W.params_from_workload(w)
@@ -105,8 +122,10 @@ def test_adjoint_against_finite_differences_adjoint_rod():
         return 0.5 * float(((x - target) ** 2).sum())
 
     rel = {}
-    for k, name in enumerate(("A", "B", "n")):
-        e = 1e-6 * abs(p[name])
+    for k, name in enumerate(JC):
+        # C and m move the loss by little: a larger step keeps their
+        # differences well above round-off
+        e = (1e-6 if name in ("A", "B", "n") else 1e-4) * abs(p[name])
         fd = (L(dict(p, **{name: p[name] + e}), speed) - L(dict(p, **{name: p[name] - e}), speed)) \
             / (2 * e)
         rel[name] = abs(gth[k] - fd) / abs(fd)
@@ -183,7 +202,6 @@ def _tape(st, cap):
     return t, keep
 
 
-@pytest.mark.filterwarnings("ignore::RuntimeWarning")
 def test_adjoint_step_dot_products_against_oracle_jvp():
     """For one step of the tiny rod (state after 4 steps: plastic flow, heating
     and wall contact under way), <bar_n, delta> from otm_step_adjoint equals
@@ -206,7 +224,7 @@ def test_adjoint_step_dot_products_against_oracle_jvp():
     assert st.epsbar.max() > 0
     dirs = step_directions(st, np.random.default_rng(1))
     jvp = {k: OG.step_jvp(st, p, lists[5], direction={k: dirs[k]}) for k in OG.STEP_FIELDS}
-    jvp_th = {k: OG.step_jvp(st, p, lists[5], param=k) for k in ("A", "B", "n")}
+    jvp_th = {k: OG.step_jvp(st, p, lists[5], param=k) for k in JC}
 
     L = _lib.lib()
     nn, nm = st.x.shape[0], st.xp.shape[0]
@@ -230,7 +248,7 @@ def test_adjoint_step_dot_products_against_oracle_jvp():
             tgt[..., :P1].copy_(torch.from_numpy(np.ascontiguousarray(sbar[..., :P1])))
         else:
             tgt.copy_(torch.from_numpy(sbar))
-        theta = torch.zeros(3, dtype=torch.float64, device="cuda")
+        theta = torch.zeros(5, dtype=torch.float64, device="cuda")
         bn, bc = nxt.struct(), cur.struct()
         _lib.check(L.otm_step_adjoint(C.byref(t0), C.byref(t1), C.byref(pp), p["dt"], _ptr(mass),
                                       C.byref(bn), C.byref(bc), _ptr(theta), _ptr(ws), ws_bytes,
@@ -256,7 +274,7 @@ def test_adjoint_step_dot_products_against_oracle_jvp():
             if scale > 0:
                 worst = max(worst, abs(lhs - rhs) / scale)
         th = theta.cpu().numpy()
-        for k, name in enumerate(("A", "B", "n")):
+        for k, name in enumerate(JC):
             jo = _tangent_layout(o, jvp_th[name][o])
             rhs = float((sbar * jo).sum())
             scale = float(np.abs(sbar * jo).sum())

@@ -52,3 +52,79 @@ def test_inverted_material_points_are_reported():
     code, d = sim.check_diag(raise_on_error=False)
     assert d.flags & (1 << (-_lib.OTM_ERR_INVERTED - 1))
     assert d.n_inverted == w.n_mp and d.first_inverted == 0
+
+
+def _flag(code):
+    return 1 << (-code - 1)
+
+
+def test_nonfinite_stress_state_is_reported_at_its_mp():
+    """NaN written from the host into b^e of one MP: the MP pass returns a
+    non-finite stress for that MP alone (every loop of the return map is
+    bounded, so the kernels finish), which is reported with its index."""
+    from paper_2206_08772_amd import _lib
+    w = W.config_by_name("small_rod")
+    sim, p = make_sim(w, scatter="segmented")
+    sim.init()
+    for _ in range(3):
+        sim.step()
+    assert sim.check_diag()[0] == 0
+    k = 1234
+    sim.bed[:, k] = float("nan")
+    sim.step(rebuild=False)
+    code, d = sim.check_diag(raise_on_error=False)
+    assert d.flags & _flag(_lib.OTM_ERR_NONFINITE)
+    assert d.n_nonfinite == 1 and d.first_nonfinite == k
+    assert torch.isnan(sim.sigma[:, k]).all()
+    assert torch.isfinite(sim.sigma[:, :k]).all() and torch.isfinite(sim.sigma[:, k + 1:]).all()
+
+
+def test_nonfinite_node_force_is_reported_at_the_node_and_its_mps():
+    """NaN written into the force of one node I: the node update reports the
+    node (index n_mp + I) and the MP pass every MP whose support holds I
+    (their positions gather the NaN); the smallest of those MPs is the first
+    index."""
+    from paper_2206_08772_amd import _lib
+    w = W.config_by_name("small_rod")
+    sim, p = make_sim(w, scatter="segmented")
+    sim.init()
+    sim.step()
+    assert sim.check_diag()[0] == 0
+    g = sim.fields()
+    I = int(g["idx"][g["offsets"][500]])           # a node of MP 500's support
+    mp_of_pair = np.repeat(np.arange(sim.n_mp), np.diff(g["offsets"]))
+    users = np.unique(mp_of_pair[g["idx"] == I])
+    assert users.size > 5
+    sim.f[1, I] = float("nan")
+    sim.step(rebuild=False)
+    code, d = sim.check_diag(raise_on_error=False)
+    assert d.flags & _flag(_lib.OTM_ERR_NONFINITE)
+    assert d.first_nonfinite == users.min()
+    assert d.n_nonfinite == 1 + users.size
+    assert torch.isnan(sim.x[:, I]).any()
+
+
+def test_return_map_non_convergence_is_reported():
+    """rm_max_iter = 1 on a step with plastic flow: the return map of the
+    yielding MPs stops unconverged.  Two bit-identical runs (segmented
+    assembly) reach the same state; the next step with the normal limit
+    tells which MPs yield, and the capped step reports those, with the first
+    index among them."""
+    from paper_2206_08772_amd import _lib
+    w = W.config_by_name("small_rod")
+    a, _ = make_sim(w, scatter="segmented")
+    b, _ = make_sim(w, scatter="segmented")
+    for s in (a, b):
+        s.init()
+        s.run(6)
+        assert s.check_diag()[0] == 0
+    eb0 = a.epsbar.cpu().numpy().copy()
+    a.step()
+    plastic = np.nonzero(a.epsbar.cpu().numpy() > eb0)[0]
+    assert plastic.size > 20
+    b.p.rm_max_iter = 1
+    b.step()
+    code, d = b.check_diag(raise_on_error=False)
+    assert code == _lib.OTM_ERR_RM_NOCONV
+    assert d.first_rm_noconv in set(plastic.tolist())
+    assert 0.9 * plastic.size <= d.n_rm_noconv <= plastic.size

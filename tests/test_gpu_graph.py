@@ -73,3 +73,20 @@ def test_cutting_step_graph_replays_match_eager_steps():
     assert b["failed"].sum() > 0 or (np.abs(b["gT"]).sum() > 0)
     eager.check_diag()
     graphed.check_diag()
+
+
+def test_graph_replay_after_erosion_raises():
+    """Erosion shrinks the MP arrays and their component stride: a graph
+    captured before it must not replay."""
+    w = W.config_by_name("small_cut")
+    sim, _ = make_sim(w)
+    sim.init()
+    sim.step()
+    g = sim.capture(steps=1)
+    g.replay()
+    sim.erode()
+    with pytest.raises(RuntimeError, match="capture the steps again"):
+        g.replay()
+    g2 = sim.capture(steps=1)
+    g2.replay()
+    sim.check_diag()

@@ -43,3 +43,27 @@ def test_resume_continues_bit_for_bit(name, tmp_path):
         assert np.array_equal(a.xp_prev.cpu().numpy(), b.xp_prev.cpu().numpy())
     a.check_diag()
     b.check_diag()
+
+
+def test_resume_between_list_rebuilds_segmented():
+    """Lists with a skin (radius r + 0.1 h) rebuilt every 10 steps, saved at
+    step 15: the resumed run keeps the saved lists (not those of a search
+    at the saved positions) and the influence lists built from them, and continues bit for bit through the rebuilds at 20 and 30."""
+    w = W.config_by_name("small_rod")
+    r = w.r_list + 0.1 * w.h
+    over = dict(r_list=r, cell_size=r * 1.0001, rebuild_every=10)
+    a, _ = make_sim(w, scatter="segmented", **over)
+    a.init()
+    a.run(15, rebuild_every=10)
+    d = a.state_dict()
+    a.run(20, rebuild_every=10)
+    b, _ = make_sim(w, scatter="segmented", **over)
+    b.load_state_dict(d)
+    assert b.n == 15
+    b.run(20, rebuild_every=10)
+    fa, fb = a.fields(), b.fields()
+    for k in ["x", "du", "m", "f", "xp", "vol", "sigma", "epsbar", "T", "N", "dN", "lam",
+              "offsets", "idx"]:
+        assert np.array_equal(np.asarray(fa[k]), np.asarray(fb[k])), k
+    a.check_diag()
+    b.check_diag()

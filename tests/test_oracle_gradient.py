@@ -31,10 +31,13 @@ def test_complex_rollout_primal_matches_real(setup):
 
 def test_complex_step_matches_central_differences(setup):
     w, p, steps, lists, target, st = setup
+    d = np.random.default_rng(3).standard_normal(w.v0_nodes.shape) * np.abs(w.v0_nodes).max()
     g = OG.complex_step_gradient(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, steps,
-                                 lists, target, params=("A", "B", "n"))
-    for name in ("A", "B", "n"):
-        e = 1e-6 * abs(p[name])
+                                 lists, target, params=("A", "B", "n", "C", "m"), v0_dirs=(d,))
+    for name in ("A", "B", "n", "C", "m"):
+        # C and m move the loss by little (rate factor and the small heating
+        # of 8 steps): a larger step keeps their differences above round-off
+        e = (1e-6 if name in ("A", "B", "n") else 1e-4) * abs(p[name])
         lp = OG.loss(OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes,
                                 dict(p, **{name: p[name] + e}), steps, lists), target)
         lm = OG.loss(OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes,
@@ -49,6 +52,14 @@ def test_complex_step_matches_central_differences(setup):
                             steps, lists), target)
     fd = (lp - lm) / (2 * e)
     assert abs(g["speed"] - fd) <= 1e-4 * abs(fd), (g["speed"], fd)
+    # along a random initial velocity field (per-node gradient)
+    e = 1e-6
+    lp = OG.loss(OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes + e * d, p,
+                            steps, lists), target)
+    lm = OG.loss(OG.rollout(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes - e * d, p,
+                            steps, lists), target)
+    fd = (lp - lm) / (2 * e)
+    assert abs(g[("v0", 0)] - fd) <= 1e-4 * abs(fd), (g[("v0", 0)], fd)
 
 
 @pytest.fixture(scope="module")
@@ -63,7 +74,7 @@ def one_step():
 
 
 @pytest.mark.filterwarnings("ignore::RuntimeWarning")
-@pytest.mark.parametrize("field", OG.STEP_FIELDS + ("A", "B", "n"))
+@pytest.mark.parametrize("field", OG.STEP_FIELDS + ("A", "B", "n", "C", "m"))
 def test_step_jvp_matches_central_differences(one_step, field):
     """The complex-step derivative of the one-step map along a seeded direction
     of each state field (and by each hardening constant) against central
