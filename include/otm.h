@@ -13,7 +13,8 @@
  *  - All array arguments are DEVICE pointers into caller-owned buffers, unless
  *    marked "host".  The library never allocates device memory: scratch space
  *    comes from a caller-provided workspace of otm_workspace_bytes() bytes,
- *    256-byte aligned.  The caller keeps ownership of everything it passes.
+ *    256-byte aligned (otm_step_noalloc instead uses a fixed device array of
+ *    the library).  The caller keeps ownership of everything it passes.
  *  - Vector fields are structure-of-arrays: a "[3][n]" array holds all x
  *    components, then all y, then all z.  Second-order tensors are stored per
  *    component: F as [9][n] row major (F_ij at component 3*i+j), symmetric
@@ -30,8 +31,9 @@
  *    points, pair capacity exceeded) are recorded in the caller's device
  *    otm_diag record and reported by otm_diag_read.
  *  - No C++ exception crosses this interface.  The library keeps no state
- *    between calls; calls on distinct streams with distinct buffers may run
- *    concurrently.
+ *    between calls (but for the per-device address of otm_step_noalloc's
+ *    scratch); calls on distinct streams with distinct buffers may run
+ *    concurrently (otm_step_noalloc calls on one device may not).
  */
 #ifndef OTM_H
 #define OTM_H
@@ -55,7 +57,9 @@ enum {
   OTM_ERR_INVERTED = -5,     /* det(dF) <= 0 at a material point */
   OTM_ERR_NONFINITE = -6,    /* non-finite stress or position */
   OTM_ERR_HIP = -7,          /* a HIP runtime call failed */
-  OTM_ERR_SUPPORT = -8       /* a support longer than the adjoint handles (48) */
+  OTM_ERR_SUPPORT = -8,      /* a support longer than the adjoint handles (48) */
+  OTM_ERR_SCRATCH = -9       /* otm_step_noalloc: the state needs more scratch
+                                than OTM_STATIC_SCRATCH_BYTES (host check) */
 };
 
 /* arithmetic of the step */
@@ -463,6 +467,33 @@ otm_status otm_init_adjoint(int64_t n_nodes, double dt, const double* du_bar, do
 otm_status otm_step_profiled(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
                              int32_t scatter_mode, void* ws, size_t ws_bytes, otm_diag* diag,
                              hipEvent_t* events, hipStream_t s);
+
+/* Size of the device scratch array otm_step_noalloc uses on each device. */
+#define OTM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): otm_step
+ * (same step, same arguments and results) with the library's own scratch in
+ * place of the caller's workspace.  The scratch is a file-scope device array
+ * of OTM_STATIC_SCRATCH_BYTES (64 MiB) per device, held by each device the
+ * library runs on until the process ends; the call allocates and frees
+ * nothing (no hipMalloc, no library routine that allocates).
+ *   Limit: states whose otm_workspace_bytes(n_nodes, n_mp, pair_capacity)
+ *   exceeds OTM_STATIC_SCRATCH_BYTES are rejected with OTM_ERR_SCRATCH before
+ *   anything is enqueued (about 30k MPs at 27 pairs each with the default
+ *   capacity margin fit).
+ *   Every call on one device shares that device's scratch, which keeps the
+ *   last call's contents: nothing carries over between calls (in the
+ *   segmented mode the influence lists are rebuilt from the state's support
+ *   lists on every call, which costs more than otm_step with rebuild = 0).
+ *   Calls that overlap in time on one device (distinct streams, or host
+ *   threads) race on the scratch and give wrong results: serialise them.
+ * Errors: as otm_step, plus OTM_ERR_SCRATCH; OTM_ERR_HIP if the scratch's
+ * device address cannot be obtained.
+ */
+otm_status otm_step_noalloc(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
+                            int32_t scatter_mode, otm_diag* diag, hipStream_t s);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(_HERE, "libotm.so")
 
 OTM_OK, OTM_ERR_ARG, OTM_ERR_CAPACITY, OTM_ERR_LME_NOCONV = 0, -1, -2, -3
 OTM_ERR_RM_NOCONV, OTM_ERR_INVERTED, OTM_ERR_NONFINITE, OTM_ERR_HIP = -4, -5, -6, -7
-OTM_ERR_SUPPORT = -8
+OTM_ERR_SUPPORT, OTM_ERR_SCRATCH = -8, -9
+OTM_STATIC_SCRATCH_BYTES = 64 << 20
 OTM_FP64, OTM_MIXED = 0, 1
 OTM_SCATTER_ATOMIC, OTM_SCATTER_SEGMENTED = 0, 1
 OTM_NEOHOOKE, OTM_J2_JC, OTM_J2_LINEAR = 0, 1, 2
@@ -120,6 +121,8 @@ _SIGS = {
     "otm_step_profiled": (C.c_int32, [C.POINTER(State), C.POINTER(Params), C.c_double,
                                       C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                       C.c_void_p, C.c_void_p]),
+    "otm_step_noalloc": (C.c_int32, [C.POINTER(State), C.POINTER(Params), C.c_double,
+                                     C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
 }
 
 _OPTIONAL = {

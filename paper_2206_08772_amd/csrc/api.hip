@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "erode.h"
 #include "launch.h"
 #include "otm_common.h"
@@ -238,6 +240,8 @@ const char* otm_status_string(otm_status s) {
     case OTM_ERR_NONFINITE: return "OTM_ERR_NONFINITE: non-finite stress or position";
     case OTM_ERR_HIP: return "OTM_ERR_HIP: HIP runtime error";
     case OTM_ERR_SUPPORT: return "OTM_ERR_SUPPORT: support longer than the adjoint handles";
+    case OTM_ERR_SCRATCH:
+      return "OTM_ERR_SCRATCH: the state needs more scratch than otm_step_noalloc has";
     default: return "unknown otm_status";
   }
 }
@@ -420,6 +424,48 @@ otm_status otm_step_profiled(otm_state* st, const otm_params* p, double dt, int3
   return step_impl(st, p, dt, rebuild, scatter_mode, ws, ws_bytes, diag, events, s);
 }
 
+}  // extern "C"
+
+// Allocation-free step: the workspace is this file-scope device array.  Each
+// device holds its own copy at its own address, found once per device with
+// hipGetSymbolAddress; host code only ever passes that address on (the
+// array's name in host code is a stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[OTM_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static otm_status static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return OTM_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+      return OTM_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return OTM_OK;
+}
+
+extern "C" {
+
+otm_status otm_step_noalloc(otm_state* st, const otm_params* p, double dt, int32_t rebuild,
+                            int32_t scatter_mode, otm_diag* diag, hipStream_t s) {
+  otm_status e;
+  if ((e = check_state(st)) != OTM_OK || (e = check_params(p)) != OTM_OK) return e;
+  if (carve_workspace(nullptr, 0, st->n_nodes, st->n_mp, st->pair_capacity, nullptr) >
+      (size_t)OTM_STATIC_SCRATCH_BYTES)
+    return OTM_ERR_SCRATCH;
+  void* ws = nullptr;
+  if ((e = static_scratch(&ws)) != OTM_OK) return e;
+  // the scratch holds whatever the last call on this device left: the
+  // segmented mode's influence lists are built anew from the state's lists
+  return step_impl(st, p, dt, rebuild, scatter_mode, ws, (size_t)OTM_STATIC_SCRATCH_BYTES,
+                   diag, nullptr, s, nullptr, true);
+}
 
 otm_status otm_erode(otm_state* st, const otm_params* p, int32_t scatter_mode, void* ws,
                      size_t ws_bytes, otm_diag* diag, int64_t* n_removed, int64_t* node_events,

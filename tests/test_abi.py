@@ -276,3 +276,20 @@ def test_erode_argument_checks(L):
     st.failed = 0
     assert call(ok, st) == L.OTM_ERR_ARG
     assert n.value == -1 and st.n_mp == 20 and st.n_nodes == 10
+
+
+def test_noalloc_step_rejects_states_larger_than_its_scratch(L):
+    """otm_step_noalloc refuses, before any device work, a state whose
+    workspace would exceed the static scratch."""
+    lib = L.lib()
+    p = _params(L)
+    st = _fake_state(L)
+    st.n_nodes, st.n_mp, st.pair_capacity = 200_000, 1_000_000, 30_000_000
+    assert lib.otm_workspace_bytes(st.n_nodes, st.n_mp, st.pair_capacity) > \
+        L.OTM_STATIC_SCRATCH_BYTES
+    code = lib.otm_step_noalloc(C.byref(st), C.byref(p), 1e-3, 1, 0, C.c_void_p(1 << 20), None)
+    assert code == L.OTM_ERR_SCRATCH
+    assert lib.otm_status_string(code).startswith(b"OTM_ERR_SCRATCH")
+    st.x = 0                                   # argument errors come first
+    assert lib.otm_step_noalloc(C.byref(st), C.byref(p), 1e-3, 1, 0, C.c_void_p(1 << 20),
+                                None) == L.OTM_ERR_ARG
