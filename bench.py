@@ -487,14 +487,15 @@ def main():
     main_run = run_variant(w, "fp64", "atomic", args.steps, args.warmup)
     variants = {}
     for v in [s for s in args.variants.split(",") if s and s != "none"]:
-        if v == "paper_rod":
-            variants[v] = run_paper_rod()
-            continue
-        if v == "cutting":
-            variants[v] = run_cutting()
-            continue
-        if v == "cutting_5m":
-            variants[v] = run_cutting_5m()
+        if v in ("paper_rod", "cutting", "cutting_5m"):
+            run = {"paper_rod": run_paper_rod, "cutting": run_cutting,
+                   "cutting_5m": run_cutting_5m}[v]
+            try:
+                variants[v] = run()
+            except Exception as e:          # a failed variant is reported, not fatal
+                variants[v] = {"error": f"{type(e).__name__}: {e}"}
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
             continue
         prec = "mixed" if v == "mixed" else "fp64"
         scat = "segmented" if v == "segmented" else "atomic"

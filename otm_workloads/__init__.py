@@ -144,7 +144,7 @@ def _morton3(i, j, k):
 
 
 def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False, clamp_x0=False,
-                  hex_order="morton", node_order="morton"):
+                  hex_order="morton", node_order="morton", clamp_x1=None):
     """Lattice nodes inside a body, their jitter, the hex cells and tets.
 
     ``inside(i, j, k)`` receives integer index arrays and returns a mask.
@@ -176,6 +176,8 @@ def _lattice_body(ijk_ranges, inside, h, seed, clamp_z0=False, clamp_x0=False,
         x[:, 2] = np.maximum(x[:, 2], 0.0)
     if clamp_x0:
         x[:, 0] = np.maximum(x[:, 0], 0.0)
+    if clamp_x1 is not None:
+        x[:, 0] = np.minimum(x[:, 0], clamp_x1)
 
     # hex cells with all 8 corners present, in (k, j, i) order
     corners = []
@@ -288,7 +290,7 @@ def ti_params(seed):
 
 def cutting_slab(h=2e-6, seed=7, length=300e-6, height=120e-6, layers=3, depth=100e-6,
                  speed=5.0, tip_radius=2e-6, clearance_deg=7.0, engage=0.0, steps=2000,
-                 dt=1e-10, name="cutting_slab", fracture=None):
+                 dt=1e-10, name="cutting_slab", fracture=None, flat_face=False):
     """Orthogonal cutting (Sec. 4.2): a workpiece of length x height
     (x, y) and ``layers`` node layers through the thickness (z), a rigid tool
     of tip radius 2 um and rake angle 0 moving at -speed along x with the
@@ -297,12 +299,14 @@ def cutting_slab(h=2e-6, seed=7, length=300e-6, height=120e-6, layers=3, depth=1
     Taylor-Quinney coefficient, the paper's T_m = 1630 C and T_r = 25 C,
     Johnson-Cook flow and fracture constants from ``seed``; Coulomb
     friction 0.8; normal and tangential penalties E h.  ``engage`` moves the
-    tool that far into the workpiece at t = 0."""
+    tool that far into the workpiece at t = 0; ``flat_face`` clamps the
+    jittered nodes to x <= length, so that a tool starting at the face
+    touches it without overlap."""
     ni = int(round(length / h))
     nj = int(round(height / h))
     x, X, x_mp, vol = _lattice_body(((0, ni), (0, nj), (0, layers - 1)),
                                     lambda i, j, k: np.ones(i.shape, bool), h, seed,
-                                    clamp_x0=True)
+                                    clamp_x0=True, clamp_x1=length if flat_face else None)
     flow, frac = ti_params(seed)
     mat = Material(MODEL_J2_JC, E=113.8e9, nu=0.342, rho0=4430.0, chi=0.9,
                    T_r=298.15, T_m=1903.15, Cp=580.0, eps_dot0=1.0, **flow)
@@ -317,18 +321,23 @@ def cutting_slab(h=2e-6, seed=7, length=300e-6, height=120e-6, layers=3, depth=1
 
 def cutting_slab_5m(h=4.64e-6, seed=11, steps=500):
     """Orthogonal cutting at the scale of a production run: a 2 x 1 x 0.05 mm
-    workpiece (431 x 216 x 12 node lattice, about 1.1M nodes and 5.5M MPs),
+    workpiece (431 x 216 x 12 node lattice, 1.12M nodes and 6.14M MPs),
     the rigid tool (rake angle 0, tip radius 2 um, clearance 7 deg) at 5 m/s
-    with 0.1 mm depth of cut, starting in contact with the workpiece's face,
+    with 0.1 mm depth of cut, starting 0.1 um (2 % of h) into the workpiece's
+    face (made flat: the jitter would otherwise put nodes up to 0.46 um inside
+    the tool at t = 0, which the penalty contact fires off at ~10^3 m/s),
     dt = 1e-10 s, 500 steps, Ti-alloy-like flow constants from ``seed``, heat
     conduction with the Ti-alloy conductivity 6.7 W/(m K), and low fracture
     constants d = (0, 0.005, -0.5, 0.014, 3.7) so that MPs ahead of the tool
     fail and are removed within the run (the real constants would need far
-    more steps); nodes are added at the freed surface (insert_dist = h / 2)
-    and nodes left in no support deleted."""
+    more steps; in 500 steps the tool advances 0.25 um, and the initial
+    engagement is what makes the MPs at the tool yield and fail within the
+    run); nodes are added at the freed surface (insert_dist = h / 2) and
+    nodes left in no support deleted."""
     w = cutting_slab(h=h, seed=seed, length=2e-3, height=1e-3, layers=12, depth=0.1e-3,
                      speed=5.0, steps=steps, dt=1e-10, name="cutting_slab_5m",
-                     fracture=(0.0, 0.005, -0.5, 0.014, 3.7))
+                     fracture=(0.0, 0.005, -0.5, 0.014, 3.7), flat_face=True,
+                     engage=0.1e-6)
     w.material.kappa = 6.7
     w.insert_dist = 0.5 * h
     w.delete_orphans = True

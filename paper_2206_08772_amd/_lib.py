@@ -143,6 +143,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2206_08772_amd.build`")
+        # torch first: libotm then binds to the HIP runtime torch loaded (the
+        # one its tensors and streams belong to), not to a second copy
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in {**_SIGS, **_OPTIONAL}.items():
             fn = getattr(L, name)

@@ -7,6 +7,8 @@
 // memory.  Each MP's nodes are kept sorted by id in LDS while they are found,
 // so lists come out in canonical order.  The squared distance is evaluated as
 // ((dx*dx + dy*dy) + dz*dz) with every operation rounded separately.
+#include <type_traits>
+
 #include "launch.h"
 #include "otm_common.h"
 
@@ -522,31 +524,52 @@ OTM_DEV void cell_scan_one(const CellHdr& h, double r2, const double4* __restric
       valid[k] = k * kWave + lane < T;
       cid[k] = (int32_t)v[k].w;
     }
+    // NM MPs of the cell (lanes t .. t + NM - 1 of ``mine``) tested together:
+    // their chains are independent, so the hardware overlaps them
+    auto test_mps = [&](auto nm_tag, int t, int32_t pl) {
+      constexpr int NM = decltype(nm_tag)::value;
+      double px[NM], py[NM], pz[NM];
+      int32_t* row[NM];
+      int32_t p[NM];
+      uint32_t n[NM];
+#pragma unroll
+      for (int i = 0; i < NM; ++i) {
+        px[i] = lane_value(mine.x, t + i);
+        py[i] = lane_value(mine.y, t + i);
+        pz[i] = lane_value(mine.z, t + i);
+        p[i] = __builtin_amdgcn_readlane(pl, t + i);
+        row[i] = stage + (int64_t)p[i] * kRowCap;
+        n[i] = 0;
+      }
+#pragma unroll
+      for (int k = 0; k < kCandChunks; ++k) {
+        if (k < nch) {
+#pragma unroll
+          for (int i = 0; i < NM; ++i) {
+            // every lane computes the distance (stand-ins are masked), so no
+            // branch around it
+            const bool hit = (sqdist(px[i], py[i], pz[i], v[k].x, v[k].y, v[k].z) <= r2) &
+                             valid[k];
+            const uint64_t m = __ballot(hit);
+            const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, n[i]));
+            if (hit & (pos < (uint32_t)kRowCap)) row[i][pos] = cid[k];
+            n[i] += (uint32_t)__popcll(m);
+          }
+        }
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NM; ++i) offsets[p[i] + 1] = n[i];
+      }
+    };
     for (int32_t mb = m0; mb < m1; mb += kWave) {
       const int mc = m1 - mb < kWave ? (int)(m1 - mb) : kWave;
       if (mb != m0) mine = mp_sorted[mb + (lane < mc ? lane : mc - 1)];
       const int32_t pl = (int32_t)mine.w;  // this lane's MP
-      for (int t = 0; t < mc; ++t) {
-        const double px = lane_value(mine.x, t), py = lane_value(mine.y, t);
-        const double pz = lane_value(mine.z, t);
-        const int32_t p = __builtin_amdgcn_readlane(pl, t);
-        int32_t* row = stage + (int64_t)p * kRowCap;
-        uint32_t n = 0;
-#pragma unroll
-        for (int k = 0; k < kCandChunks; ++k) {
-          if (k < nch) {
-            // every lane computes the distance (stand-ins are masked), so no
-            // branch around it
-            const bool hit = (sqdist(px, py, pz, v[k].x, v[k].y, v[k].z) <= r2) & valid[k];
-            const uint64_t m = __ballot(hit);
-            const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, n));
-            if (hit & (pos < (uint32_t)kRowCap)) row[pos] = cid[k];
-            n += (uint32_t)__popcll(m);
-          }
-        }
-        if (lane == 0) offsets[p + 1] = n;
-      }
+      int t = 0;
+      for (; t + 1 < mc; t += 2) test_mps(std::integral_constant<int, 2>{}, t, pl);
+      if (t < mc) test_mps(std::integral_constant<int, 1>{}, t, pl);
     }
   } else {
     // dense neighbourhood: one MP at a time, candidates read from memory

@@ -100,3 +100,28 @@ def test_one_step_at_full_size(rod, precision, tol):
     OST.assemble(full, p)
     assert rel_err(g1["m"], full.m) < 1e-12
     assert rel_err(g1["f"], full.f) < (1e-12 if precision == "fp64" else 1e-6)
+
+
+def test_mixed_drift_over_100_steps_at_full_size(rod):
+    """The Taylor rod's 100 steps (1.13M MPs, lists rebuilt every step) in
+    mixed precision against the float64 run of the same steps on the GPU
+    (the float64 path is held to the oracle at 1e-10 by the tests above and
+    at the smaller sizes): every field within 1e-5 (R20 measure, positions as
+    displacements)."""
+    from tests.helpers import compare, gpu_fields
+    out = {}
+    for prec in ("fp64", "mixed"):
+        sim, p = make_sim(rod, prec, "atomic")
+        sim.init()
+        sim.run(rod.steps)
+        sim.check_diag()
+        out[prec] = gpu_fields(sim.fields(), rod.x_nodes, rod.x_mp, p["T_r"])
+        del sim
+    # the two runs may find different lists for MPs on the search radius, so
+    # per-pair fields are left out
+    fields = ["u", "du", "m", "f", "up", "vol", "Fm1", "be_m1", "sigma", "epsbar", "dT"]
+    errs = compare(out["mixed"], out["fp64"], fields)
+    print("mixed vs float64 after 100 steps, 1.13M MPs:",
+          {k: float("%.2e" % v) for k, v in errs.items()})
+    bad = {k: v for k, v in errs.items() if not v < 1e-5}
+    assert not bad, bad
