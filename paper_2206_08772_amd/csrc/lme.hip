@@ -148,6 +148,7 @@ OTM_DEV void store_dn(DN* dN, int64_t cap, int64_t q, const double g[3]) {
 
 // What happens to each finished pair besides storing N and grad N.
 struct NoSink {
+  static constexpr bool kBatch = false;
   OTM_DEV void begin(int64_t) {}
   OTM_DEV void operator()(int64_t, double, const double*) {}
 };
@@ -161,6 +162,7 @@ struct NoSink {
 // once the Newton solve is done.
 template <typename R, bool HEAT>
 struct AsmSink {
+  static constexpr bool kBatch = true;  // the cached path inserts a batch of pairs at once
   static constexpr int V = HEAT ? 6 : 4;
   NodeTableV<V>* t;
   const int32_t* idx;
@@ -172,11 +174,10 @@ struct AsmSink {
   NodeDst<V> dst;
   int64_t n_mp;
   double mp, vd, Tp, q0, q1, q2;
-  R v, s0, s1, s2, s3, s4, s5;
+  R s0, s1, s2, s3, s4, s5;
   OTM_DEV void begin(int64_t p) {
     mp = mass[p];
     vd = vol[p];
-    v = (R)vd;
     s0 = sigma[p]; s1 = sigma[n_mp + p]; s2 = sigma[2 * n_mp + p];
     s3 = sigma[3 * n_mp + p]; s4 = sigma[4 * n_mp + p]; s5 = sigma[5 * n_mp + p];
     if constexpr (HEAT) {
@@ -184,18 +185,23 @@ struct AsmSink {
       q0 = q[p]; q1 = q[n_mp + p]; q2 = q[2 * n_mp + p];
     }
   }
-  OTM_DEV void operator()(int64_t q_, double Nq, const double g[3]) {
+  OTM_DEV void values(double Nq, const double g[3], double (&c)[V]) const {
     const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
-    double c[V];
     c[0] = Nq * mp;
-    c[1] = (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2));
-    c[2] = (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2));
-    c[3] = (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2));
+    pair_force<R>(vd, s0, s1, s2, s3, s4, s5, g0, g1, g2, c[1], c[2], c[3]);
     if constexpr (HEAT) {
       c[4] = c[0] * Tp;
       c[5] = vd * ((q0 * (double)g0 + q1 * (double)g1) + q2 * (double)g2);
     }
+  }
+  OTM_DEV void operator()(int64_t q_, double Nq, const double g[3]) {
+    double c[V];
+    values(Nq, g, c);
     table_insert<V>(*t, idx[q_], c, dst);
+  }
+  template <int NB>
+  OTM_DEV void insert(const int32_t (&I)[NB], const bool (&use)[NB], const double (&c)[NB][V]) {
+    table_insert_batch<V, NB>(*t, I, use, c, dst);
   }
 };
 
@@ -204,25 +210,26 @@ struct AsmSink {
 // place in the node-sorted order, where each node later sums them in order.
 template <typename R>
 struct SegSink {
+  static constexpr bool kBatch = false;
   const double* vol;
   const double* mass;
   const R* sigma;
   const int32_t* pos_of;
   double4* contrib;
   int64_t n_mp;
-  double mp;
-  R v, s0, s1, s2, s3, s4, s5;
+  double mp, vd;
+  R s0, s1, s2, s3, s4, s5;
   OTM_DEV void begin(int64_t p) {
     mp = mass[p];
-    v = (R)vol[p];
+    vd = vol[p];
     s0 = sigma[p]; s1 = sigma[n_mp + p]; s2 = sigma[2 * n_mp + p];
     s3 = sigma[3 * n_mp + p]; s4 = sigma[4 * n_mp + p]; s5 = sigma[5 * n_mp + p];
   }
   OTM_DEV void operator()(int64_t q, double Nq, const double g[3]) {
     const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
-    contrib[pos_of[q]] = make_double4(Nq * mp, (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2)),
-                                      (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2)),
-                                      (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2)));
+    double c1, c2, c3;
+    pair_force<R>(vd, s0, s1, s2, s3, s4, s5, g0, g1, g2, c1, c2, c3);
+    contrib[pos_of[q]] = make_double4(Nq * mp, c1, c2, c3);
   }
 };
 
@@ -305,7 +312,40 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
     store_dn<DN>(dN, cap, off + q, g);
     sink(off + q, Nq, g);
   };
-  if constexpr (CACHED) {
+  if constexpr (CACHED && Sink::kBatch) {
+    // the pairs in two batches (a bound on the registers the contributions
+    // hold): N and grad N stored, then the batch's contributions inserted
+    constexpr int V = Sink::V, NB = (PPL + 1) / 2;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      int32_t I[NB];
+      bool use[NB];
+      double c[NB][V];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int k = b * NB + j;
+        const int q = k * G + lane;
+        use[j] = k < PPL && q < K;
+        I[j] = use[j] ? idx[off + q] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int k = b * NB + j;
+        if (k < PPL && use[j]) {
+          const int q = k * G + lane;
+          const double Nq = ek[k] * iz;
+          const double d3[3] = {pr.d[k][0], pr.d[k][1], pr.d[k][2]};
+          double g[3];
+          sym_mul_vec(Mi, d3, g);
+          g[0] *= -Nq; g[1] *= -Nq; g[2] *= -Nq;
+          Nout[off + q] = Nq;
+          store_dn<DN>(dN, cap, off + q, g);
+          sink.values(Nq, g, c[j]);
+        }
+      }
+      sink.insert(I, use, c);
+    }
+  } else if constexpr (CACHED) {
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
       const int q = k * G + lane;

@@ -9,13 +9,14 @@
 //   phase 2 (update): one lane per MP reads its sums back and runs the
 //     constitutive update, so the heavy scalar code uses every lane.
 // The node update also writes each node as one 64-byte record
-// (x, y, z, du_x, du_y, du_z, 0, 0) to the workspace: the MP pass fetches a
-// node with three 16-byte loads and the shape functions its position with
-// two, instead of six 8-byte loads from the SoA arrays.  The gathers are
-// limited by the texture addresser (one cache-line lookup per cycle), so the
-// number of load instructions per node is what counts.
+// (x, y, z, du_x, du_y, du_z, T, rate) to the workspace: the MP pass fetches
+// a node with three 16-byte loads (four with conduction) and the shape
+// functions its position with two, instead of one 8-byte load per value
+// from the SoA arrays.
 // Tensors near the identity are carried as deviations (F - 1, b^e - 1, dF - 1)
-// so that the float32 form of the mixed-precision mode keeps its accuracy.
+// so that their float32 storage in the mixed-precision mode keeps relative
+// accuracy.  The update itself computes in float64 in both modes (type Q);
+// only the stored tensors (R) differ.
 #include "constitutive.h"
 #include "launch.h"
 #include "otm_common.h"
@@ -200,13 +201,13 @@ constexpr int kSlots = 32 / kGather;   // pairs per lane loaded branch-free
 // sum_I N_Ip rate_I from the node records' (T_I, rate_I), kept in sums[13..16]
 // (past the slots that phase 2 parks values in); phase 2 adds
 // dt sum N rate to T_{n+1} and stores the flux -kappa grad T_p.
-template <typename R, bool COND>
+template <typename R, bool COND, typename Q = R>
 __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     const double4* __restrict__ nodes, int64_t n_nodes, int64_t n_mp,
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
     int64_t cap, const double* __restrict__ N, const R* __restrict__ dN,
     double* __restrict__ xp, double* __restrict__ vol, R* __restrict__ Fd, R* __restrict__ bed,
-    double* __restrict__ epsbar, double* __restrict__ T, R* __restrict__ sigma, Mat<R> M,
+    double* __restrict__ epsbar, double* __restrict__ T, R* __restrict__ sigma, Mat<Q> M,
     double* __restrict__ xp_prev, double* __restrict__ dFm1, int32_t* __restrict__ failed,
     double* __restrict__ clock, double dt, otm_diag* diag, double kappa,
     double* __restrict__ qflux) {
@@ -427,12 +428,12 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   for (int c = 0; c < 3; ++c) xp[c * n_mp + p] = xnew[c];
 
   // F - 1 <- H + Fd + H Fd
-  M3<R> h, fo, fn;
+  M3<Q> h, fo, fn;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      h.a[i][j] = (R)H.a[i][j];
+      h.a[i][j] = (Q)H.a[i][j];
       fo.a[i][j] = Fd[(3 * i + j) * n_mp + p];
     }
 #pragma unroll
@@ -445,69 +446,69 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Fd[(3 * i + j) * n_mp + p] = fn.a[i][j];
-  const R Jm1 = det_one_plus_minus_one(fn);
-  R J = R(1) + Jm1;
+  const Q Jm1 = det_one_plus_minus_one(fn);
+  Q J = Q(1) + Jm1;
 
-  S3<R> sig;
+  S3<Q> sig;
   if (M.model == OTM_NEOHOOKE) {
     // sigma = (mu/J)(b - 1) + (lambda ln J / J) 1, b - 1 = X + X^T + X X^T
     const int ii[6] = {0, 1, 2, 0, 1, 0}, jj[6] = {0, 1, 2, 1, 2, 2};
-    const R lnJ = m_log1p(Jm1);
+    const Q lnJ = m_log1p(Jm1);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       const int i = ii[c], j = jj[c];
-      const R bm1 = fn.a[i][j] + fn.a[j][i] +
+      const Q bm1 = fn.a[i][j] + fn.a[j][i] +
                     (fn.a[i][0] * fn.a[j][0] + fn.a[i][1] * fn.a[j][1] + fn.a[i][2] * fn.a[j][2]);
-      sig.v[c] = M.mu / J * bm1 + (c < 3 ? M.lamL * lnJ / J : R(0));
+      sig.v[c] = M.mu / J * bm1 + (c < 3 ? M.lamL * lnJ / J : Q(0));
     }
   } else if (was_failed) {
     // eroded: no stress; b^e, epsbar and T stay as they were (but for the
     // conduction increment: a failed MP still holds heat)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) sig.v[c] = R(0);
+    for (int c = 0; c < 6; ++c) sig.v[c] = Q(0);
     if constexpr (COND) T[p] = T[p] + dTc;
   } else {
     // trial elastic left Cauchy-Green tensor, as a deviation from 1:
     // b_tr - 1 = H + H^T + H H^T + (1+H) Bd (1+H)^T
-    S3<R> bd;
+    S3<Q> bd;
 #pragma unroll
     for (int c = 0; c < 6; ++c) bd.v[c] = bed[c * n_mp + p];
-    const M3<R> B = full(bd);
-    M3<R> HB;  // (1 + H) Bd
+    const M3<Q> B = full(bd);
+    M3<Q> HB;  // (1 + H) Bd
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         HB.a[i][j] = B.a[i][j] + h.a[i][0] * B.a[0][j] + h.a[i][1] * B.a[1][j] + h.a[i][2] * B.a[2][j];
-    S3<R> dtr;
+    S3<Q> dtr;
     const int ii[6] = {0, 1, 2, 0, 1, 0}, jj[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       const int i = ii[c], j = jj[c];
       // (1+H) Bd (1+H)^T = HB + HB H^T
-      const R hbh = HB.a[i][j] + HB.a[i][0] * h.a[j][0] + HB.a[i][1] * h.a[j][1] + HB.a[i][2] * h.a[j][2];
+      const Q hbh = HB.a[i][j] + HB.a[i][0] * h.a[j][0] + HB.a[i][1] * h.a[j][1] + HB.a[i][2] * h.a[j][2];
       dtr.v[c] = h.a[i][j] + h.a[j][i] +
                  (h.a[i][0] * h.a[j][0] + h.a[i][1] * h.a[j][1] + h.a[i][2] * h.a[j][2]) + hbh;
     }
-    R d[3], V[3][3];
+    Q d[3], V[3][3];
     jacobi_eig(dtr, d, V);
-    R e[3];
+    Q e[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) e[a] = R(0.5) * m_log1p(d[a]);
-    R tr = e[0] + e[1] + e[2];
-    R dev[3];
+    for (int a = 0; a < 3; ++a) e[a] = Q(0.5) * m_log1p(d[a]);
+    Q tr = e[0] + e[1] + e[2];
+    Q dev[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / R(3);
-    const R q_tr = R(2) * M.mu * m_sqrt(R(1.5) * (dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]));
+    for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / Q(3);
+    const Q q_tr = Q(2) * M.mu * m_sqrt(Q(1.5) * (dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]));
     const double ebn = epsbar[p], Tn = T[p];
-    R Ts = R(0);
+    Q Ts = Q(0);
     if (M.model == OTM_J2_JC) {
-      R t = (R)((Tn - (double)M.Tr) / ((double)M.Tm - (double)M.Tr));
-      Ts = t < R(0) ? R(0) : (t > R(1) ? R(1) : t);
+      Q t = (Q)((Tn - (double)M.Tr) / ((double)M.Tm - (double)M.Tr));
+      Ts = t < Q(0) ? Q(0) : (t > Q(1) ? Q(1) : t);
     }
-    R sy0, dsy0;
-    flow_stress(M, (R)ebn, R(0), Ts, sy0, dsy0);
-    R deps = R(0), c = R(0);
+    Q sy0, dsy0;
+    flow_stress(M, (Q)ebn, Q(0), Ts, sy0, dsy0);
+    Q deps = Q(0), c = Q(0);
     if (q_tr > sy0) {
       // the solve is the register peak of the kernel: park what it does not
       // use in LDS and read it back afterwards
@@ -519,28 +520,28 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
       }
       sums[12][tid] = (double)J;
       bool ok;
-      deps = solve_return(M, q_tr, (R)ebn, Ts, sy0, ok);
+      deps = solve_return(M, q_tr, (Q)ebn, Ts, sy0, ok);
       if (!ok) diag_fail(diag, OTM_ERR_RM_NOCONV, (uint64_t)p);
-      c = R(3) * M.mu * deps / q_tr;
+      c = Q(3) * M.mu * deps / q_tr;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) V[i][j] = (R)sums[3 * i + j][tid];
-        e[i] = (R)sums[9 + i][tid];
+        for (int j = 0; j < 3; ++j) V[i][j] = (Q)sums[3 * i + j][tid];
+        e[i] = (Q)sums[9 + i][tid];
       }
-      J = (R)sums[12][tid];
+      J = (Q)sums[12][tid];
       tr = e[0] + e[1] + e[2];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / R(3);
+      for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / Q(3);
     }
-    R bnew[3], tau[3];
+    Q bnew[3], tau[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const R ea = e[a] - c * dev[a];
-      bnew[a] = m_expm1(R(2) * ea);
-      tau[a] = (M.K * tr + R(2) * M.mu * (R(1) - c) * dev[a]) / J;
+      const Q ea = e[a] - c * dev[a];
+      bnew[a] = m_expm1(Q(2) * ea);
+      tau[a] = (M.K * tr + Q(2) * M.mu * (Q(1) - c) * dev[a]) / J;
     }
-    const S3<R> bn = spectral_compose(V, bnew);
+    const S3<Q> bn = spectral_compose(V, bnew);
     sig = spectral_compose(V, tau);
 #pragma unroll
     for (int k = 0; k < 6; ++k) bed[k * n_mp + p] = bn.v[k];
@@ -548,7 +549,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     epsbar[p] = eb_new;
     double T_new = Tn;
     if (M.model == OTM_J2_JC) {
-      T_new = (Tn + dTc) + (double)(M.chi * (R(1) - c) * q_tr * deps / M.rhoCp);
+      T_new = (Tn + dTc) + (double)(M.chi * (Q(1) - c) * q_tr * deps / M.rhoCp);
       T[p] = T_new;
     }
     if (failed != nullptr && eb_new > 0.0) {
@@ -568,7 +569,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
       if (eb_new >= ef) {
         failed[p] = 1;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) sig.v[k] = R(0);
+        for (int k = 0; k < 6; ++k) sig.v[k] = Q(0);
       }
     }
   }
@@ -599,18 +600,17 @@ void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
                                    st.qflux);
   };
   const bool cond = p.kappa > 0.0;
+  const auto m = make_mat<double>(p, dt);  // float64 arithmetic in both modes
   if (st.precision == OTM_FP64) {
-    auto m = make_mat<double>(p, dt);
     double *fd = (double*)st.Fd, *bd = (double*)st.bed, *sg = (double*)st.sigma;
     const double* dn = (const double*)st.dN;
     if (cond) run(k_mp_update<double, true>, dn, fd, bd, sg, m);
     else run(k_mp_update<double, false>, dn, fd, bd, sg, m);
   } else {
-    auto m = make_mat<float>(p, dt);
     float *fd = (float*)st.Fd, *bd = (float*)st.bed, *sg = (float*)st.sigma;
     const float* dn = (const float*)st.dN;
-    if (cond) run(k_mp_update<float, true>, dn, fd, bd, sg, m);
-    else run(k_mp_update<float, false>, dn, fd, bd, sg, m);
+    if (cond) run(k_mp_update<float, true, double>, dn, fd, bd, sg, m);
+    else run(k_mp_update<float, false, double>, dn, fd, bd, sg, m);
   }
 }
 

@@ -58,6 +58,21 @@ OTM_DEV uint32_t xcd_block() {
   return x * q + (x < r ? x : r) + b / 8u;
 }
 
+// -------------------------------------------------------- pair force
+// Internal-force contribution -v sigma grad N_Ip of one pair (the nodal
+// residual, Sec. 2.1), sigma in Voigt order (xx yy zz xy yz xz).  sigma and
+// grad N come in their stored type (float32 in the mixed-precision mode);
+// products and sums are formed in float64.
+template <typename R>
+OTM_DEV void pair_force(double v, R s0, R s1, R s2, R s3, R s4, R s5, R g0, R g1, R g2,
+                        double& c1, double& c2, double& c3) {
+  const double h0 = g0, h1 = g1, h2 = g2;
+  const double t0 = s0, t1 = s1, t2 = s2, t3 = s3, t4 = s4, t5 = s5;
+  c1 = -v * (t0 * h0 + t3 * h1 + t5 * h2);
+  c2 = -v * (t3 * h0 + t1 * h1 + t4 * h2);
+  c3 = -v * (t5 * h0 + t4 * h1 + t2 * h2);
+}
+
 // ------------------------------------------------------------- reductions
 // All-reduce over aligned groups of G <= 16 lanes with DPP row moves (no LDS
 // round trip): row_ror:8 folds the two halves of a 16-lane row, then
@@ -280,23 +295,54 @@ OTM_DEV void table_clear(NodeTableV<V>& t, int tid, int nthreads) {
   }
 }
 
+// Insertion of NB items per lane at once: every item's first probe (a
+// compare-and-swap on its hash slot) is issued before any result is
+// examined, so the LDS round trips overlap; an item whose slot holds another
+// node probes on, one slot at a time (rare at the table's load).  Items with
+// use[k] false are skipped.  The sums are the same as NB table_insert calls.
+template <int V, int NB>
+OTM_DEV void table_insert_batch(NodeTableV<V>& t, const int32_t (&I)[NB], const bool (&use)[NB],
+                                const double (&c)[NB][V], const NodeDst<V>& dst) {
+  uint32_t h[NB];
+  int32_t prev[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    h[k] = ((uint32_t)I[k] * 2654435761u) >> (32 - kTableBits);
+    prev[k] = use[k] ? atomicCAS(&t.keys[h[k]], -1, I[k]) : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (!use[k]) continue;
+    int slot = -1;
+    if (prev[k] == -1 || prev[k] == I[k]) {
+      slot = (int)h[k];
+    } else {
+#pragma unroll 1
+      for (int probe = 1; probe < 32; ++probe) {
+        const uint32_t hh = (h[k] + (uint32_t)probe) & (kTableSlots - 1);
+        const int32_t pv = atomicCAS(&t.keys[hh], -1, I[k]);
+        if (pv == -1 || pv == I[k]) { slot = (int)hh; break; }
+      }
+    }
+    if (slot >= 0) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) atomicAdd(&t.vals[v][slot], c[k][v]);
+    } else {  // crowded table: straight to memory
+#pragma unroll
+      for (int v = 0; v < V; ++v) atomicAdd(&dst.d[v][I[k]], c[k][v]);
+    }
+  }
+}
+
 template <int V>
 OTM_DEV void table_insert(NodeTableV<V>& t, int32_t I, const double (&c)[V],
                           const NodeDst<V>& dst) {
-  uint32_t h = ((uint32_t)I * 2654435761u) >> (32 - kTableBits);
-  int slot = -1;
-  for (int probe = 0; probe < 32; ++probe) {
-    const int32_t prev = atomicCAS(&t.keys[h], -1, I);
-    if (prev == -1 || prev == I) { slot = (int)h; break; }
-    h = (h + 1) & (kTableSlots - 1);
-  }
-  if (slot >= 0) {
+  const int32_t key[1] = {I};
+  const bool use[1] = {true};
+  double cc[1][V];
 #pragma unroll
-    for (int k = 0; k < V; ++k) atomicAdd(&t.vals[k][slot], c[k]);
-  } else {  // crowded table: straight to memory
-#pragma unroll
-    for (int k = 0; k < V; ++k) atomicAdd(&dst.d[k][I], c[k]);
-  }
+  for (int v = 0; v < V; ++v) cc[0][v] = c[v];
+  table_insert_batch<V, 1>(t, key, use, cc, dst);
 }
 
 OTM_DEV void table_insert(NodeTable& t, int32_t I, double c0, double c1, double c2, double c3,

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_seg_contrib(
   if (p >= n_mp) return;
   if (offsets[n_mp] > cap) return;
   const double mp = mass[p];
-  const R v = (R)vol[p];
+  const double v = vol[p];
   const R s0 = sigma[p], s1 = sigma[n_mp + p], s2 = sigma[2 * n_mp + p];
   const R s3 = sigma[3 * n_mp + p], s4 = sigma[4 * n_mp + p], s5 = sigma[5 * n_mp + p];
   StabMP sm;
@@ -232,9 +232,8 @@ __global__ __launch_bounds__(256) void k_seg_contrib(
   for (int64_t q = offsets[p] + lane; q < offsets[p + 1]; q += kScLanes) {
     const R g0 = dN[q], g1 = dN[cap + q], g2 = dN[2 * cap + q];
     const double Nq = N[q];
-    double c1 = (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2));
-    double c2 = (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2));
-    double c3 = (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2));
+    double c1, c2, c3;
+    pair_force<R>(v, s0, s1, s2, s3, s4, s5, g0, g1, g2, c1, c2, c3);
     if constexpr (STAB) stab_add(sb, sm, idx[q], Nq, c1, c2, c3);
     contrib[pos_of[q]] = make_double4(Nq * mp, c1, c2, c3);
   }
@@ -330,7 +329,7 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
     const int64_t p = base + r * (256 / kAsmLanes) + tid / kAsmLanes;
     if (!ok || p >= n_mp) continue;
     const double mp = mass[p];
-    const R v = (R)vol[p];
+    const double v = vol[p];
     const R s0 = sigma[p], s1 = sigma[n_mp + p], s2 = sigma[2 * n_mp + p];
     const R s3 = sigma[3 * n_mp + p], s4 = sigma[4 * n_mp + p], s5 = sigma[5 * n_mp + p];
     const int64_t o0 = offsets[p], o1 = offsets[p + 1];
@@ -345,9 +344,7 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
       const R g0 = dN[q], g1 = dN[cap + q], g2 = dN[2 * cap + q];
       const double Nq = N[q];
       c0 = Nq * mp;
-      c1 = (double)(-v * (s0 * g0 + s3 * g1 + s5 * g2));
-      c2 = (double)(-v * (s3 * g0 + s1 * g1 + s4 * g2));
-      c3 = (double)(-v * (s5 * g0 + s4 * g1 + s2 * g2));
+      pair_force<R>(v, s0, s1, s2, s3, s4, s5, g0, g1, g2, c1, c2, c3);
       if constexpr (STAB) stab_add(sb, sm, I, Nq, c1, c2, c3);
     };
     const int K = (int)(o1 - o0);

@@ -70,11 +70,11 @@ def test_eroded_small_cut_fp64(eroded_cut, scatter):
 
 
 def test_eroded_small_cut_mixed(eroded_cut):
-    """Mixed precision (F, b^e and the stress compacted as float32): the same
-    MPs removed and every field within 1e-5 of the float64 oracle except the
-    per-step increment du, a difference of nearly equal positions, whose
-    float32 force error is divided by the small lumped masses of the nodes on
-    the freshly freed surface (measured 2.7e-5; asserted 5e-5)."""
+    """Mixed precision (F, b^e and the stress stored and compacted as
+    float32): the same MPs removed and every field within 1e-5 of the float64
+    oracle, the increment du included, although the nodes of the freshly
+    freed surface carry a few per cent of the median lumped mass, which
+    divides the force's rounding error."""
     w, p, st, orig, removed = eroded_cut
     print("eroded small cut, mixed", flush=True)
     sim, got = _run_gpu(w, "atomic", precision="mixed")
@@ -84,7 +84,7 @@ def test_eroded_small_cut_mixed(eroded_cut):
     errs = compare(gpu_fields(g, w.x_nodes, w.x_mp[orig], p["T_r"]),
                    oracle_fields(st, w.x_nodes, w.x_mp[orig], p["T_r"]))
     print("mixed, removed", removed, json.dumps({k: float(v) for k, v in errs.items()}))
-    bad = {k: v for k, v in errs.items() if not v < (5e-5 if k == "du" else 1e-5)}
+    bad = {k: v for k, v in errs.items() if not v < 1e-5}
     assert not bad, bad
 
 
