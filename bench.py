@@ -8,12 +8,14 @@ lists rebuilt every step.  A step is one full pass of the hot path: node
 update, MP update (kinematics + return map), linked-cell search, LME shape
 functions and nodal force assembly.
 
-The main line is float64 with atomic assembly; the mixed-precision mode and
-the deterministic (segmented) assembly are timed the same way and reported
-under "variants", as is the step with the stabilisation term (eps = mu h^2),
-together with the Taylor rod and the chip-formation workpiece at the paper's
-own sizes (27,840 and 108,000 MPs, 2000 steps each; eager and
-graph-replayed) beside the paper's per-step times.  Inputs are resident in HBM before the timed region; the
+The main line is float64 with atomic assembly; the two mixed-precision modes
+(float32 return map and force products; float32 storage with float64
+arithmetic) and the deterministic (segmented) assembly are timed the same way
+and reported under "variants", as is the step with the stabilisation term
+(eps = mu h^2), together with the Taylor rod and the chip-formation workpiece
+at the paper's own sizes (27,840 and 108,000 MPs, 2000 steps each; eager and
+graph-replayed) beside the paper's per-step times, and the 6.1M-MP cutting
+workload with erosion and heat conduction.  Inputs are resident in HBM before the timed region; the
 timed region is bracketed by device synchronisation and HIP events on the
 stream the kernels run on.  Per-phase durations come from events recorded by
 the library between its kernels (otm_step_profiled).
@@ -452,9 +454,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="taylor_rod")
     ap.add_argument("--variants",
-                    default="mixed,segmented,stabilised,paper_rod,cutting,cutting_5m",
-                    help="extra timed variants: mixed, segmented, stabilised, paper_rod, "
-                         "cutting, cutting_5m (comma separated, or none)")
+                    default="mixed,mixed_storage,segmented,stabilised,paper_rod,cutting,"
+                            "cutting_5m",
+                    help="extra timed variants: mixed, mixed_storage, segmented, stabilised, "
+                         "paper_rod, cutting, cutting_5m (comma separated, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -497,7 +500,7 @@ def main():
                 torch.cuda.synchronize()
                 torch.cuda.empty_cache()
             continue
-        prec = "mixed" if v == "mixed" else "fp64"
+        prec = v if v in ("mixed", "mixed_storage") else "fp64"
         scat = "segmented" if v == "segmented" else "atomic"
         over = {}
         if v == "stabilised":       # the stabilisation term with eps = mu h^2
@@ -514,7 +517,7 @@ def main():
                            phase_ms={k: round(x, 4) for k, x in pm.items()})
         if over:
             variants[v]["eps_stab"] = over["eps_stab"]
-        if prec == "mixed":
+        if prec != "fp64":
             nb = mp_pass_bytes(w.n_mp, w.n_nodes, r["pairs"], "mixed", w.material.model)
             variants[v]["mp_pass_roofline"] = roofline_entry(nb, r["phase_ms"]["mp_update"])
 

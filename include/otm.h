@@ -63,10 +63,13 @@ enum {
 };
 
 /* arithmetic of the step */
-enum { OTM_FP64 = 0,     /* everything in float64 */
-       OTM_MIXED = 1 };  /* return map, stress, F, b^e, grad N and force
-                            products in float32; LME Newton, N, positions,
-                            volumes, masses and nodal accumulation in float64 */
+enum { OTM_FP64 = 0,            /* everything in float64 */
+       OTM_MIXED = 1,           /* return map, stress, F, b^e, grad N and force
+                                   products in float32; LME Newton, N,
+                                   positions, volumes, masses and nodal
+                                   accumulation in float64 */
+       OTM_MIXED_STORAGE = 2 }; /* F, b^e, stress and grad N stored in float32
+                                   (as OTM_MIXED), all arithmetic in float64 */
 /* nodal force assembly */
 enum { OTM_SCATTER_ATOMIC = 0,      /* contributions summed per node in LDS
                                        by each workgroup, then float64 atomic
@@ -160,7 +163,8 @@ typedef struct otm_params {
 typedef struct otm_state {
   int64_t n_nodes, n_mp;
   int64_t pair_capacity;  /* length of nbr_idx and N; dN is [3][pair_capacity] */
-  int32_t precision;      /* OTM_FP64 or OTM_MIXED: types of the void* fields */
+  int32_t precision;      /* OTM_FP64, OTM_MIXED or OTM_MIXED_STORAGE: types of
+                             the void* fields (float in both mixed modes) */
   int32_t pad0;
   /* nodes */
   double* x;              /* [3][n_nodes] current positions */
@@ -172,7 +176,7 @@ typedef struct otm_state {
   double* vol;            /* [n_mp] current volume */
   const double* mass;     /* [n_mp] mass (constant; otm_erode compacts it) */
   double* lam;            /* [3][n_mp] LME multiplier (warm start) */
-  void* Fd;               /* [9][n_mp] F - 1 (double, or float in OTM_MIXED) */
+  void* Fd;               /* [9][n_mp] F - 1 (double, or float in the mixed modes) */
   void* bed;              /* [6][n_mp] b^e - 1 (double / float) */
   double* epsbar;         /* [n_mp] equivalent plastic strain */
   double* T;              /* [n_mp] temperature */
@@ -259,7 +263,7 @@ otm_status otm_build_neighbors(int64_t n_nodes, const double* x_nodes, int64_t n
  * cold start), stopping at |sum N_I d_I|_2 <= tol.  Gradients
  * dN_I = -N_I J^{-1} d_I with J = sum N_I d_I d_I^T - r r^T (the derivative of
  * the consistency condition; not printed in the paper).  Always float64
- * arithmetic; dN is written as double (OTM_FP64) or float (OTM_MIXED) with
+ * arithmetic; dN is written as double (OTM_FP64) or float (either mixed mode) with
  * component stride pair_capacity.  Non-convergence is recorded in diag.
  */
 otm_status otm_lme_shape(int64_t n_nodes, const double* x_nodes, int64_t n_mp,

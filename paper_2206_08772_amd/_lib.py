@@ -15,7 +15,7 @@ OTM_OK, OTM_ERR_ARG, OTM_ERR_CAPACITY, OTM_ERR_LME_NOCONV = 0, -1, -2, -3
 OTM_ERR_RM_NOCONV, OTM_ERR_INVERTED, OTM_ERR_NONFINITE, OTM_ERR_HIP = -4, -5, -6, -7
 OTM_ERR_SUPPORT, OTM_ERR_SCRATCH = -8, -9
 OTM_STATIC_SCRATCH_BYTES = 64 << 20
-OTM_FP64, OTM_MIXED = 0, 1
+OTM_FP64, OTM_MIXED, OTM_MIXED_STORAGE = 0, 1, 2
 OTM_SCATTER_ATOMIC, OTM_SCATTER_SEGMENTED = 0, 1
 OTM_NEOHOOKE, OTM_J2_JC, OTM_J2_LINEAR = 0, 1, 2
 

@@ -149,7 +149,9 @@ static otm_status check_state(const otm_state* st) {
   if (st->n_nodes < 0 || st->n_mp < 0 || st->pair_capacity < 0) return OTM_ERR_ARG;
   if (st->pair_capacity >= (int64_t(1) << 31)) return OTM_ERR_ARG;  // int32 pair ids
   if (st->n_nodes >= (int64_t(1) << 31) || st->n_mp >= (int64_t(1) << 31)) return OTM_ERR_ARG;
-  if (st->precision != OTM_FP64 && st->precision != OTM_MIXED) return OTM_ERR_ARG;
+  if (st->precision != OTM_FP64 && st->precision != OTM_MIXED &&
+      st->precision != OTM_MIXED_STORAGE)
+    return OTM_ERR_ARG;
   const size_t rs = st->precision == OTM_FP64 ? 8 : 4;
   if (!dev_ok(st->x, 8) || !dev_ok(st->du, 8) || !dev_ok(st->m, 8) || !dev_ok(st->f, 8))
     return OTM_ERR_ARG;
@@ -304,7 +306,8 @@ otm_status otm_lme_shape(int64_t n_nodes, const double* x_nodes, int64_t n_mp,
                          hipStream_t s) {
   if (n_nodes < 0 || n_mp < 0 || pair_capacity < 0) return OTM_ERR_ARG;
   if (!(beta > 0) || !(tol > 0) || max_iter < 1) return OTM_ERR_ARG;
-  if (precision != OTM_FP64 && precision != OTM_MIXED) return OTM_ERR_ARG;
+  if (precision != OTM_FP64 && precision != OTM_MIXED && precision != OTM_MIXED_STORAGE)
+    return OTM_ERR_ARG;
   const size_t rs = precision == OTM_FP64 ? 8 : 4;
   if (n_mp == 0) return OTM_OK;
   if (!dev_ok(x_nodes, 8) || !dev_ok(x_mp, 8) || !dev_ok(nbr_offsets, 8) || !dev_ok(lam, 8))

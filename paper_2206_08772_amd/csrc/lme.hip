@@ -1,15 +1,16 @@
 // Local max-ent shape functions (Sec. 2.3) by a per-material-point damped
 // Newton solve for the Lagrange multiplier, in float64.
 //
-// A group of G = 4 lanes works on one MP; each lane keeps up to PPL = 10 of
-// the MP's pairs in registers (offset d = x_p - x_I and the prior
-// -beta |d|^2), so one Newton evaluation costs one exp per pair and 10 group
-// reductions (Z, r, S = sum e d d^T) of two DPP stages each.  The 3x3 solve
-// is repeated in every lane of the group, so the group never diverges.  Few
-// lanes per MP keep the per-MP work (reductions, solve, line search) from
-// being repeated across many lanes, which is what bounds this kernel: it is
-// float64 ALU work, not memory traffic.  MPs with more than 40 pairs take the
-// same iteration with pairs re-read from memory.
+// A group of G = 4 lanes works on one MP; each lane keeps up to PPL = 8 of
+// the MP's pairs in registers (offset d = x_p - x_I), so one Newton
+// evaluation costs one exp per pair and 10 group reductions (Z, r,
+// S = sum e d d^T) of two DPP stages each.  The 3x3 solve is repeated in
+// every lane of the group, so the group never diverges.  Few lanes per MP
+// keep the per-MP work (reductions, solve, line search) from being repeated
+// across many lanes; the kernel is bound by the latency of that per-MP chain
+// at two waves per SIMD, not by memory traffic.  The supports of the
+// lattice-like bodies hold 20-33 nodes (radius 1.86 h); MPs with more than
+// 32 pairs take the same iteration with pairs re-read from memory.
 //
 // Newton reading (the paper gives none): start from the previous multiplier;
 // step -J^{-1} r with J = sum N d d^T - r r^T; Armijo backtracking on log Z
@@ -67,9 +68,19 @@ struct Eval {
 
 template <int G, int PPL, bool CACHED>
 struct Pairs {
-  // cached offsets and priors (CACHED only)
+  // cached offsets x_p - x_I (CACHED only); the prior -beta |d|^2 is
+  // recomputed from them at each evaluation, which costs fewer cycles than
+  // the registers it would hold
   double d[CACHED ? PPL : 1][3];
-  double prior[CACHED ? PPL : 1];
+};
+
+// A row of the support lists fetched ahead of its solve: its start, length
+// and (for rows of at most G * PPL pairs) this lane's node ids.
+template <int PPL>
+struct RowIds {
+  int64_t off;
+  int K;
+  int32_t I[PPL];
 };
 
 template <int G, int PPL, bool CACHED>
@@ -82,7 +93,9 @@ OTM_DEV void lme_eval(const Pairs<G, PPL, CACHED>& pr, int lane, int K, int64_t 
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
       if (k * G + lane < K) {
-        ek[k] = pr.prior[k] + (lam[0] * pr.d[k][0] + lam[1] * pr.d[k][1] + lam[2] * pr.d[k][2]);
+        const double prior = -beta * ((pr.d[k][0] * pr.d[k][0] + pr.d[k][1] * pr.d[k][1]) +
+                                      pr.d[k][2] * pr.d[k][2]);
+        ek[k] = prior + (lam[0] * pr.d[k][0] + lam[1] * pr.d[k][1] + lam[2] * pr.d[k][2]);
         fm = fmax(fm, ek[k]);
       }
     }
@@ -160,7 +173,7 @@ struct NoSink {
 // N m_p T_p and v_p q_p . grad N (float64, grad N rounded the same way).
 // begin() loads the MP's mass, volume, stress (and temperature and flux)
 // once the Newton solve is done.
-template <typename R, bool HEAT>
+template <typename R, bool HEAT, typename Q>
 struct AsmSink {
   static constexpr bool kBatch = true;  // the cached path inserts a batch of pairs at once
   static constexpr int V = HEAT ? 6 : 4;
@@ -188,7 +201,7 @@ struct AsmSink {
   OTM_DEV void values(double Nq, const double g[3], double (&c)[V]) const {
     const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
     c[0] = Nq * mp;
-    pair_force<R>(vd, s0, s1, s2, s3, s4, s5, g0, g1, g2, c[1], c[2], c[3]);
+    pair_force<Q>(vd, s0, s1, s2, s3, s4, s5, g0, g1, g2, c[1], c[2], c[3]);
     if constexpr (HEAT) {
       c[4] = c[0] * Tp;
       c[5] = vd * ((q0 * (double)g0 + q1 * (double)g1) + q2 * (double)g2);
@@ -208,7 +221,7 @@ struct AsmSink {
 // Fused contribution store of the deterministic assembly: the pair's four
 // contributions (the standalone contribution kernel's arithmetic) go to its
 // place in the node-sorted order, where each node later sums them in order.
-template <typename R>
+template <typename R, typename Q>
 struct SegSink {
   static constexpr bool kBatch = false;
   const double* vol;
@@ -228,19 +241,40 @@ struct SegSink {
   OTM_DEV void operator()(int64_t q, double Nq, const double g[3]) {
     const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
     double c1, c2, c3;
-    pair_force<R>(vd, s0, s1, s2, s3, s4, s5, g0, g1, g2, c1, c2, c3);
+    pair_force<Q>(vd, s0, s1, s2, s3, s4, s5, g0, g1, g2, c1, c2, c3);
     contrib[pos_of[q]] = make_double4(Nq * mp, c1, c2, c3);
   }
 };
 
-template <int G, int PPL, bool CACHED, typename DN, class Sink>
+// Fetch this lane's node ids of a row whose start and length are set (rows
+// longer than G * PPL take the uncached path, which reads its ids itself).
+template <int G, int PPL>
+OTM_DEV void load_row_ids(RowIds<PPL>& r, const int32_t* __restrict__ idx, int lane) {
+  if (r.K > 0 && r.K <= G * PPL) {
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      const int q = k * G + lane;
+      r.I[k] = idx[r.off + (q < r.K ? q : 0)];
+    }
+  }
+}
+
+struct NoMid {
+  OTM_DEV void operator()() const {}
+};
+
+// One MP's solve.  ``pre`` (nullable) holds the row fetched ahead; ``mid``
+// runs once the Newton iteration has ended (the fused kernel fetches the
+// next round's node ids there, so they arrive while this MP finishes).
+template <int G, int PPL, bool CACHED, typename DN, class Sink, class Mid = NoMid>
 OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, const double* __restrict__ xp,
                        const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
                        int64_t cap, double beta, double tol, int max_iter,
                        double* __restrict__ lam_io, double* __restrict__ Nout,
-                       DN* __restrict__ dN, otm_diag* diag, Sink& sink) {
-  const int64_t off = offsets[p];
-  const int K = (int)(offsets[p + 1] - off);
+                       DN* __restrict__ dN, otm_diag* diag, Sink& sink,
+                       const RowIds<PPL>* pre = nullptr, Mid mid = Mid{}) {
+  const int64_t off = pre != nullptr ? pre->off : offsets[p];
+  const int K = pre != nullptr ? pre->K : (int)(offsets[p + 1] - off);
   const double px = xp[p], py = xp[n_mp + p], pz = xp[2 * n_mp + p];
   Pairs<G, PPL, CACHED> pr;
   if constexpr (CACHED) {
@@ -250,14 +284,12 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         const int q = k * G + lane;
-        const int32_t I = idx[off + (q < K ? q : 0)];
+        const int32_t I = pre != nullptr ? pre->I[k] : idx[off + (q < K ? q : 0)];
         double nx, ny, nz;
         node_xyz(ns, I, nx, ny, nz);
         pr.d[k][0] = px - nx;
         pr.d[k][1] = py - ny;
         pr.d[k][2] = pz - nz;
-        pr.prior[k] = -beta * ((pr.d[k][0] * pr.d[k][0] + pr.d[k][1] * pr.d[k][1]) +
-                               pr.d[k][2] * pr.d[k][2]);
       }
     }
   }
@@ -294,6 +326,7 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
       t *= 0.5;
     }
   }
+  mid();
   if (lane == 0) {
     lam_io[p] = lam[0]; lam_io[n_mp + p] = lam[1]; lam_io[2 * n_mp + p] = lam[2];
     if (!converged) diag_fail(diag, OTM_ERR_LME_NOCONV, (uint64_t)p);
@@ -326,7 +359,7 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
         const int k = b * NB + j;
         const int q = k * G + lane;
         use[j] = k < PPL && q < K;
-        I[j] = use[j] ? idx[off + q] : 0;
+        I[j] = !use[j] ? 0 : (pre != nullptr ? pre->I[k < PPL ? k : 0] : idx[off + q]);
       }
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
@@ -392,7 +425,7 @@ __global__ __launch_bounds__(256) void k_lme(NodeSrc ns, int64_t n_mp, const dou
 // workgroup, so the barriers around a flush are reached by all of them.
 constexpr int kLmeAsmBlocks = 512;
 
-template <int G, int PPL, typename DN, bool HEAT>
+template <int G, int PPL, typename DN, bool HEAT, typename Q>
 __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
                                                  const double* __restrict__ xp,
                                                  const int64_t* __restrict__ offsets,
@@ -403,7 +436,7 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
                                                  otm_diag* diag, AsmIn a) {
   constexpr int per_round = 256 / G;
   constexpr int flush_rounds = 512 / per_round;
-  using Sink = AsmSink<DN, HEAT>;
+  using Sink = AsmSink<DN, HEAT, Q>;
   __shared__ NodeTableV<Sink::V> table;
   const int tid = threadIdx.x;
   table_clear(table, tid, 256);
@@ -423,18 +456,36 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
     dst.d[5] = a.heat + a.n_nodes;
   }
   Sink sink{&table, idx, a.vol, a.mass, (const DN*)a.sigma, a.T, a.q, dst, n_mp};
+  // rows are fetched one round ahead: the next round's start and length at
+  // the top of a round, its node ids once this round's Newton solve is done,
+  // so a round begins with its node gathers instead of two dependent loads
+  auto row_at = [&](int64_t q, RowIds<PPL>& rw) {
+    rw.off = 0;
+    rw.K = 0;
+    if (ok && q < hi) {
+      rw.off = offsets[q];
+      rw.K = (int)(offsets[q + 1] - rw.off);
+    }
+  };
+  RowIds<PPL> cur, nxt;
+  row_at(lo + tid / G, cur);
+  load_row_ids<G, PPL>(cur, idx, lane);
   int r = 0;
   for (int64_t p0 = lo; p0 < hi; p0 += per_round) {
     const int64_t p = p0 + tid / G;
+    row_at(p + per_round, nxt);
+    auto mid = [&]() { load_row_ids<G, PPL>(nxt, idx, lane); };
     if (ok && p < hi) {
-      const int K = (int)(offsets[p + 1] - offsets[p]);
-      if (K <= G * PPL)
+      if (cur.K <= G * PPL)
         lme_point<G, PPL, true, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
-                                    max_iter, lam, N, dN, diag, sink);
+                                    max_iter, lam, N, dN, diag, sink, &cur, mid);
       else
         lme_point<G, PPL, false, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
-                                     max_iter, lam, N, dN, diag, sink);
+                                     max_iter, lam, N, dN, diag, sink, &cur, mid);
+    } else {
+      mid();
     }
+    cur = nxt;
     if (++r == flush_rounds) {
       r = 0;
       __syncthreads();
@@ -453,7 +504,7 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
                 const AsmIn* fused, const SegIn* seg) {
   if (n_mp <= 0) return;
   const NodeSrc ns{x_nodes, packed, n_nodes};
-  constexpr int G = 4, PPL = 10;
+  constexpr int G = 4, PPL = 8;
   if (fused != nullptr) {
     auto run = [&](auto kernel, auto* dn) {
       kernel<<<kLmeAsmBlocks, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity,
@@ -461,11 +512,14 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
     };
     const bool heat = fused->heat != nullptr;
     if (precision == OTM_FP64) {
-      if (heat) run(k_lme_asm<G, PPL, double, true>, (double*)dN);
-      else run(k_lme_asm<G, PPL, double, false>, (double*)dN);
+      if (heat) run(k_lme_asm<G, PPL, double, true, double>, (double*)dN);
+      else run(k_lme_asm<G, PPL, double, false, double>, (double*)dN);
+    } else if (precision == OTM_MIXED) {
+      if (heat) run(k_lme_asm<G, PPL, float, true, float>, (float*)dN);
+      else run(k_lme_asm<G, PPL, float, false, float>, (float*)dN);
     } else {
-      if (heat) run(k_lme_asm<G, PPL, float, true>, (float*)dN);
-      else run(k_lme_asm<G, PPL, float, false>, (float*)dN);
+      if (heat) run(k_lme_asm<G, PPL, float, true, double>, (float*)dN);
+      else run(k_lme_asm<G, PPL, float, false, double>, (float*)dN);
     }
     return;
   }
@@ -476,18 +530,21 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
   };
   if (precision == OTM_FP64) {
     if (seg != nullptr)
-      run(SegSink<double>{seg->vol, seg->mass, (const double*)seg->sigma, seg->pos_of,
-                          seg->contrib, n_mp},
+      run(SegSink<double, double>{seg->vol, seg->mass, (const double*)seg->sigma, seg->pos_of,
+                                  seg->contrib, n_mp},
           (double*)dN);
     else
       run(NoSink{}, (double*)dN);
+  } else if (seg != nullptr && precision == OTM_MIXED) {
+    run(SegSink<float, float>{seg->vol, seg->mass, (const float*)seg->sigma, seg->pos_of,
+                              seg->contrib, n_mp},
+        (float*)dN);
+  } else if (seg != nullptr) {
+    run(SegSink<float, double>{seg->vol, seg->mass, (const float*)seg->sigma, seg->pos_of,
+                               seg->contrib, n_mp},
+        (float*)dN);
   } else {
-    if (seg != nullptr)
-      run(SegSink<float>{seg->vol, seg->mass, (const float*)seg->sigma, seg->pos_of,
-                         seg->contrib, n_mp},
-          (float*)dN);
-    else
-      run(NoSink{}, (float*)dN);
+    run(NoSink{}, (float*)dN);
   }
 }
 

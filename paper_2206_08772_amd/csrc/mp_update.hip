@@ -14,9 +14,10 @@
 // functions its position with two, instead of one 8-byte load per value
 // from the SoA arrays.
 // Tensors near the identity are carried as deviations (F - 1, b^e - 1, dF - 1)
-// so that their float32 storage in the mixed-precision mode keeps relative
-// accuracy.  The update itself computes in float64 in both modes (type Q);
-// only the stored tensors (R) differ.
+// so that their float32 forms keep relative accuracy.  The stored tensors
+// have type R and the update computes in type Q: float64 / float64 in
+// OTM_FP64, float32 / float32 in OTM_MIXED, float32 / float64 in
+// OTM_MIXED_STORAGE.
 #include "constitutive.h"
 #include "launch.h"
 #include "otm_common.h"
@@ -600,15 +601,22 @@ void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
                                    st.qflux);
   };
   const bool cond = p.kappa > 0.0;
-  const auto m = make_mat<double>(p, dt);  // float64 arithmetic in both modes
   if (st.precision == OTM_FP64) {
+    const auto m = make_mat<double>(p, dt);
     double *fd = (double*)st.Fd, *bd = (double*)st.bed, *sg = (double*)st.sigma;
     const double* dn = (const double*)st.dN;
     if (cond) run(k_mp_update<double, true>, dn, fd, bd, sg, m);
     else run(k_mp_update<double, false>, dn, fd, bd, sg, m);
-  } else {
-    float *fd = (float*)st.Fd, *bd = (float*)st.bed, *sg = (float*)st.sigma;
-    const float* dn = (const float*)st.dN;
+    return;
+  }
+  float *fd = (float*)st.Fd, *bd = (float*)st.bed, *sg = (float*)st.sigma;
+  const float* dn = (const float*)st.dN;
+  if (st.precision == OTM_MIXED) {  // the return map in float32
+    const auto m = make_mat<float>(p, dt);
+    if (cond) run(k_mp_update<float, true, float>, dn, fd, bd, sg, m);
+    else run(k_mp_update<float, false, float>, dn, fd, bd, sg, m);
+  } else {  // float32 storage, float64 arithmetic
+    const auto m = make_mat<double>(p, dt);
     if (cond) run(k_mp_update<float, true, double>, dn, fd, bd, sg, m);
     else run(k_mp_update<float, false, double>, dn, fd, bd, sg, m);
   }

@@ -61,16 +61,18 @@ OTM_DEV uint32_t xcd_block() {
 // -------------------------------------------------------- pair force
 // Internal-force contribution -v sigma grad N_Ip of one pair (the nodal
 // residual, Sec. 2.1), sigma in Voigt order (xx yy zz xy yz xz).  sigma and
-// grad N come in their stored type (float32 in the mixed-precision mode);
-// products and sums are formed in float64.
-template <typename R>
+// grad N come in their stored type R; the products and sums are formed in
+// Q (float32 in OTM_MIXED, float64 in the other modes) and handed on as
+// float64 for the nodal accumulation.
+template <typename Q, typename R>
 OTM_DEV void pair_force(double v, R s0, R s1, R s2, R s3, R s4, R s5, R g0, R g1, R g2,
                         double& c1, double& c2, double& c3) {
-  const double h0 = g0, h1 = g1, h2 = g2;
-  const double t0 = s0, t1 = s1, t2 = s2, t3 = s3, t4 = s4, t5 = s5;
-  c1 = -v * (t0 * h0 + t3 * h1 + t5 * h2);
-  c2 = -v * (t3 * h0 + t1 * h1 + t4 * h2);
-  c3 = -v * (t5 * h0 + t4 * h1 + t2 * h2);
+  const Q h0 = g0, h1 = g1, h2 = g2;
+  const Q t0 = s0, t1 = s1, t2 = s2, t3 = s3, t4 = s4, t5 = s5;
+  const Q vq = (Q)v;
+  c1 = (double)(-vq * (t0 * h0 + t3 * h1 + t5 * h2));
+  c2 = (double)(-vq * (t3 * h0 + t1 * h1 + t4 * h2));
+  c3 = (double)(-vq * (t5 * h0 + t4 * h1 + t2 * h2));
 }
 
 // ------------------------------------------------------------- reductions

@@ -212,7 +212,7 @@ void launch_influence_lists(const otm_state& st, const Workspace& w, hipStream_t
 constexpr int kScLanes = 8;
 constexpr int kScMPs = 256 / kScLanes;
 
-template <typename R, bool STAB>
+template <typename R, typename Q, bool STAB>
 __global__ __launch_bounds__(256) void k_seg_contrib(
     int64_t n_mp, int64_t cap, const int64_t* __restrict__ offsets,
     const int32_t* __restrict__ idx, const double* __restrict__ N, const R* __restrict__ dN,
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_seg_contrib(
     const R g0 = dN[q], g1 = dN[cap + q], g2 = dN[2 * cap + q];
     const double Nq = N[q];
     double c1, c2, c3;
-    pair_force<R>(v, s0, s1, s2, s3, s4, s5, g0, g1, g2, c1, c2, c3);
+    pair_force<Q>(v, s0, s1, s2, s3, s4, s5, g0, g1, g2, c1, c2, c3);
     if constexpr (STAB) stab_add(sb, sm, idx[q], Nq, c1, c2, c3);
     contrib[pos_of[q]] = make_double4(Nq * mp, c1, c2, c3);
   }
@@ -268,11 +268,11 @@ __global__ __launch_bounds__(256) void k_seg_gather(int64_t n_nodes, int64_t n_m
   }
 }
 
-template <typename R, bool STAB>
+template <typename R, typename Q, bool STAB>
 static void seg_contrib(const otm_state& st, const Workspace& w, const Stab& sb, hipStream_t s) {
   const int64_t nm = st.n_mp;
   const unsigned nb = (unsigned)((nm + kScMPs - 1) / kScMPs);
-  k_seg_contrib<R, STAB><<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.nbr_idx,
+  k_seg_contrib<R, Q, STAB><<<nb, 256, 0, s>>>(nm, st.pair_capacity, st.nbr_offsets, st.nbr_idx,
                                             st.N, (const R*)st.dN, st.vol, st.mass,
                                             (const R*)st.sigma, w.tr_pos, w.contrib, sb);
 }
@@ -284,9 +284,14 @@ void launch_scatter_segmented(const otm_state& st, const Workspace& w, const Sta
   if (nm > 0) {
     const bool stab = sb.eps > 0.0;
     if (st.precision == OTM_FP64)
-      stab ? seg_contrib<double, true>(st, w, sb, s) : seg_contrib<double, false>(st, w, sb, s);
+      stab ? seg_contrib<double, double, true>(st, w, sb, s)
+           : seg_contrib<double, double, false>(st, w, sb, s);
+    else if (st.precision == OTM_MIXED)
+      stab ? seg_contrib<float, float, true>(st, w, sb, s)
+           : seg_contrib<float, float, false>(st, w, sb, s);
     else
-      stab ? seg_contrib<float, true>(st, w, sb, s) : seg_contrib<float, false>(st, w, sb, s);
+      stab ? seg_contrib<float, double, true>(st, w, sb, s)
+           : seg_contrib<float, double, false>(st, w, sb, s);
   }
   launch_seg_gather(st, w, s);
 }
@@ -312,7 +317,7 @@ namespace otm {
 constexpr int kAsmMPs = 512;
 constexpr int kAsmLanes = 8;
 
-template <typename R, bool STAB>
+template <typename R, typename Q, bool STAB>
 __global__ __launch_bounds__(256) void k_assemble_atomic(
     int64_t n_nodes, int64_t n_mp, int64_t cap, const int64_t* __restrict__ offsets,
     const int32_t* __restrict__ idx, const double* __restrict__ N, const R* __restrict__ dN,
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
       const R g0 = dN[q], g1 = dN[cap + q], g2 = dN[2 * cap + q];
       const double Nq = N[q];
       c0 = Nq * mp;
-      pair_force<R>(v, s0, s1, s2, s3, s4, s5, g0, g1, g2, c1, c2, c3);
+      pair_force<Q>(v, s0, s1, s2, s3, s4, s5, g0, g1, g2, c1, c2, c3);
       if constexpr (STAB) stab_add(sb, sm, I, Nq, c1, c2, c3);
     };
     const int K = (int)(o1 - o0);
@@ -372,11 +377,11 @@ __global__ __launch_bounds__(256) void k_assemble_atomic(
   table_flush(table, tid, 256, m, f, n_nodes);
 }
 
-template <typename R, bool STAB>
+template <typename R, typename Q, bool STAB>
 static void assemble_atomic(const otm_state& st, const Stab& sb, hipStream_t s) {
   const int64_t nm = st.n_mp;
   const unsigned nb = (unsigned)((nm + kAsmMPs - 1) / kAsmMPs);
-  k_assemble_atomic<R, STAB><<<nb, 256, 0, s>>>(st.n_nodes, nm, st.pair_capacity,
+  k_assemble_atomic<R, Q, STAB><<<nb, 256, 0, s>>>(st.n_nodes, nm, st.pair_capacity,
                                                 st.nbr_offsets, st.nbr_idx, st.N,
                                                 (const R*)st.dN, st.vol, st.mass,
                                                 (const R*)st.sigma, st.m, st.f, sb);
@@ -386,9 +391,14 @@ void launch_assemble_atomic(const otm_state& st, const Stab& sb, hipStream_t s) 
   if (st.n_mp <= 0) return;
   const bool stab = sb.eps > 0.0;
   if (st.precision == OTM_FP64)
-    stab ? assemble_atomic<double, true>(st, sb, s) : assemble_atomic<double, false>(st, sb, s);
+    stab ? assemble_atomic<double, double, true>(st, sb, s)
+         : assemble_atomic<double, double, false>(st, sb, s);
+  else if (st.precision == OTM_MIXED)
+    stab ? assemble_atomic<float, float, true>(st, sb, s)
+         : assemble_atomic<float, float, false>(st, sb, s);
   else
-    stab ? assemble_atomic<float, true>(st, sb, s) : assemble_atomic<float, false>(st, sb, s);
+    stab ? assemble_atomic<float, double, true>(st, sb, s)
+         : assemble_atomic<float, double, false>(st, sb, s);
 }
 
 }  // namespace otm

@@ -144,7 +144,9 @@ class Sim:
 
     x_nodes (nn,3), x_mp (np,3), vol_mp, mass_mp (np,), v0_nodes (nn,3) are
     host arrays; ``params`` is a flat dict (oracle keys, including ``dt``).
-    ``precision`` is "fp64" or "mixed"; ``scatter`` "atomic" or "segmented"
+    ``precision`` is "fp64", "mixed" (float32 return map and force products)
+    or "mixed_storage" (float32 storage, float64 arithmetic); ``scatter``
+    "atomic" or "segmented"
     (bit-reproducible).  The pair buffer is sized from a first search times
     ``capacity_margin``.  Optional parts follow ``params``: ``eps_stab`` > 0
     (stabilisation term), ``fracture`` with ``jc_d`` (Johnson-Cook fracture)
@@ -167,7 +169,11 @@ class Sim:
         self.params = dict(params)
         self.p = make_params(params)
         self.dt = float(params["dt"])
-        self.prec = _lib.OTM_FP64 if precision == "fp64" else _lib.OTM_MIXED
+        precs = {"fp64": _lib.OTM_FP64, "mixed": _lib.OTM_MIXED,
+                 "mixed_storage": _lib.OTM_MIXED_STORAGE}
+        if precision not in precs:
+            raise ValueError(f"precision must be one of {sorted(precs)}")
+        self.prec = precs[precision]
         self.mode = _lib.OTM_SCATTER_ATOMIC if scatter == "atomic" else _lib.OTM_SCATTER_SEGMENTED
         dev = self.device
         rdt = torch.float64 if self.prec == _lib.OTM_FP64 else torch.float32

@@ -104,13 +104,13 @@ def test_one_step_at_full_size(rod, precision, tol):
 
 def test_mixed_drift_over_100_steps_at_full_size(rod):
     """The Taylor rod's 100 steps (1.13M MPs, lists rebuilt every step) in
-    mixed precision against the float64 run of the same steps on the GPU
+    both mixed modes against the float64 run of the same steps on the GPU
     (the float64 path is held to the oracle at 1e-10 by the tests above and
     at the smaller sizes): every field within 1e-5 (R20 measure, positions as
     displacements)."""
     from tests.helpers import compare, gpu_fields
     out = {}
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed_storage"):
         sim, p = make_sim(rod, prec, "atomic")
         sim.init()
         sim.run(rod.steps)
@@ -120,8 +120,9 @@ def test_mixed_drift_over_100_steps_at_full_size(rod):
     # the two runs may find different lists for MPs on the search radius, so
     # per-pair fields are left out
     fields = ["u", "du", "m", "f", "up", "vol", "Fm1", "be_m1", "sigma", "epsbar", "dT"]
-    errs = compare(out["mixed"], out["fp64"], fields)
-    print("mixed vs float64 after 100 steps, 1.13M MPs:",
-          {k: float("%.2e" % v) for k, v in errs.items()})
-    bad = {k: v for k, v in errs.items() if not v < 1e-5}
-    assert not bad, bad
+    for prec in ("mixed", "mixed_storage"):
+        errs = compare(out[prec], out["fp64"], fields)
+        print(f"{prec} vs float64 after 100 steps, 1.13M MPs:",
+              {k: float("%.2e" % v) for k, v in errs.items()})
+        bad = {k: v for k, v in errs.items() if not v < 1e-5}
+        assert not bad, (prec, bad)

@@ -221,13 +221,14 @@ MIXED_TOL = {  # stated mixed-precision error bounds over 100 steps (relative, m
 }
 
 
-def test_small_rod_100_steps_mixed(rod_oracle):
+@pytest.mark.parametrize("precision", ["mixed", "mixed_storage"])
+def test_small_rod_100_steps_mixed(rod_oracle, precision):
     w, st, p = rod_oracle
-    g, _ = _gpu_run(w, 100, precision="mixed")
+    g, _ = _gpu_run(w, 100, precision=precision)
     assert np.array_equal(g["offsets"], st.offsets) and np.array_equal(g["idx"], st.idx)
     errs = compare(gpu_fields(g, w.x_nodes, w.x_mp, p["T_r"]),
                    oracle_fields(st, w.x_nodes, w.x_mp, p["T_r"]))
-    print("mixed-precision errors after 100 steps:", json.dumps(errs))
+    print(f"{precision} errors after 100 steps:", json.dumps(errs))
     bad = {k: v for k, v in errs.items() if not v < MIXED_TOL[k]}
     assert not bad, bad
 
