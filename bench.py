@@ -340,7 +340,11 @@ def run_cutting_5m(erode_every=50):
                                              sim.ws.ptr, sim.ws.nbytes, _ptr(sim.diag), ev[k],
                                              stream), "otm_step_profiled")
         torch.cuda.synchronize()
-        code, d = sim.check_diag()
+        try:
+            code, d = sim.check_diag()
+        except _lib.OtmError as e:
+            raise RuntimeError(f"steps {s0 + 1}..{s0 + n_seg} after {len(erode_ms)} "
+                               f"erosions: {e}") from None
         P = int(d.pairs_needed)
         for k in range(s0, s0 + n_seg):
             for a, b in zip(used[:-1], used[1:]):
@@ -487,9 +491,14 @@ def main():
         return
     w = W.config_by_name(args.workload)
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    progress(f"main line: {w.name}, fp64, atomic, {args.steps} steps")
     main_run = run_variant(w, "fp64", "atomic", args.steps, args.warmup)
     variants = {}
     for v in [s for s in args.variants.split(",") if s and s != "none"]:
+        progress(f"variant {v}")
         if v in ("paper_rod", "cutting", "cutting_5m"):
             run = {"paper_rod": run_paper_rod, "cutting": run_cutting,
                    "cutting_5m": run_cutting_5m}[v]
@@ -573,10 +582,12 @@ def main():
         "adjoint_forward_ratio": None,
     }
     if not args.no_adjoint:
+        progress("adjoint rollout")
         adj = adjoint_ratio()
         line["adjoint_forward_ratio"] = adj["ratio"]
         line["adjoint"] = adj
     if not args.no_cpu_baseline:
+        progress("oracle on the host")
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
 

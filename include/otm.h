@@ -127,8 +127,11 @@ typedef struct otm_params {
      tool_cN |g| along the outward normal plus a tangential force: the trial
      -tool_cT g_T (g_T the node's tangential gap, see otm_state::tool_gt)
      while it is at most tool_mu times the normal force (stick), else that
-     limit along it (Coulomb slip).  The force joins the internal force in the
-     node update.  Needs st->tool_gt and st->clock. */
+     limit along it (Coulomb slip).  At a node of lumped mass m both penalty
+     stiffnesses are limited to m / dt^2 (one step removes the whole
+     penetration; a light node would otherwise make the explicit contact
+     unstable), and a node without mass feels none.  The force joins the
+     internal force in the node update.  Needs st->tool_gt and st->clock. */
   double tool_c[3];       /* centre of the tip circle at t = 0 */
   double tool_v[3];       /* tool velocity */
   double tool_r;          /* tip radius > 0 */

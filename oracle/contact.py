@@ -25,7 +25,13 @@ Readings (the paper points elsewhere for the details):
   the current tangent plane); the trial force -c_T g_T is kept if its size is
   at most mu times the normal force (stick), else it is scaled to that limit
   (slip, opposite to the slip direction) and the gap reset to -t_T / c_T;
-  a node out of contact has zero tangential gap.
+  a node out of contact has zero tangential gap;
+* the penalty stiffnesses of a node are limited to m_I / dt^2, the stiffness
+  at which one step removes the node's whole penetration (the paper states
+  the non-penetration condition, not its penalty constants): a node whose
+  lumped mass is below c dt^2 (the light nodes a freed surface leaves) would
+  otherwise make the explicit update unstable (the contact spring's
+  frequency beyond 2 / dt); a node without mass gets no contact force.
 """
 from __future__ import annotations
 
@@ -68,21 +74,31 @@ def tool_gap(x, t, p):
     return sd - float(p["tool_r"]), nrm
 
 
-def tool_forces(x, du, gT, t, p):
-    """Contact force (n,3) on the nodes and their new tangential gaps (n,3)."""
+def tool_forces(x, du, gT, t, p, m=None):
+    """Contact force (n,3) on the nodes and their new tangential gaps (n,3).
+    ``m`` (n,): the nodes' lumped masses, which limit the penalty
+    stiffnesses to m / dt^2 (None: no limit)."""
     g, nrm = tool_gap(x, t, p)
     pen = g < 0
-    tn = float(p["tool_cN"]) * np.where(pen, -g, 0.0)
+    n = x.shape[0]
+    cN = np.full(n, float(p["tool_cN"]))
+    cT = np.full(n, float(p["tool_cT"]))
+    if m is not None:
+        klim = np.where(m.real > 0, m / (p["dt"] * p["dt"]), 0.0)
+        cN = np.where(klim.real < cN, klim, cN)
+        cT = np.where(klim.real < cT, klim, cT)
+    tn = cN * np.where(pen, -g, 0.0)
     rel = du - p["dt"] * np.asarray(p["tool_v"], float)
     rel_t = rel - (rel * nrm).sum(axis=1)[:, None] * nrm
     old_t = gT - (gT * nrm).sum(axis=1)[:, None] * nrm
     trial = old_t + rel_t
-    tT = -float(p["tool_cT"]) * trial
+    tT = -cT[:, None] * trial
     mag = np.sqrt((tT * tT).sum(axis=1))
     lim = float(p["tool_mu"]) * tn
     slip = mag > lim
     scale = np.where(slip, lim / np.where(mag > 0, mag, 1.0), 1.0)
     tT = tT * scale[:, None]
     f = np.where(pen[:, None], tn[:, None] * nrm + tT, 0.0)
-    gT_new = np.where(pen[:, None], -tT / float(p["tool_cT"]), 0.0)
+    safe = np.where(cT.real > 0, cT, 1.0)
+    gT_new = np.where((pen & (cT.real > 0))[:, None], -tT / safe[:, None], 0.0)
     return f, gT_new

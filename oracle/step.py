@@ -134,7 +134,7 @@ def node_update(st, p):
     f = st.f
     if p.get("tool"):
         # rigid tool: penalty contact force at x_n, tool at t_n
-        fc, st.gT = contact.tool_forces(st.x, st.du, st.gT, st.clock, p)
+        fc, st.gT = contact.tool_forces(st.x, st.du, st.gT, st.clock, p, st.m)
         f = f + fc
         st.clock = st.clock + dt
     # a node outside every support has no lumped mass and no force: it keeps

@@ -326,20 +326,19 @@ def cutting_slab_5m(h=4.64e-6, seed=11, steps=500):
     with 0.1 mm depth of cut, starting 0.1 um (2 % of h) into the workpiece's
     face (made flat: the jitter would otherwise put nodes up to 0.46 um inside
     the tool at t = 0, which the penalty contact fires off at ~10^3 m/s),
-    dt = 5e-11 s, 500 steps, Ti-alloy-like flow constants from ``seed``, heat
+    dt = 1e-10 s, 500 steps, Ti-alloy-like flow constants from ``seed``, heat
     conduction with the Ti-alloy conductivity 6.7 W/(m K), and low fracture
     constants d = (0, 0.005, -0.5, 0.014, 3.7) so that MPs ahead of the tool
     fail and are removed within the run (the real constants would need far
-    more steps; in 500 steps the tool advances 0.125 um, and the initial
+    more steps; in 500 steps the tool advances 0.25 um, and the initial
     engagement is what makes the MPs at the tool yield and fail within the
     run); nodes are added at the freed surface (insert_dist = h / 2) and
-    nodes left in no support deleted.  The step is half that of the smaller
-    cutting slab: erosion leaves light nodes at the tool tip, where the
-    penalty contact with dt = 1e-10 s grew into a blow-up a few tens of
-    steps after the second erosion (with and without added nodes, in float64
-    and mixed precision alike); with 5e-11 s the run stays bounded."""
+    nodes left in no support deleted.  Erosion leaves light nodes at the
+    tool tip; the contact penalty limited by the nodal mass keeps them
+    stable (without that limit the run blew up a few tens of steps after
+    the second erosion)."""
     w = cutting_slab(h=h, seed=seed, length=2e-3, height=1e-3, layers=12, depth=0.1e-3,
-                     speed=5.0, steps=steps, dt=5e-11, name="cutting_slab_5m",
+                     speed=5.0, steps=steps, dt=1e-10, name="cutting_slab_5m",
                      fracture=(0.0, 0.005, -0.5, 0.014, 3.7), flat_face=True,
                      engage=0.1e-6)
     w.material.kappa = 6.7

@@ -37,10 +37,13 @@ struct ToolArgs {
   double* gt;           // [3][n] tangential gaps
 };
 
-// Contact force on node i at position xo with last increment du_old; updates
-// its tangential gap.
+// Contact force on node i at position xo with last increment du_old and
+// lumped mass mi; updates its tangential gap.  The penalty stiffnesses are
+// limited to mi / dt^2 (one step removes the whole penetration), so a light
+// node does not make the explicit contact unstable; a node without mass
+// feels no contact force.
 OTM_DEV void tool_contact(const ToolArgs& t, int64_t n, int64_t i, const double xo[3],
-                          const double du_old[3], double fc[3]) {
+                          const double du_old[3], double mi, double fc[3]) {
   const double tm = t.clock[0];
   const double dx = xo[0] - (t.cx + tm * t.vx), dy = xo[1] - (t.cy + tm * t.vy);
   const double a = -dx, b = t.sa * dx - t.ca * dy;  // n1 . d, n2 . d
@@ -69,7 +72,9 @@ OTM_DEV void tool_contact(const ToolArgs& t, int64_t n, int64_t i, const double 
     return;
   }
   const double nrm[3] = {nx, ny, 0.0};
-  const double tn = t.cN * -g;
+  const double klim = mi > 0.0 ? mi / (t.dt * t.dt) : 0.0;
+  const double kN = klim < t.cN ? klim : t.cN, kT = klim < t.cT ? klim : t.cT;
+  const double tn = kN * -g;
   const double rel[3] = {du_old[0] - t.dt * t.vx, du_old[1] - t.dt * t.vy,
                          du_old[2] - t.dt * t.vz};
   const double go[3] = {t.gt[i], t.gt[n + i], t.gt[2 * n + i]};
@@ -77,7 +82,7 @@ OTM_DEV void tool_contact(const ToolArgs& t, int64_t n, int64_t i, const double 
   const double gn = go[0] * nrm[0] + go[1] * nrm[1] + go[2] * nrm[2];
   double tt[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) tt[c] = -t.cT * ((go[c] - gn * nrm[c]) + (rel[c] - rn * nrm[c]));
+  for (int c = 0; c < 3; ++c) tt[c] = -kT * ((go[c] - gn * nrm[c]) + (rel[c] - rn * nrm[c]));
   const double mag = sqrt(tt[0] * tt[0] + tt[1] * tt[1] + tt[2] * tt[2]);
   const double lim = t.mu * tn;
   const double scale = mag > lim ? lim / (mag > 0.0 ? mag : 1.0) : 1.0;
@@ -85,7 +90,7 @@ OTM_DEV void tool_contact(const ToolArgs& t, int64_t n, int64_t i, const double 
   for (int c = 0; c < 3; ++c) {
     tt[c] *= scale;
     fc[c] = tn * nrm[c] + tt[c];
-    t.gt[c * n + i] = -tt[c] / t.cT;
+    t.gt[c * n + i] = kT > 0.0 ? -tt[c] / kT : 0.0;
   }
 }
 
@@ -121,7 +126,7 @@ __global__ __launch_bounds__(256) void k_node_update(int64_t n, double* __restri
   }
   if (tool.on) {
     double fc[3];
-    tool_contact(tool, n, i, xo, u, fc);
+    tool_contact(tool, n, i, xo, u, mi, fc);
 #pragma unroll
     for (int c = 0; c < 3; ++c) fi[c] += fc[c];
   }

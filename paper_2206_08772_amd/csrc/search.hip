@@ -408,15 +408,16 @@ OTM_DEV double lane_value(double v, int t) {  // v of lane t (t uniform)
 }
 
 // Cell-centric pass: one wave per grid cell.  All MPs of a cell have the same
-// 27 candidate cells, so the wave loads the candidates once, puts them in
-// ascending node id order (rank sort of the ids in LDS; ids are distinct)
-// and keeps them in registers, lane l holding candidates l, l + 64, ...  Each
-// MP of the cell (binned like the nodes) is then tested against them: a
-// ballot of the hits, taken in candidate order, is already the MP's sorted
-// row, written to its staging row at the hit's prefix count.  The count goes
-// to offsets[p + 1]; rows longer than kRowCap are only counted (the
-// compaction re-finds them).  A cell with more than kCand candidates takes
-// each MP separately: hits are appended to LDS by ballot and rank-sorted.
+// 27 candidate cells, so the wave loads the candidates once and keeps them in
+// registers, lane l holding candidates l, l + 64, ...  Each MP of the cell
+// (binned like the nodes) is then tested against them: a ballot of the hits,
+// taken in candidate order, gives each hit its place in the MP's staging
+// row.  The row is in stencil order; the compaction sorts it by node id (one
+// lane per row, in registers), which costs far fewer instructions than
+// sorting each cell's candidates.  The count goes to offsets[p + 1]; rows
+// longer than kRowCap are only counted (the compaction re-finds them).  A
+// cell with more than kCand candidates takes each MP separately: hits are
+// appended to LDS by ballot and rank-sorted.
 //
 // The cell index is wave-uniform, so a cell's header (MP range, candidate
 // rows) comes from scalar loads, and the next cell's header is requested
@@ -446,8 +447,7 @@ OTM_DEV CellHdr cell_header(int64_t c, const Grid& g, const int32_t* __restrict_
   return h;
 }
 
-struct CellLds {  // candidate coordinates and ids, structure of arrays
-  double x[kCand], y[kCand], z[kCand];
+struct CellLds {  // the hits of one MP in the dense path
   int32_t ids[kCand];
 };
 
@@ -463,58 +463,14 @@ OTM_DEV void cell_scan_one(const CellHdr& h, double r2, const double4* __restric
     // the first 64 MPs of the cell, requested with the candidates
     const int mc0 = m1 - m0 < kWave ? (int)(m1 - m0) : kWave;
     double4 mine = mp_sorted[m0 + (lane < mc0 ? lane : mc0 - 1)];
-    if (T > 0) {
-      // ids padded with INT32_MAX to a multiple of 16 (never smaller than an id)
-      const int32_t T16 = (T + 15) & ~15;
-      int32_t id[kCandChunks];
+    // the candidates in stencil order: the rows come out unsorted and the
+    // compaction sorts each one by node id
 #pragma unroll
-      for (int k = 0; k < kCandChunks; ++k) {
-        if (k < nch) {
-          const int32_t j = k * kWave + lane;
-          v[k] = sorted[cand_pos(j < T ? j : 0, h.rs, h.pre)];
-          id[k] = j < T ? (int32_t)v[k].w : INT32_MAX;
-          if (j < T16) L.ids[j] = id[k];
-        }
-      }
-      wave_sync();
-      // rank = number of smaller ids, 16 ids per step from four 16-byte LDS
-      // reads (broadcast: every lane reads the same words); each candidate
-      // is then stored at its rank and read back in rank order
-      int32_t r[kCandChunks];
-#pragma unroll
-      for (int k = 0; k < kCandChunks; ++k) r[k] = 0;
-      for (int32_t t = 0; t < T16; t += 16) {
-        int4 q[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) q[u] = *(const int4*)&L.ids[t + 4 * u];
-#pragma unroll
-        for (int k = 0; k < kCandChunks; ++k) {
-          if (k < nch) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-              r[k] += (q[u].x < id[k]) + (q[u].y < id[k]) + (q[u].z < id[k]) + (q[u].w < id[k]);
-          }
-        }
-      }
-      wave_sync();  // every rank is known before the ids are overwritten
-#pragma unroll
-      for (int k = 0; k < kCandChunks; ++k) {
+    for (int k = 0; k < kCandChunks; ++k) {
+      if (k < nch) {
         const int32_t j = k * kWave + lane;
-        if (k < nch && j < T) {
-          L.x[r[k]] = v[k].x; L.y[r[k]] = v[k].y; L.z[r[k]] = v[k].z;
-          L.ids[r[k]] = id[k];
-        }
+        v[k] = sorted[cand_pos(j < T ? j : 0, h.rs, h.pre)];
       }
-      wave_sync();
-#pragma unroll
-      for (int k = 0; k < kCandChunks; ++k) {
-        const int32_t j = k * kWave + lane;
-        if (k < nch) {
-          const int32_t jj = j < T ? j : 0;
-          v[k] = make_double4(L.x[jj], L.y[jj], L.z[jj], (double)L.ids[jj]);
-        }
-      }
-      wave_sync();  // the LDS arrays are free again for the next cell
     }
     // per chunk: lanes holding a real candidate, and the candidate ids
     bool valid[kCandChunks];
@@ -632,6 +588,34 @@ __global__ __launch_bounds__(kCellWaves * kWave) void k_cell_scan(
 
 constexpr int kScanMPs = 64;  // MPs per compaction workgroup
 
+// Ascending order of a staged row of K <= 32 node ids (distinct): a bitonic
+// network over 32 registers, the slots past K padded with INT32_MAX.
+OTM_DEV void sort_row32(int32_t* row, int K) {
+  int32_t a[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) a[i] = i < K ? row[i] : INT32_MAX;
+#pragma unroll
+  for (int k = 2; k <= 32; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const int32_t x = a[i], y = a[l];
+          const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+          const bool up = (i & k) == 0;
+          a[i] = up ? lo : hi;
+          a[l] = up ? hi : lo;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 32; ++i)
+    if (i < K) row[i] = a[i];
+}
+
 // Copies each workgroup's staged rows into its contiguous CSR segment with
 // unit-stride stores; rows longer than kRowCap are found again and sorted
 // in place by their own lane.
@@ -670,6 +654,23 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
   }
   if (offsets[n_mp] > capacity) return;  // lists do not fit: counts only
   for (int i = tid; i < nloc * kRowCap; i += 256) rows[i] = stage[p0 * kRowCap + i];
+  __syncthreads();
+  // the staged rows come in stencil order: one lane sorts each (rows past
+  // 32 ids, rare, by insertion in LDS; rows past kRowCap are re-found below)
+  if (tid < nloc) {
+    const int K = (int)(off[tid + 1] - off[tid]);
+    int32_t* row = rows + tid * kRowCap;
+    if (K <= 32) {
+      sort_row32(row, K);
+    } else if (K <= kRowCap) {
+      for (int j = 1; j < K; ++j) {
+        const int32_t id = row[j];
+        int t = j;
+        for (; t > 0 && row[t - 1] > id; --t) row[t] = row[t - 1];
+        row[t] = id;
+      }
+    }
+  }
   __syncthreads();
   const int64_t base = off[0];
   const int total = (int)(off[nloc] - base);

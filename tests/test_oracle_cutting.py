@@ -167,3 +167,47 @@ def test_short_cut_contact_friction_and_fracture(cut_run):
         tn = p["tool_cN"] * np.maximum(-gp, 0.0)
         assert np.all(np.sqrt((tT * tT).sum(1)) <= p["tool_mu"] * tn * (1 + 1e-12))
     assert abs(last.clock - w.steps * w.dt) < 1e-12 * w.steps * w.dt
+
+
+def test_light_node_penalty_is_limited_by_its_mass():
+    """The node 3 nm inside the rake face: with a lumped mass m below
+    c_N dt^2 the normal force is (m / dt^2) 3 nm; with a heavier node it is
+    c_N 3 nm; a node without mass feels none."""
+    p = _p()
+    c = np.asarray(p["tool_c"])
+    x = np.array([[c[0] - p["tool_r"] + 3e-9, c[1] + 5e-6, 1e-6]] * 3)
+    k = p["tool_cN"] * p["dt"] ** 2
+    m = np.array([0.1 * k, 10.0 * k, 0.0])
+    f, gT = CT.tool_forces(x, np.zeros((3, 3)), np.zeros((3, 3)), 0.0, p, m)
+    assert np.allclose(f[0], [-0.1 * p["tool_cN"] * 3e-9, 0, 0], rtol=1e-9, atol=0)
+    assert np.allclose(f[1], [-p["tool_cN"] * 3e-9, 0, 0], rtol=1e-9, atol=0)
+    assert np.all(f[2] == 0) and np.all(gT == 0)
+
+
+@pytest.mark.parametrize("limited", [True, False])
+def test_limited_penalty_keeps_a_light_node_bounded(limited):
+    """One light node (m = 0.01 c_N dt^2) released 3 nm inside a resting tool,
+    moved by the central difference with the contact force alone: with the
+    mass limit one step puts it back on the surface and it leaves at 3 nm per
+    step, its penetration never exceeding the initial 3 nm; without the limit
+    the contact spring's frequency is beyond 2 / dt and one step fires it off
+    at 100 times that (c_N dt^2 / m = 100)."""
+    p = _p(tool_v=np.zeros(3))
+    c = np.asarray(p["tool_c"])
+    dt2 = p["dt"] ** 2
+    m = np.array([0.01 * p["tool_cN"] * dt2])
+    x = np.array([[c[0] - p["tool_r"] + 3e-9, c[1] + 5e-6, 1e-6]])
+    du = np.zeros((1, 3))
+    gT = np.zeros((1, 3))
+    worst, fastest = 0.0, 0.0
+    for _ in range(50):
+        f, gT = CT.tool_forces(x, du, gT, 0.0, p, m if limited else None)
+        du = du + dt2 * f / m[:, None]
+        x = x + du
+        g, _ = CT.tool_gap(x, 0.0, p)
+        worst = max(worst, -g[0])
+        fastest = max(fastest, float(np.sqrt((du * du).sum())))
+    if limited:
+        assert worst <= 3e-9 * (1 + 1e-9) and fastest <= 3e-9 * (1 + 1e-9)
+    else:
+        assert fastest >= 0.99 * 100 * 3e-9
