@@ -548,7 +548,7 @@ def main():
     phases["mp_update"] = dict(roof, ms=round(ph["mp_update"], 4))
     # `roofline` is the MP pass (the kernel the HBM target is set on); the
     # longest kernel is the shape functions with the fused assembly
-    longest = dict(kernel="k_lme_asm<4, 10, double> (LME Newton + fused atomic assembly)",
+    longest = dict(kernel="k_lme_asm<double> (LME Newton + fused atomic assembly)",
                    ms=phases["lme_assembly"]["ms"],
                    share_of_step=round(phases["lme_assembly"]["ms"] / main_run["ms_per_step"], 3),
                    hbm_frac=phases["lme_assembly"]["frac"],

@@ -1,7 +1,7 @@
 // Local max-ent shape functions (Sec. 2.3) by a per-material-point damped
 // Newton solve for the Lagrange multiplier, in float64.
 //
-// A group of G = 4 lanes works on one MP; each lane keeps up to PPL = 8 of
+// A group of G = 4 lanes works on one MP; each lane keeps up to PPL = 9 of
 // the MP's pairs in registers (offset d = x_p - x_I), so one Newton
 // evaluation costs one exp per pair and 10 group reductions (Z, r,
 // S = sum e d d^T) of two DPP stages each.  The 3x3 solve is repeated in
@@ -9,8 +9,12 @@
 // keep the per-MP work (reductions, solve, line search) from being repeated
 // across many lanes; the kernel is bound by the latency of that per-MP chain
 // at two waves per SIMD, not by memory traffic.  The supports of the
-// lattice-like bodies hold 20-33 nodes (radius 1.86 h); MPs with more than
-// 32 pairs take the same iteration with pairs re-read from memory.
+// lattice-like bodies hold 20-33 nodes (radius 1.86 h), up to 35 where the
+// rod is compressed; MPs with more than 36 pairs take the same iteration
+// with pairs re-read from memory, which is several times slower, and since
+// such MPs cluster in space the workgroup holding them sets the kernel's
+// end (with 32 cached pairs the rod's 0.03 % of MPs with 33-35 pairs cost
+// 13 % of the kernel after 100 steps).
 //
 // Newton reading (the paper gives none): start from the previous multiplier;
 // step -J^{-1} r with J = sum N d d^T - r r^T; Armijo backtracking on log Z
@@ -504,7 +508,7 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
                 const AsmIn* fused, const SegIn* seg) {
   if (n_mp <= 0) return;
   const NodeSrc ns{x_nodes, packed, n_nodes};
-  constexpr int G = 4, PPL = 8;
+  constexpr int G = 4, PPL = 9;
   if (fused != nullptr) {
     auto run = [&](auto kernel, auto* dn) {
       kernel<<<kLmeAsmBlocks, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity,
