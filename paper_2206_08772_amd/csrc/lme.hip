@@ -167,6 +167,7 @@ OTM_DEV void store_dn(DN* dN, int64_t cap, int64_t q, const double g[3]) {
 struct NoSink {
   static constexpr bool kBatch = false;
   OTM_DEV void begin(int64_t) {}
+  OTM_DEV void ready() const {}
   OTM_DEV void operator()(int64_t, double, const double*) {}
 };
 
@@ -201,6 +202,15 @@ struct AsmSink {
       Tp = Tmp[p];
       q0 = q[p]; q1 = q[n_mp + p]; q2 = q[2 * n_mp + p];
     }
+  }
+  // The values loaded by begin() are first used inside the per-pair
+  // branches, where the compiler waits for them with a full wait that also
+  // waits for every store issued so far (N, grad N of the earlier pairs); an
+  // empty statement that reads them here puts that one wait in straight-line
+  // code before the pairs, so the pairs' stores stay in flight.
+  OTM_DEV void ready() const {
+    __asm__ volatile("" ::"v"(mp), "v"(vd), "v"(s0), "v"(s1), "v"(s2), "v"(s3), "v"(s4), "v"(s5));
+    if constexpr (HEAT) __asm__ volatile("" ::"v"(Tp), "v"(q0), "v"(q1), "v"(q2));
   }
   OTM_DEV void values(double Nq, const double g[3], double (&c)[V]) const {
     const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
@@ -241,6 +251,10 @@ struct SegSink {
     vd = vol[p];
     s0 = sigma[p]; s1 = sigma[n_mp + p]; s2 = sigma[2 * n_mp + p];
     s3 = sigma[3 * n_mp + p]; s4 = sigma[4 * n_mp + p]; s5 = sigma[5 * n_mp + p];
+  }
+  // as AsmSink::ready
+  OTM_DEV void ready() const {
+    __asm__ volatile("" ::"v"(mp), "v"(vd), "v"(s0), "v"(s1), "v"(s2), "v"(s3), "v"(s4), "v"(s5));
   }
   OTM_DEV void operator()(int64_t q, double Nq, const double g[3]) {
     const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
@@ -339,6 +353,7 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
   sym_inv(ev.J, Mi, det);
   const double iz = 1.0 / ev.Z;
   sink.begin(p);
+  sink.ready();
   auto finish = [&](int q, double e, double dx, double dy, double dz) {
     const double Nq = e * iz;
     const double d3[3] = {dx, dy, dz};

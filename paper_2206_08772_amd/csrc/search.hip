@@ -412,9 +412,9 @@ OTM_DEV double lane_value(double v, int t) {  // v of lane t (t uniform)
 // registers, lane l holding candidates l, l + 64, ...  Each MP of the cell
 // (binned like the nodes) is then tested against them: a ballot of the hits,
 // taken in candidate order, gives each hit its place in the MP's staging
-// row.  The row is in stencil order; the compaction sorts it by node id (one
-// lane per row, in registers), which costs far fewer instructions than
-// sorting each cell's candidates.  The count goes to offsets[p + 1]; rows
+// row.  The row is in stencil order; the compaction sorts it by node id (the
+// four lanes of a quad per row, in registers), which costs far fewer
+// instructions than sorting each cell's candidates.  The count goes to offsets[p + 1]; rows
 // longer than kRowCap are only counted (the compaction re-finds them).  A
 // cell with more than kCand candidates takes each MP separately: hits are
 // appended to LDS by ballot and rank-sorted.
@@ -588,32 +588,47 @@ __global__ __launch_bounds__(kCellWaves * kWave) void k_cell_scan(
 
 constexpr int kScanMPs = 64;  // MPs per compaction workgroup
 
-// Ascending order of a staged row of K <= 32 node ids (distinct): a bitonic
-// network over 32 registers, the slots past K padded with INT32_MAX.
-OTM_DEV void sort_row32(int32_t* row, int K) {
-  int32_t a[32];
+// Ascending order of a staged row of K <= 32 node ids (distinct), sorted by
+// the four lanes of a quad: a bitonic network over 32 slots (the slots past
+// K padded with INT32_MAX), lane l of the quad holding slots 8l .. 8l + 7.
+// Compare-exchanges between slots 8 or 16 apart pair a lane with the quad
+// lane l ^ 1 or l ^ 2 (DPP quad permutations); the others stay in the lane.
+// Every lane of the quad must call it with the same row.
+OTM_DEV void sort_row32_quad(int32_t* row, int K, int l) {
+  int32_t a[8];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) a[i] = i < K ? row[i] : INT32_MAX;
+  for (int e = 0; e < 8; ++e) a[e] = 8 * l + e < K ? row[8 * l + e] : INT32_MAX;
 #pragma unroll
   for (int k = 2; k <= 32; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 8) {
+        const bool lower = (l & (j >> 3)) == 0;
 #pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        const int l = i ^ j;
-        if (l > i) {
-          const int32_t x = a[i], y = a[l];
-          const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
-          const bool up = (i & k) == 0;
-          a[i] = up ? lo : hi;
-          a[l] = up ? hi : lo;
+        for (int e = 0; e < 8; ++e) {
+          const int32_t w = j == 8 ? dpp_move<0xB1>(a[e]) : dpp_move<0x4E>(a[e]);
+          const int32_t lo = a[e] < w ? a[e] : w, hi = a[e] < w ? w : a[e];
+          const bool up = ((8 * l + e) & k) == 0;
+          a[e] = lower == up ? lo : hi;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int f = e ^ j;
+          if (f > e) {
+            const int32_t x = a[e], y = a[f];
+            const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+            const bool up = ((8 * l + e) & k) == 0;
+            a[e] = up ? lo : hi;
+            a[f] = up ? hi : lo;
+          }
         }
       }
     }
   }
 #pragma unroll
-  for (int i = 0; i < 32; ++i)
-    if (i < K) row[i] = a[i];
+  for (int e = 0; e < 8; ++e)
+    if (8 * l + e < K) row[8 * l + e] = a[e];
 }
 
 // Copies each workgroup's staged rows into its contiguous CSR segment with
@@ -655,14 +670,17 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
   if (offsets[n_mp] > capacity) return;  // lists do not fit: counts only
   for (int i = tid; i < nloc * kRowCap; i += 256) rows[i] = stage[p0 * kRowCap + i];
   __syncthreads();
-  // the staged rows come in stencil order: one lane sorts each (rows past
-  // 32 ids, rare, by insertion in LDS; rows past kRowCap are re-found below)
-  if (tid < nloc) {
-    const int K = (int)(off[tid + 1] - off[tid]);
-    int32_t* row = rows + tid * kRowCap;
+  // the staged rows come in stencil order: the four lanes of quad i sort row
+  // i (rows past 32 ids, rare, by insertion in LDS in the quad's first lane;
+  // rows past kRowCap are re-found below)
+  static_assert(4 * kScanMPs == 256, "one quad per staged row");
+  if (tid / 4 < nloc) {
+    const int i = tid / 4, l = tid % 4;
+    const int K = (int)(off[i + 1] - off[i]);
+    int32_t* row = rows + i * kRowCap;
     if (K <= 32) {
-      sort_row32(row, K);
-    } else if (K <= kRowCap) {
+      sort_row32_quad(row, K, l);
+    } else if (K <= kRowCap && l == 0) {
       for (int j = 1; j < K; ++j) {
         const int32_t id = row[j];
         int t = j;

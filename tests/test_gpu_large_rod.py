@@ -21,8 +21,10 @@ pytestmark = pytest.mark.gpu
 STEPS = 200
 # float32 return map and scatter over 200 steps: bound on the max-norm
 # relative drift of each field against the float64 run (positions as
-# displacements); the 100-step small-rod errors are below 4e-6
+# displacements); the 100-step small-rod errors are below 5e-6.  float32
+# storage with float64 arithmetic stays within 1e-5.
 MIXED_BOUND = 2e-5
+STORAGE_BOUND = 1e-5
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -74,22 +76,26 @@ def _run(rod, precision, scatter, check_lists=False):
 def test_large_rod_mixed_drift_and_throughput(rod):
     ref, ms64 = _run(rod, "fp64", "atomic", check_lists=True)
     ma, ms_a = _run(rod, "mixed", "atomic")
+    mst, ms_st = _run(rod, "mixed_storage", "atomic")
     ms_s_runs, seg = [], []
     for _ in range(2):
         f, ms = _run(rod, "mixed", "segmented")
         seg.append(f)
         ms_s_runs.append(ms)
     drift = {}
-    for name, fields in (("mixed_atomic", ma), ("mixed_segmented", seg[0])):
+    for name, fields in (("mixed_atomic", ma), ("mixed_segmented", seg[0]),
+                         ("mixed_storage_atomic", mst)):
         drift[name] = {k: float(rel_err(fields[k], ref[k])) for k in ref}
     rate = lambda ms: rod.n_mp * STEPS / (ms * 1e-3)
     print("large rod:", json.dumps(dict(
         n_mp=rod.n_mp, n_nodes=rod.n_nodes, steps=STEPS,
         mp_steps_per_s=dict(fp64_atomic=rate(ms64), mixed_atomic=rate(ms_a),
+                            mixed_storage_atomic=rate(ms_st),
                             mixed_segmented=rate(min(ms_s_runs))),
         drift_vs_fp64=drift)))
     for name, d in drift.items():
-        assert all(v <= MIXED_BOUND for v in d.values()), (name, d)
+        bound = STORAGE_BOUND if name.startswith("mixed_storage") else MIXED_BOUND
+        assert all(v <= bound for v in d.values()), (name, d)
     # the segmented assembly is deterministic: two runs agree bit for bit
     for k in seg[0]:
         assert np.array_equal(seg[0][k], seg[1][k]), k
