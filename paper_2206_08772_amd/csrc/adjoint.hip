@@ -731,6 +731,9 @@ __global__ __launch_bounds__(256) void k_adj_mp_scatter(AdjScatArgs a) {
     double Fb[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) Fb[i][j] = a.dfb[(3 * i + j) * n + p];
+    for (int c = 0; c < 3; ++c) hold(xpb[c]);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) hold(Fb[i][j]);
     // kAdjScatSlots pairs per lane at a time, loads first (slots past the
     // support reload pair q0 and are not used)
     constexpr int L = kAdjScatLanes, S = kAdjScatSlots;
@@ -747,6 +750,12 @@ __global__ __launch_bounds__(256) void k_adj_mp_scatter(AdjScatArgs a) {
         g[k][0] = a.dN[qq];
         g[k][1] = a.dN[a.stride + qq];
         g[k][2] = a.dN[2 * a.stride + qq];
+      }
+      // one wait for the chunk, before the per-slot branches
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        hold(I[k]); hold(w[k]);
+        hold(g[k][0]); hold(g[k][1]); hold(g[k][2]);
       }
 #pragma unroll
       for (int k = 0; k < S; ++k) {
@@ -867,6 +876,11 @@ __global__ __launch_bounds__(256) void k_adj_assembly(AdjAsmArgs a) {
   double Fb[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) Fb[i][j] = a.dfb[(3 * i + j) * n + p];
+  hold(v); hold(mp);
+  for (int c = 0; c < 6; ++c) hold(s[c]);
+  for (int c = 0; c < 3; ++c) hold(xpb[c]);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) hold(Fb[i][j]);
   double sb[6] = {0, 0, 0, 0, 0, 0}, vb = 0.0;
   const int64_t q0 = a.off[p], q1 = a.off[p + 1];
   const double2* rec2 = reinterpret_cast<const double2*>(a.nrec);
@@ -891,6 +905,12 @@ __global__ __launch_bounds__(256) void k_adj_assembly(AdjAsmArgs a) {
       r0[k] = a.nrec[2 * (int64_t)I[k]];
       r1[k] = rec2[4 * (int64_t)I[k] + 2];   // (du_y, du_z)
       fm[k] = a.fmb[I[k]];
+    }
+    // one wait for the chunk, before the per-slot branches
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      hold(r0[k]); hold(r1[k]); hold(fm[k]);
+      hold(g[k][0]); hold(g[k][1]); hold(g[k][2]);
     }
 #pragma unroll
     for (int k = 0; k < S; ++k) {

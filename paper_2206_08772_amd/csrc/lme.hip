@@ -205,12 +205,13 @@ struct AsmSink {
   }
   // The values loaded by begin() are first used inside the per-pair
   // branches, where the compiler waits for them with a full wait that also
-  // waits for every store issued so far (N, grad N of the earlier pairs); an
-  // empty statement that reads them here puts that one wait in straight-line
-  // code before the pairs, so the pairs' stores stay in flight.
+  // waits for every store issued so far (N, grad N of the earlier pairs);
+  // holding them here puts that one wait in straight-line code before the
+  // pairs, so the pairs' stores stay in flight.
   OTM_DEV void ready() const {
-    __asm__ volatile("" ::"v"(mp), "v"(vd), "v"(s0), "v"(s1), "v"(s2), "v"(s3), "v"(s4), "v"(s5));
-    if constexpr (HEAT) __asm__ volatile("" ::"v"(Tp), "v"(q0), "v"(q1), "v"(q2));
+    hold(mp); hold(vd);
+    hold(s0); hold(s1); hold(s2); hold(s3); hold(s4); hold(s5);
+    if constexpr (HEAT) { hold(Tp); hold(q0); hold(q1); hold(q2); }
   }
   OTM_DEV void values(double Nq, const double g[3], double (&c)[V]) const {
     const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];
@@ -254,7 +255,8 @@ struct SegSink {
   }
   // as AsmSink::ready
   OTM_DEV void ready() const {
-    __asm__ volatile("" ::"v"(mp), "v"(vd), "v"(s0), "v"(s1), "v"(s2), "v"(s3), "v"(s4), "v"(s5));
+    hold(mp); hold(vd);
+    hold(s0); hold(s1); hold(s2); hold(s3); hold(s4); hold(s5);
   }
   OTM_DEV void operator()(int64_t q, double Nq, const double g[3]) {
     const R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2];

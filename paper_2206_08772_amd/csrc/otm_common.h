@@ -58,6 +58,19 @@ OTM_DEV uint32_t xcd_block() {
   return x * q + (x < r ? x : r) + b / 8u;
 }
 
+// ------------------------------------------------------------ hold
+// An empty statement that reads a loaded value.  Values loaded together and
+// then used inside several branches (one per pair slot) are waited for once,
+// at this point in straight-line code: otherwise the compiler moves a load
+// used by one branch into that branch (its latency no longer overlaps the
+// others), or waits at the top of every branch with a full wait, which also
+// waits for every store issued before.
+OTM_DEV void hold(double v) { __asm__ volatile("" ::"v"(v)); }
+OTM_DEV void hold(float v) { __asm__ volatile("" ::"v"(v)); }
+OTM_DEV void hold(int32_t v) { __asm__ volatile("" ::"v"(v)); }
+OTM_DEV void hold(const double2& v) { hold(v.x); hold(v.y); }
+OTM_DEV void hold(const double4& v) { hold(v.x); hold(v.y); hold(v.z); hold(v.w); }
+
 // -------------------------------------------------------- pair force
 // Internal-force contribution -v sigma grad N_Ip of one pair (the nodal
 // residual, Sec. 2.1), sigma in Voigt order (xx yy zz xy yz xz).  sigma and
