@@ -78,11 +78,13 @@ struct Pairs {
   double d[CACHED ? PPL : 1][3];
 };
 
-// A row of the support lists fetched ahead of its solve: its start, length
-// and (for rows of at most G * PPL pairs) this lane's node ids.
+// A row of the support lists fetched ahead of its solve: its start and
+// the next row's start, its length (taken from the two only once the ids are
+// fetched, so that no wait follows the offsets' load) and, for rows of at
+// most G * PPL pairs, this lane's node ids.
 template <int PPL>
 struct RowIds {
-  int64_t off;
+  int64_t off, end;
   int K;
   int32_t I[PPL];
 };
@@ -266,10 +268,11 @@ struct SegSink {
   }
 };
 
-// Fetch this lane's node ids of a row whose start and length are set (rows
-// longer than G * PPL take the uncached path, which reads its ids itself).
+// Fetch this lane's node ids of a row whose bounds are set (rows longer than
+// G * PPL take the uncached path, which reads its ids itself).
 template <int G, int PPL>
 OTM_DEV void load_row_ids(RowIds<PPL>& r, const int32_t* __restrict__ idx, int lane) {
+  r.K = (int)(r.end - r.off);
   if (r.K > 0 && r.K <= G * PPL) {
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
@@ -279,13 +282,36 @@ OTM_DEV void load_row_ids(RowIds<PPL>& r, const int32_t* __restrict__ idx, int l
   }
 }
 
+// Waits for a fetched row in straight-line code.  A row still in flight
+// where control paths join (the end of a round) gets a full wait there, which
+// also waits for every store of the round.  (Its bounds were waited for when
+// its length was taken.)
+template <int PPL>
+OTM_DEV void hold_row(const RowIds<PPL>& r) {
+  hold(r.K);
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) hold(r.I[k]);
+}
+
 struct NoMid {
   OTM_DEV void operator()() const {}
+  OTM_DEV void ready() const {}
+};
+
+// Two hooks into an MP's solve: ``fetch`` once the Newton iteration has
+// ended, ``wait`` where the MP's own assembly loads are waited for.
+template <class F, class W>
+struct MidHooks {
+  F fetch;
+  W wait;
+  OTM_DEV void operator()() const { fetch(); }
+  OTM_DEV void ready() const { wait(); }
 };
 
 // One MP's solve.  ``pre`` (nullable) holds the row fetched ahead; ``mid``
 // runs once the Newton iteration has ended (the fused kernel fetches the
-// next round's node ids there, so they arrive while this MP finishes).
+// next round's node ids there, so they arrive while this MP finishes) and
+// ``mid.ready()`` where the MP's own assembly loads are waited for.
 template <int G, int PPL, bool CACHED, typename DN, class Sink, class Mid = NoMid>
 OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, const double* __restrict__ xp,
                        const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
@@ -296,6 +322,7 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
   const int64_t off = pre != nullptr ? pre->off : offsets[p];
   const int K = pre != nullptr ? pre->K : (int)(offsets[p + 1] - off);
   const double px = xp[p], py = xp[n_mp + p], pz = xp[2 * n_mp + p];
+  double lam[3] = {lam_io[p], lam_io[n_mp + p], lam_io[2 * n_mp + p]};
   Pairs<G, PPL, CACHED> pr;
   if constexpr (CACHED) {
     // branch-free loads (the MP's first pair stands in for empty slots) so
@@ -313,7 +340,8 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
       }
     }
   }
-  double lam[3] = {lam_io[p], lam_io[n_mp + p], lam_io[2 * n_mp + p]};
+  // the multiplier arrives with the node gathers (one wait for both)
+  hold(lam[0]); hold(lam[1]); hold(lam[2]);
   // ek holds the exponentials of the last evaluation; every line search
   // ends with an accepted trial, so they always belong to the current lambda
   double ek[CACHED ? PPL : 1];
@@ -356,6 +384,7 @@ OTM_DEV void lme_point(int64_t p, int lane, const NodeSrc& ns, int64_t n_mp, con
   const double iz = 1.0 / ev.Z;
   sink.begin(p);
   sink.ready();
+  mid.ready();
   auto finish = [&](int q, double e, double dx, double dy, double dz) {
     const double Nq = e * iz;
     const double d3[3] = {dx, dy, dz};
@@ -482,20 +511,27 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
   // so a round begins with its node gathers instead of two dependent loads
   auto row_at = [&](int64_t q, RowIds<PPL>& rw) {
     rw.off = 0;
+    rw.end = 0;
     rw.K = 0;
     if (ok && q < hi) {
       rw.off = offsets[q];
-      rw.K = (int)(offsets[q + 1] - rw.off);
+      rw.end = offsets[q + 1];
     }
   };
+  // the next round's ids are fetched once this round's Newton solve is done
+  // and waited for together with the MP's own loads
   RowIds<PPL> cur, nxt;
-  row_at(lo + tid / G, cur);
-  load_row_ids<G, PPL>(cur, idx, lane);
+  auto fetch = [&]() { load_row_ids<G, PPL>(nxt, idx, lane); };
+  auto wait = [&]() { hold_row(nxt); };
+  const MidHooks<decltype(fetch), decltype(wait)> mid{fetch, wait};
+  row_at(lo + tid / G, nxt);
+  fetch();
+  wait();
+  cur = nxt;
   int r = 0;
   for (int64_t p0 = lo; p0 < hi; p0 += per_round) {
     const int64_t p = p0 + tid / G;
     row_at(p + per_round, nxt);
-    auto mid = [&]() { load_row_ids<G, PPL>(nxt, idx, lane); };
     if (ok && p < hi) {
       if (cur.K <= G * PPL)
         lme_point<G, PPL, true, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
@@ -503,9 +539,9 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
       else
         lme_point<G, PPL, false, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
                                      max_iter, lam, N, dN, diag, sink, &cur, mid);
-    } else {
-      mid();
     }
+    // a lane without an MP this round has none the next round either (its
+    // next row is empty), so it fetches no ids
     cur = nxt;
     if (++r == flush_rounds) {
       r = 0;
