@@ -424,7 +424,7 @@ OTM_DEV double lane_value(double v, int t) {  // v of lane t (t uniform)
 // before the current cell is processed.  Each XCD strides over its own
 // contiguous eighth of the cells (neighbouring cells share that XCD's L2).
 constexpr int kCellWaves = 4;
-constexpr unsigned kCellBlocks = 8 * 512;
+constexpr unsigned kCellBlocks = 8 * 1024;
 constexpr int kCand = 320;
 constexpr int kCandChunks = kCand / kWave;
 constexpr int kRowCap = kRowCapacity;
@@ -648,7 +648,25 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
   const int64_t p0 = blk * kScanMPs;
   if (p0 >= n_mp) return;
   const int nloc = (int)(n_mp - p0 < kScanMPs ? n_mp - p0 : kScanMPs);
-  for (int i = tid; i <= nloc; i += 256) off[i] = offsets[p0 + i];
+  // every global input is requested before any is used (one memory latency
+  // instead of three in a row): the row starts, the total and the staged rows
+  static_assert(kScanMPs < 256, "one row start per thread");
+  constexpr int kPer = kScanMPs * kRowCap / 256;
+  static_assert(kPer * 256 == kScanMPs * kRowCap, "staged rows split evenly");
+  const int64_t my_off = tid <= nloc ? offsets[p0 + tid] : 0;
+  const int64_t total_pairs = offsets[n_mp];
+  int32_t st[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = k * 256 + tid;
+    st[k] = i < nloc * kRowCap ? stage[p0 * kRowCap + i] : 0;
+  }
+  if (tid <= nloc) off[tid] = my_off;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = k * 256 + tid;
+    if (i < nloc * kRowCap) rows[i] = st[k];
+  }
   __syncthreads();
   // largest support of the workgroup (reduced once more by k_search_done;
   // one atomic per MP on a single counter would serialise the pass)
@@ -667,9 +685,7 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
       blk_max = m;
     }
   }
-  if (offsets[n_mp] > capacity) return;  // lists do not fit: counts only
-  for (int i = tid; i < nloc * kRowCap; i += 256) rows[i] = stage[p0 * kRowCap + i];
-  __syncthreads();
+  if (total_pairs > capacity) return;  // lists do not fit: counts only
   // the staged rows come in stencil order: the four lanes of quad i sort row
   // i (rows past 32 ids, rare, by insertion in LDS in the quad's first lane;
   // rows past kRowCap are re-found below)
