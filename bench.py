@@ -190,6 +190,30 @@ def run_variant(w, precision, scatter, steps, warmup, **over):
     return out
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Best of ``reps`` device-to-device copies of ``nbytes`` (one copy kernel
+    each, timed with events): bytes read plus written over its time, GB/s.  A
+    measured ceiling for streaming kernels, beside the vendor peak."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
 def roofline_entry(nbytes, ms):
     gbs = nbytes / (ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -501,6 +525,7 @@ def main():
 
     progress(f"main line: {w.name}, fp64, atomic, {args.steps} steps")
     main_run = run_variant(w, "fp64", "atomic", args.steps, args.warmup)
+    copy_gbs = copy_bandwidth()
     variants = {}
     for v in [s for s in args.variants.split(",") if s and s != "none"]:
         progress(f"variant {v}")
@@ -541,6 +566,9 @@ def main():
     roof = roofline_entry(mp_b, ph["mp_update"])
     roof["kernel"] = "k_mp_update<double> (MP pass: kinematics + J2/JC return map)"
     roof["traffic"] = measured_traffic()
+    # the same kernel against a measured 1 GiB device-to-device copy
+    roof["measured_copy_gbs"] = round(copy_gbs, 1)
+    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
     phases = {
         "node_update": roofline_entry(node_bytes(w.n_nodes), ph["node_update"]),
         "search": roofline_entry(search_bytes(w.n_mp, w.n_nodes, P), ph["search"]),
