@@ -150,32 +150,89 @@ __global__ __launch_bounds__(256) void k_tr_fill(int64_t n_mp, int64_t cap,
   });
 }
 
-// Sixteen lanes per node: the place of each pair of the bucket in ascending
-// pair order (a rank count; pair ids are distinct), written straight to pos_of
-// so the sorted bucket itself is never stored.  Buckets up to kSortCap are
-// ranked from LDS, longer ones (degenerate inputs) from global memory.
+// Sixteen lanes per node: the bucket (distinct pair ids) put in ascending
+// order by a bitonic network over 256 slots, lane l of the node's 16-lane row
+// holding slots 16l .. 16l + 15 (past the bucket: INT32_MAX), and each pair's
+// place in that order written straight to pos_of, so the sorted bucket itself
+// is never stored.  Compare-exchanges between slots 16 or more apart pair a
+// lane with lane l ^ 1, ^ 2, ^ 4 or ^ 8 of its row (DPP quad permutations, a
+// swizzle, a row rotation by 8); the others stay in the lane.  Buckets past
+// kSortCap (degenerate inputs) are ranked from global memory.
 constexpr int kSortLanes = 16;
 constexpr int kSortNodes = 256 / kSortLanes;
 constexpr int kSortCap = 256;
+constexpr int kSortPer = kSortCap / kSortLanes;
+
+// Value of lane l ^ M of the same 16-lane row.
+template <int M>
+OTM_DEV int32_t row_xor(int32_t v) {
+  static_assert(M == 1 || M == 2 || M == 4 || M == 8, "lane distance within a row");
+  if constexpr (M == 1) return dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  else if constexpr (M == 2) return dpp_move<0x4E>(v);  // quad_perm [2,3,0,1]
+  else if constexpr (M == 4) return __builtin_amdgcn_ds_swizzle(v, (4 << 10) | 0x1F);
+  else return dpp_move<0x128>(v);  // row_ror:8
+}
+
+// One compare-exchange stage at distance J of the merge of width K.
+template <int K, int J>
+OTM_DEV void sort_stage(int32_t (&a)[kSortPer], int l) {
+  if constexpr (J >= kSortPer) {
+    constexpr int M = J / kSortPer;
+    const bool lower = (l & M) == 0;
+#pragma unroll
+    for (int e = 0; e < kSortPer; ++e) {
+      const int32_t w = row_xor<M>(a[e]);
+      const int32_t lo = a[e] < w ? a[e] : w, hi = a[e] < w ? w : a[e];
+      const bool up = ((kSortPer * l + e) & K) == 0;
+      a[e] = lower == up ? lo : hi;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < kSortPer; ++e) {
+      const int f = e ^ J;
+      if (f > e) {
+        const int32_t x = a[e], y = a[f];
+        const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+        const bool up = ((kSortPer * l + e) & K) == 0;
+        a[e] = up ? lo : hi;
+        a[f] = up ? hi : lo;
+      }
+    }
+  }
+}
+
+template <int K, int J>
+OTM_DEV void sort_merge(int32_t (&a)[kSortPer], int l) {
+  sort_stage<K, J>(a, l);
+  if constexpr (J > 1) sort_merge<K, J / 2>(a, l);
+}
+
+template <int K>
+OTM_DEV void sort_levels(int32_t (&a)[kSortPer], int l) {
+  sort_merge<K, K / 2>(a, l);
+  if constexpr (K < kSortCap) sort_levels<2 * K>(a, l);
+}
+
 __global__ __launch_bounds__(256) void k_tr_sort(int64_t n_nodes, const int64_t* __restrict__ start,
                                                  const int32_t* __restrict__ pairs,
                                                  int32_t* __restrict__ pos_of) {
-  __shared__ int32_t buf[kSortNodes][kSortCap];
   const int g = threadIdx.x / kSortLanes, lane = threadIdx.x % kSortLanes;
   const int64_t I = (int64_t)xcd_block() * kSortNodes + g;
-  if (I >= n_nodes) return;
+  if (I >= n_nodes) return;  // whole row leaves together
   const int64_t s0 = start[I];
   const int n = (int)(start[I + 1] - s0);
   if (n <= kSortCap) {
-    for (int i = lane; i < n; i += kSortLanes) buf[g][i] = pairs[s0 + i];
-    // the group's lanes are in one wave: a wave barrier orders the LDS accesses
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (int i = lane; i < n; i += kSortLanes) {
-      const int32_t v = buf[g][i];
-      int r = 0;
-      for (int j = 0; j < n; ++j) r += buf[g][j] < v;
-      pos_of[v] = (int32_t)(s0 + r);
+    int32_t a[kSortPer];
+#pragma unroll
+    for (int e = 0; e < kSortPer; ++e) {
+      const int i = kSortPer * lane + e;
+      a[e] = i < n ? pairs[s0 + i] : INT32_MAX;
+    }
+    sort_levels<2>(a, lane);
+#pragma unroll
+    for (int e = 0; e < kSortPer; ++e) {
+      const int i = kSortPer * lane + e;
+      if (i < n) pos_of[a[e]] = (int32_t)(s0 + i);
     }
   } else {
     for (int i = lane; i < n; i += kSortLanes) {
