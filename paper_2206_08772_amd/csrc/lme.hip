@@ -469,11 +469,23 @@ __global__ __launch_bounds__(256) void k_lme(NodeSrc ns, int64_t n_mp, const dou
 
 // Shape functions with the atomic nodal assembly fused in.  A fixed grid of
 // kLmeAsmBlocks workgroups (two per CU at this kernel's register use) each
-// take a contiguous range of MPs in rounds of 256 / G; every
-// kLmeAsmFlushRounds rounds (512 MPs, spatially compact) the node table is
-// flushed to m and f.  The round count is the same for every lane of a
-// workgroup, so the barriers around a flush are reached by all of them.
+// take chunks of `chunk` consecutive MPs (spatially compact) in rounds of
+// 256 / G (a chunk's last round may be partial); the node table is flushed to m and f every
+// kLmeAsmFlushRounds rounds and at the end of each chunk.  The round count is
+// the same for every lane of a workgroup, so the barriers around a flush are
+// reached by all of them.
 constexpr int kLmeAsmBlocks = 512;
+constexpr int kLmeAsmFlushRounds = 8;
+static_assert(kLmeAsmBlocks % 8 == 0, "the workgroups split evenly over the 8 XCDs");
+
+// Chunk size.  With four or more chunks of 512 MPs per workgroup, 512 (the
+// chunks are dealt round-robin); otherwise one contiguous range per
+// workgroup, every workgroup busy (smaller chunks would add flushes faster
+// than they even out the work).
+inline int64_t lme_asm_chunk(int64_t n_mp) {
+  const int64_t per_wg = (n_mp + kLmeAsmBlocks - 1) / kLmeAsmBlocks;
+  return per_wg >= 4 * 512 ? 512 : per_wg;
+}
 
 template <int G, int PPL, typename DN, bool HEAT, typename Q>
 __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
@@ -483,17 +495,23 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
                                                  double beta, double tol, int max_iter,
                                                  double* __restrict__ lam,
                                                  double* __restrict__ N, DN* __restrict__ dN,
-                                                 otm_diag* diag, AsmIn a) {
+                                                 otm_diag* diag, AsmIn a, int64_t chunk) {
   constexpr int per_round = 256 / G;
-  constexpr int flush_rounds = 512 / per_round;
+  const int64_t rpc = (chunk + per_round - 1) / per_round;  // rounds per chunk
   using Sink = AsmSink<DN, HEAT, Q>;
   __shared__ NodeTableV<Sink::V> table;
   const int tid = threadIdx.x;
   table_clear(table, tid, 256);
   __syncthreads();
-  const int64_t chunk = (n_mp + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = (int64_t)xcd_block() * chunk;
-  const int64_t hi = lo + chunk < n_mp ? lo + chunk : n_mp;
+  // Each XCD takes a contiguous eighth of the chunks (its workgroups' gathers
+  // then share its L2) and deals them round-robin to its workgroups.  With
+  // several chunks per workgroup, a workgroup's chunks come from across its
+  // XCD's range, so regions of slow MPs (more pairs, more Newton steps) are
+  // shared out instead of setting one workgroup's, and the kernel's, end;
+  // with one, each workgroup has a contiguous range.
+  const int64_t n_chunks = (n_mp + chunk - 1) / chunk;
+  const int64_t xcd = blockIdx.x % 8u, wgs = gridDim.x / 8u, j = blockIdx.x / 8u;
+  const int64_t c_lo = n_chunks * xcd / 8, c_hi = n_chunks * (xcd + 1) / 8;
   const bool ok = offsets[n_mp] <= cap;  // lists were written (capacity)
   const int lane = tid % G;
   NodeDst<Sink::V> dst;
@@ -509,11 +527,14 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
   // rows are fetched one round ahead: the next round's start and length at
   // the top of a round, its node ids once this round's Newton solve is done,
   // so a round begins with its node gathers instead of two dependent loads
-  auto row_at = [&](int64_t q, RowIds<PPL>& rw) {
+  // round k of chunk c (this workgroup's chunks are c_lo + j, + wgs, ...)
+  auto row_at = [&](int64_t c, int64_t k, RowIds<PPL>& rw) {
     rw.off = 0;
     rw.end = 0;
     rw.K = 0;
-    if (ok && q < hi) {
+    const int64_t i = k * per_round + tid / G;  // place in the chunk
+    const int64_t q = c * chunk + i;
+    if (ok && c < c_hi && i < chunk && q < n_mp) {
       rw.off = offsets[q];
       rw.end = offsets[q + 1];
     }
@@ -524,15 +545,18 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
   auto fetch = [&]() { load_row_ids<G, PPL>(nxt, idx, lane); };
   auto wait = [&]() { hold_row(nxt); };
   const MidHooks<decltype(fetch), decltype(wait)> mid{fetch, wait};
-  row_at(lo + tid / G, nxt);
+  int64_t c = c_lo + j, k = 0;
+  row_at(c, 0, nxt);
   fetch();
   wait();
   cur = nxt;
-  int r = 0;
-  for (int64_t p0 = lo; p0 < hi; p0 += per_round) {
-    const int64_t p = p0 + tid / G;
-    row_at(p + per_round, nxt);
-    if (ok && p < hi) {
+  while (c < c_hi) {
+    const int64_t i = k * per_round + tid / G;  // place in the chunk
+    const int64_t p = c * chunk + i;
+    const bool chunk_end = k + 1 == rpc;
+    const int64_t cn = chunk_end ? c + wgs : c, kn = chunk_end ? 0 : k + 1;
+    row_at(cn, kn, nxt);
+    if (ok && i < chunk && p < n_mp) {
       if (cur.K <= G * PPL)
         lme_point<G, PPL, true, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
                                     max_iter, lam, N, dN, diag, sink, &cur, mid);
@@ -540,15 +564,17 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
         lme_point<G, PPL, false, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
                                      max_iter, lam, N, dN, diag, sink, &cur, mid);
     }
-    // a lane without an MP this round has none the next round either (its
-    // next row is empty), so it fetches no ids
+    // a lane without an MP this round (past its chunk's end or the last MP:
+    // only in a chunk's last round) has an empty next row (the next round is
+    // in the same chunk, further on, or there is none), so it fetches no ids
     cur = nxt;
-    if (++r == flush_rounds) {
-      r = 0;
+    if (chunk_end || (k + 1) % kLmeAsmFlushRounds == 0) {
       __syncthreads();
       table_flush(table, tid, 256, dst);
       __syncthreads();
     }
+    c = cn;
+    k = kn;
   }
   __syncthreads();
   table_flush(table, tid, 256, dst);
@@ -563,9 +589,11 @@ void launch_lme(int64_t n_nodes, const double* x_nodes, int64_t n_mp, const doub
   const NodeSrc ns{x_nodes, packed, n_nodes};
   constexpr int G = 4, PPL = 9;
   if (fused != nullptr) {
+    static_assert(256 / G == 64, "rounds of 64 MPs");
+    const int64_t chunk = lme_asm_chunk(n_mp);
     auto run = [&](auto kernel, auto* dn) {
       kernel<<<kLmeAsmBlocks, 256, 0, s>>>(ns, n_mp, x_mp, nbr_offsets, nbr_idx, pair_capacity,
-                                           beta, tol, max_iter, lam, N, dn, diag, *fused);
+                                           beta, tol, max_iter, lam, N, dn, diag, *fused, chunk);
     };
     const bool heat = fused->heat != nullptr;
     if (precision == OTM_FP64) {
