@@ -397,11 +397,26 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   } else {
     for (int i = tid; i < kSums * kMpBlock; i += kMpBlock) sums[i / kMpBlock][i % kMpBlock] = 0.0;
   }
+  // phase 2's inputs of this lane's MP, requested before the barrier: their
+  // latency overlaps the end of the gathers and the update waits for them
+  // once instead of once per input as it reaches it
+  const int64_t p = base + tid;
+  const bool mine = p < n_mp && lists_ok;
+  double vol_n = 0.0, ebn = 0.0, Tn = 0.0;
+  R fd_n[9], bd_n[6];
+  if (mine) {
+    vol_n = vol[p];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) fd_n[k] = Fd[k * n_mp + p];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) bd_n[k] = bed[k * n_mp + p];
+    ebn = epsbar[p];
+    Tn = T[p];
+  }
   __syncthreads();
 
   // phase 2: one lane per MP
-  const int64_t p = base + tid;
-  if (p >= n_mp || !lists_ok) return;
+  if (!mine) return;
   M3<double> H;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -419,9 +434,11 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   }
   const double detdF = 1.0 + det_one_plus_minus_one(H);
   // a failed MP (fracture) carries nothing, so its inversion does not matter
+  // (loaded here: a value merged over the null-pointer branch would be
+  // waited for before the barrier; here this one wait covers all the above)
   const bool was_failed = failed != nullptr && failed[p] != 0;
   if (!(detdF > 0.0) && !was_failed) diag_fail(diag, OTM_ERR_INVERTED, (uint64_t)p);
-  vol[p] = detdF * vol[p];
+  vol[p] = detdF * vol_n;
   if (dFm1 != nullptr) {  // history of the stabilisation term
 #pragma unroll
     for (int c = 0; c < 3; ++c) xp_prev[c * n_mp + p] = xp[c * n_mp + p];
@@ -440,7 +457,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       h.a[i][j] = (Q)H.a[i][j];
-      fo.a[i][j] = Fd[(3 * i + j) * n_mp + p];
+      fo.a[i][j] = fd_n[3 * i + j];
     }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -472,13 +489,13 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     // conduction increment: a failed MP still holds heat)
 #pragma unroll
     for (int c = 0; c < 6; ++c) sig.v[c] = Q(0);
-    if constexpr (COND) T[p] = T[p] + dTc;
+    if constexpr (COND) T[p] = Tn + dTc;
   } else {
     // trial elastic left Cauchy-Green tensor, as a deviation from 1:
     // b_tr - 1 = H + H^T + H H^T + (1+H) Bd (1+H)^T
     S3<Q> bd;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) bd.v[c] = bed[c * n_mp + p];
+    for (int c = 0; c < 6; ++c) bd.v[c] = bd_n[c];
     const M3<Q> B = full(bd);
     M3<Q> HB;  // (1 + H) Bd
 #pragma unroll
@@ -506,7 +523,6 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
 #pragma unroll
     for (int a = 0; a < 3; ++a) dev[a] = e[a] - tr / Q(3);
     const Q q_tr = Q(2) * M.mu * m_sqrt(Q(1.5) * (dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]));
-    const double ebn = epsbar[p], Tn = T[p];
     Q Ts = Q(0);
     if (M.model == OTM_J2_JC) {
       Q t = (Q)((Tn - (double)M.Tr) / ((double)M.Tm - (double)M.Tr));
