@@ -524,7 +524,8 @@ OTM_DEV void cell_scan_one(const CellHdr& h, double r2, const double4* __restric
       if (mb != m0) mine = mp_sorted[mb + (lane < mc ? lane : mc - 1)];
       const int32_t pl = (int32_t)mine.w;  // this lane's MP
       int t = 0;
-      for (; t + 1 < mc; t += 2) test_mps(std::integral_constant<int, 2>{}, t, pl);
+      for (; t + 3 < mc; t += 4) test_mps(std::integral_constant<int, 4>{}, t, pl);
+      if (t + 1 < mc) { test_mps(std::integral_constant<int, 2>{}, t, pl); t += 2; }
       if (t < mc) test_mps(std::integral_constant<int, 1>{}, t, pl);
     }
   } else {
