@@ -757,8 +757,19 @@ __global__ __launch_bounds__(1024) void k_search_done(const int64_t* offsets, in
                                                       const int32_t* block_max, int64_t nblocks,
                                                       int64_t capacity, otm_diag* diag) {
   __shared__ int32_t red[1024 / kWave];
+  // the total is requested first, and the maxima eight at a time, so the
+  // loads overlap instead of following one another
+  const int64_t P = threadIdx.x == 0 ? offsets[n_mp] : 0;
   int32_t m = 0;
-  for (int64_t b = threadIdx.x; b < nblocks; b += 1024) m = block_max[b] > m ? block_max[b] : m;
+  int64_t b = threadIdx.x;
+  for (; b + 7 * 1024 < nblocks; b += 8 * 1024) {
+    int32_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = block_max[b + k * 1024];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m = v[k] > m ? v[k] : m;
+  }
+  for (; b < nblocks; b += 1024) m = block_max[b] > m ? block_max[b] : m;
   for (int o = kWave / 2; o > 0; o >>= 1) {
     const int32_t u = __shfl_xor(m, o);
     m = u > m ? u : m;
@@ -767,7 +778,6 @@ __global__ __launch_bounds__(1024) void k_search_done(const int64_t* offsets, in
   __syncthreads();
   if (threadIdx.x != 0 || diag == nullptr) return;
   for (int w = 1; w < 1024 / kWave; ++w) m = red[w] > m ? red[w] : m;
-  const int64_t P = offsets[n_mp];
   diag->pairs_needed = P;
   diag->max_support = m;
   if (P > capacity) atomicOr(&diag->flags, 1u << (-OTM_ERR_CAPACITY - 1));
