@@ -470,10 +470,10 @@ __global__ __launch_bounds__(256) void k_lme(NodeSrc ns, int64_t n_mp, const dou
 // Shape functions with the atomic nodal assembly fused in.  A fixed grid of
 // kLmeAsmBlocks workgroups (two per CU at this kernel's register use) each
 // take chunks of `chunk` consecutive MPs (spatially compact) in rounds of
-// 256 / G (a chunk's last round may be partial); the node table is flushed to m and f every
-// kLmeAsmFlushRounds rounds and at the end of each chunk.  The round count is
-// the same for every lane of a workgroup, so the barriers around a flush are
-// reached by all of them.
+// 256 / G (a chunk's last round may be partial); the node table is flushed
+// to m and f every kLmeAsmFlushRounds rounds and at the end of each chunk.
+// The round count is the same for every lane of a workgroup, so the barriers
+// around a flush are reached by all of them.
 constexpr int kLmeAsmBlocks = 512;
 constexpr int kLmeAsmFlushRounds = 8;
 static_assert(kLmeAsmBlocks % 8 == 0, "the workgroups split evenly over the 8 XCDs");
@@ -564,9 +564,10 @@ __global__ __launch_bounds__(256) void k_lme_asm(NodeSrc ns, int64_t n_mp,
         lme_point<G, PPL, false, DN>(p, lane, ns, n_mp, xp, offsets, idx, cap, beta, tol,
                                      max_iter, lam, N, dN, diag, sink, &cur, mid);
     }
-    // a lane without an MP this round (past its chunk's end or the last MP:
-    // only in a chunk's last round) has an empty next row (the next round is
-    // in the same chunk, further on, or there is none), so it fetches no ids
+    // a lane without an MP this round (past its chunk's end, or past the last
+    // MP) has an empty next row: the next round is further on in the same
+    // chunk, or there is none (a chunk that ends early is the workgroup's
+    // only one, or the last of all), so it fetches no ids
     cur = nxt;
     if (chunk_end || (k + 1) % kLmeAsmFlushRounds == 0) {
       __syncthreads();
