@@ -222,7 +222,9 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   // over the return-map solve (each lane only touches its own column)
   constexpr int kSums = COND ? 17 : 13;
   constexpr int kGathered = COND ? 16 : 12;
-  __shared__ double sums[kSums][kMpBlock];
+  // rows padded by one double, so that the lanes of a group writing the
+  // sums of one MP hit different LDS banks
+  __shared__ double sums[kSums][kMpBlock + 1];
   __shared__ int64_t row[kMpBlock + 1];
   const int64_t base = (int64_t)xcd_block() * kMpBlock;
   const int tid = threadIdx.x;
@@ -312,16 +314,11 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
           a[15] += wt * rI;
         }
       }
-#pragma unroll
-      for (int c = 0; c < kGathered; ++c) a[c] = group_sum<kGather>(a[c]);
-      if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) sums[c][r * kPer + grp] = a[c];
-        if constexpr (COND) {
-#pragma unroll
-          for (int c = 12; c < 16; ++c) sums[c + 1][r * kPer + grp] = a[c];
-        }
-      }
+      // each of the group's lanes ends with the total of one sum (or none)
+      // and writes it: one store instead of kGathered from one lane
+      int c;
+      const double t = row_sum_scatter<kGathered>(a, c);
+      if (c >= 0) sums[COND && c >= 12 ? c + 1 : c][r * kPer + grp] = t;
     };
     // rounds past the last reload the last round's rows (uniform control flow)
     auto cl = [](int r) { return r < kGather ? r : kGather - 1; };
@@ -361,7 +358,11 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     }
     __builtin_amdgcn_sched_barrier(0);
     // long rows: the pairs past kSlots * kGather, summed per group and added
-    // to the row's sums (the same lane wrote them, so no barrier is needed)
+    // to the row's sums by the group's lane 0; the round totals were written
+    // by other lanes of the same wave, so a wave-level fence comes first
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int r = 0; r < kGather; ++r) {
       const int local = r * kPer + grp;
       const int64_t o0 = row[local], o1 = row[local + 1];

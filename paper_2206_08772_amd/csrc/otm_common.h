@@ -112,6 +112,53 @@ template <int G, typename T>
 OTM_DEV T group_sum(T v) {
   return group_reduce<G>(v, [](T a, T b) { return a + b; });
 }
+
+// One stage of row_sum_scatter: the lane keeps the lower or the upper half
+// of its N-list (``upper``), sends the other half to its partner (the lane
+// that keeps the opposite half of the same list) and adds what the partner
+// sends.  A missing upper element (N odd) is a zero that stays zero.
+template <int CTRL, int N, int M>
+OTM_DEV void split_stage(const double (&in)[N], double (&out)[M], bool upper) {
+  static_assert(M == (N + 1) / 2, "halving stage");
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const double lo = in[i];
+    const double hi = i + M < N ? in[i + M] : 0.0;
+    out[i] = (upper ? hi : lo) + dpp_move<CTRL>(upper ? lo : hi);
+  }
+}
+
+// Reduce-scatter over an aligned 16-lane row: V <= 16 values per lane in,
+// the row's total of one of them out.  The four stages pair lane l with
+// l ^ 8 (row_ror:8), then l ^ 7 (row_half_mirror), l ^ 2 and l ^ 1 (quad
+// permutations); at each one the partners differ in the bit that picks the
+// half kept (bits 3, 2, 1, 0) and agree in the bits of the earlier stages,
+// so they hold the same list, and each lane's total collects all 16 lanes.
+// The adds number about V instead of 4 V for V all-reduces.  ``c`` gets the
+// index of the value whose total the lane holds, or -1 (a padding slot).
+template <int V>
+OTM_DEV double row_sum_scatter(const double (&a)[V], int& c) {
+  static_assert(V >= 2 && V <= 16, "2 to 16 values over a 16-lane row");
+  constexpr int M1 = (V + 1) / 2, M2 = (M1 + 1) / 2, M3 = (M2 + 1) / 2;
+  static_assert((M3 + 1) / 2 == 1, "four stages");
+  const int l = (int)(__lane_id() & 15u);
+  double b1[M1], b2[M2], b3[M3], b4[1];
+  split_stage<0x128>(a, b1, (l & 8) != 0);   // row_ror:8
+  split_stage<0x141>(b1, b2, (l & 4) != 0);  // row_half_mirror
+  split_stage<0x4E>(b2, b3, (l & 2) != 0);   // quad_perm [2,3,0,1]
+  split_stage<0xB1>(b3, b4, (l & 1) != 0);   // quad_perm [1,0,3,2]
+  // the kept element's place in the original list and whether it is real
+  int idx = 0, len = V;
+  auto step = [&](int m, bool upper) {
+    if (upper) { idx += m; len -= m; } else if (len > m) { len = m; }
+  };
+  step(M1, (l & 8) != 0);
+  step(M2, (l & 4) != 0);
+  step(M3, (l & 2) != 0);
+  step(1, (l & 1) != 0);
+  c = len >= 1 ? idx : -1;
+  return b4[0];
+}
 template <int G>
 OTM_DEV double group_max(double v) {
   return group_reduce<G>(v, [](double a, double b) { return fmax(a, b); });
