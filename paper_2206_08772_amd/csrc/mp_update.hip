@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
       const double t = row_sum_scatter<kGathered>(a, c);
       if (c >= 0) sums[COND && c >= 12 ? c + 1 : c][r * kPer + grp] = t;
     };
-    // rounds past the last reload the last round's rows (uniform control flow)
+    // round r + 4 of the last loop pass reloads the last round's rows
     auto cl = [](int r) { return r < kGather ? r : kGather - 1; };
     Ids i0, i1;
     Pairs p0, p1;
@@ -339,23 +339,30 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     load_pairs(p1, 1);
     __builtin_amdgcn_sched_barrier(0);
     load_ids(i0, 2);
-    static_assert(kGather % 2 == 0, "rounds are taken in pairs");
-    for (int r = 0; r < kGather; r += 2) {
+    static_assert(kGather % 2 == 0 && kGather >= 4, "rounds are taken in pairs");
+    for (int r = 0; r < kGather - 2; r += 2) {
       __builtin_amdgcn_sched_barrier(0);
       load_nodes(n1, i1);             // gathers of round r + 1
       __builtin_amdgcn_sched_barrier(0);
       sum_round(r, n0, p0);
       __builtin_amdgcn_sched_barrier(0);
-      load_pairs(p0, cl(r + 2));
-      load_ids(i1, cl(r + 3));
+      load_pairs(p0, r + 2);
+      load_ids(i1, r + 3);
       __builtin_amdgcn_sched_barrier(0);
       load_nodes(n0, i0);             // gathers of round r + 2
       __builtin_amdgcn_sched_barrier(0);
       sum_round(r + 1, n1, p1);
       __builtin_amdgcn_sched_barrier(0);
-      load_pairs(p1, cl(r + 3));
+      load_pairs(p1, r + 3);
       load_ids(i0, cl(r + 4));
     }
+    // the last two rounds: nothing left to fetch ahead
+    __builtin_amdgcn_sched_barrier(0);
+    load_nodes(n1, i1);
+    __builtin_amdgcn_sched_barrier(0);
+    sum_round(kGather - 2, n0, p0);
+    __builtin_amdgcn_sched_barrier(0);
+    sum_round(kGather - 1, n1, p1);
     __builtin_amdgcn_sched_barrier(0);
     // long rows: the pairs past kSlots * kGather, summed per group and added
     // to the row's sums by the group's lane 0; the round totals were written
