@@ -320,8 +320,6 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
       const double t = row_sum_scatter<kGathered>(a, c);
       if (c >= 0) sums[COND && c >= 12 ? c + 1 : c][r * kPer + grp] = t;
     };
-    // round r + 4 of the last loop pass reloads the last round's rows
-    auto cl = [](int r) { return r < kGather ? r : kGather - 1; };
     Ids i0, i1;
     Pairs p0, p1;
     Nodes n0, n1;
@@ -339,8 +337,10 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     load_pairs(p1, 1);
     __builtin_amdgcn_sched_barrier(0);
     load_ids(i0, 2);
-    static_assert(kGather % 2 == 0 && kGather >= 4, "rounds are taken in pairs");
-    for (int r = 0; r < kGather - 2; r += 2) {
+    static_assert(kGather % 2 == 0 && kGather >= 6, "rounds are taken in pairs");
+    // rounds r, r + 1, fetching ahead up to round r + 4 (with_ids: the ids of
+    // round r + 4 exist)
+    auto two_rounds = [&](int r, bool with_ids) {
       __builtin_amdgcn_sched_barrier(0);
       load_nodes(n1, i1);             // gathers of round r + 1
       __builtin_amdgcn_sched_barrier(0);
@@ -354,8 +354,10 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
       sum_round(r + 1, n1, p1);
       __builtin_amdgcn_sched_barrier(0);
       load_pairs(p1, r + 3);
-      load_ids(i0, cl(r + 4));
-    }
+      if (with_ids) load_ids(i0, r + 4);
+    };
+    for (int r = 0; r < kGather - 4; r += 2) two_rounds(r, true);
+    two_rounds(kGather - 4, false);
     // the last two rounds: nothing left to fetch ahead
     __builtin_amdgcn_sched_barrier(0);
     load_nodes(n1, i1);
