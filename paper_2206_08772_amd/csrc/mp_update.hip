@@ -18,6 +18,10 @@
 // have type R and the update computes in type Q: float64 / float64 in
 // OTM_FP64, float32 / float32 in OTM_MIXED, float32 / float64 in
 // OTM_MIXED_STORAGE.
+#include <stdint.h>
+
+#include <type_traits>
+
 #include "constitutive.h"
 #include "launch.h"
 #include "otm_common.h"
@@ -207,7 +211,12 @@ constexpr int kSlots = 32 / kGather;   // pairs per lane loaded branch-free
 // sum_I N_Ip rate_I from the node records' (T_I, rate_I), kept in sums[13..16]
 // (past the slots that phase 2 parks values in); phase 2 adds
 // dt sum N rate to T_{n+1} and stores the flux -kappa grad T_p.
-template <typename R, bool COND, typename Q = R>
+//
+// PAIRED: a lane's two slots are two consecutive pairs starting at an even
+// index, so idx, N and each component of grad N come in one load of two
+// values (8 or 16 bytes) instead of two; this needs idx 8-byte, N and grad N
+// 2 sizeof(R)-byte aligned and an even capacity (the launcher checks).
+template <typename R, bool COND, typename Q = R, bool PAIRED = false>
 __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     const double4* __restrict__ nodes, int64_t n_nodes, int64_t n_mp,
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
@@ -244,9 +253,12 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   // complete in issue order, so a wait can only leave younger loads in flight;
   // with this order every wait is for pair data issued two rounds earlier or
   // for gathers issued one round earlier, never for the newest HBM loads.
-  // Register sets alternate with the parity of the round.  Slots past a row's
-  // end read pair 0 / node 0 and get weight 0, so all loads are branch-free;
-  // pairs past kSlots * kGather (long rows) are added after the pipeline.
+  // Register sets alternate with the parity of the round.  Slot k of lane l
+  // is pair k * kGather + l of the row, or with PAIRED pair q0 + k, q0 = the
+  // row's start rounded down to even + 2 l (a slot before the start or past
+  // the end is unused).  Unused slots read pair 0 / node 0 and get weight 0,
+  // so all loads are branch-free; the pairs past the slots (long rows) are
+  // added after the pipeline.
   if (lists_ok && have_nodes) {
     const int lane = tid % kGather;
     const int grp = tid / kGather;
@@ -268,19 +280,50 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
       use = q < row[local + 1];
       return use ? q : (int64_t)0;
     };
+    // PAIRED: the lane's first pair (even; q0 + 1 < capacity whenever
+    // q0 < capacity, the capacity being even), or 0 if neither slot is used
+    static_assert(!PAIRED || kSlots == 2, "two consecutive pairs per lane");
+    auto pair0 = [&](int r, bool (&use)[kSlots]) {
+      const int local = r * kPer + grp;
+      const int64_t a = row[local], b = row[local + 1];
+      const int64_t q0 = (a & ~(int64_t)1) + 2 * lane;
+      use[0] = q0 >= a && q0 < b;
+      use[1] = q0 + 1 < b;
+      return use[0] || use[1] ? q0 : (int64_t)0;
+    };
+    using R2 = std::conditional_t<std::is_same_v<R, double>, double2, float2>;
     auto load_ids = [&](Ids& s, int r) {
+      if constexpr (PAIRED) {
+        const int2 v = *reinterpret_cast<const int2*>(idx + pair0(r, s.use));
+        s.i[0] = v.x;
+        s.i[1] = v.y;
+      } else {
 #pragma unroll
-      for (int k = 0; k < kSlots; ++k) s.i[k] = idx[slot(r, k, s.use[k])];
+        for (int k = 0; k < kSlots; ++k) s.i[k] = idx[slot(r, k, s.use[k])];
+      }
     };
     auto load_pairs = [&](Pairs& s, int r) {
+      if constexpr (PAIRED) {
+        bool use[kSlots];
+        const int64_t q0 = pair0(r, use);
+        const double2 w = *reinterpret_cast<const double2*>(N + q0);
+        const R2 g0 = *reinterpret_cast<const R2*>(dN + q0);
+        const R2 g1 = *reinterpret_cast<const R2*>(dN + cap + q0);
+        const R2 g2 = *reinterpret_cast<const R2*>(dN + 2 * cap + q0);
+        s.w[0] = w.x; s.w[1] = w.y;
+        s.g0[0] = g0.x; s.g0[1] = g0.y;
+        s.g1[0] = g1.x; s.g1[1] = g1.y;
+        s.g2[0] = g2.x; s.g2[1] = g2.y;
+      } else {
 #pragma unroll
-      for (int k = 0; k < kSlots; ++k) {
-        bool use;
-        const int64_t q = slot(r, k, use);
-        s.w[k] = N[q];
-        s.g0[k] = dN[q];
-        s.g1[k] = dN[cap + q];
-        s.g2[k] = dN[2 * cap + q];
+        for (int k = 0; k < kSlots; ++k) {
+          bool use;
+          const int64_t q = slot(r, k, use);
+          s.w[k] = N[q];
+          s.g0[k] = dN[q];
+          s.g1[k] = dN[cap + q];
+          s.g2[k] = dN[2 * cap + q];
+        }
       }
     };
     auto load_nodes = [&](Nodes& s, const Ids& ids) {
@@ -366,18 +409,19 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
     __builtin_amdgcn_sched_barrier(0);
     sum_round(kGather - 1, n1, p1);
     __builtin_amdgcn_sched_barrier(0);
-    // long rows: the pairs past kSlots * kGather, summed per group and added
-    // to the row's sums by the group's lane 0; the round totals were written
-    // by other lanes of the same wave, so a wave-level fence comes first
+    // long rows: the pairs past the slots, summed per group and added to the
+    // row's sums by the group's lane 0; the round totals were written by
+    // other lanes of the same wave, so a wave-level fence comes first
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int r = 0; r < kGather; ++r) {
       const int local = r * kPer + grp;
       const int64_t o0 = row[local], o1 = row[local + 1];
-      if (o1 - o0 <= kSlots * kGather) continue;  // uniform within the group
+      const int64_t done = (PAIRED ? (o0 & ~(int64_t)1) : o0) + kSlots * kGather;
+      if (o1 <= done) continue;  // uniform within the group
       double a[kGathered] = {};
-      for (int64_t q = o0 + kSlots * kGather + lane; q < o1; q += kGather) {
+      for (int64_t q = done + lane; q < o1; q += kGather) {
         const int32_t J = idx[q];
         const double wt = N[q];
         const double h0 = (double)dN[q], h1 = (double)dN[cap + q], h2 = (double)dN[2 * cap + q];
@@ -631,26 +675,33 @@ void launch_mp_update(const otm_state& st, const otm_params& p, double dt,
                                    st.T, sg, mat, hist_x, hist_f, frac, clock, dt, diag, p.kappa,
                                    st.qflux);
   };
+  // paired pair loads where the arrays allow them (see k_mp_update)
+  const size_t dn_size = st.precision == OTM_FP64 ? sizeof(double) : sizeof(float);
+  const bool paired = st.pair_capacity % 2 == 0 && (uintptr_t)st.nbr_idx % 8 == 0 &&
+                      (uintptr_t)st.N % 16 == 0 && (uintptr_t)st.dN % (2 * dn_size) == 0;
   const bool cond = p.kappa > 0.0;
+  auto pick = [&](auto r_tag, auto q_tag, auto dn, auto fd, auto bd, auto sg, auto m) {
+    using R = decltype(r_tag);
+    using Q = decltype(q_tag);
+    if (cond) {
+      if (paired) run(k_mp_update<R, true, Q, true>, dn, fd, bd, sg, m);
+      else run(k_mp_update<R, true, Q, false>, dn, fd, bd, sg, m);
+    } else {
+      if (paired) run(k_mp_update<R, false, Q, true>, dn, fd, bd, sg, m);
+      else run(k_mp_update<R, false, Q, false>, dn, fd, bd, sg, m);
+    }
+  };
   if (st.precision == OTM_FP64) {
-    const auto m = make_mat<double>(p, dt);
-    double *fd = (double*)st.Fd, *bd = (double*)st.bed, *sg = (double*)st.sigma;
-    const double* dn = (const double*)st.dN;
-    if (cond) run(k_mp_update<double, true>, dn, fd, bd, sg, m);
-    else run(k_mp_update<double, false>, dn, fd, bd, sg, m);
+    pick(double{}, double{}, (const double*)st.dN, (double*)st.Fd, (double*)st.bed,
+         (double*)st.sigma, make_mat<double>(p, dt));
     return;
   }
   float *fd = (float*)st.Fd, *bd = (float*)st.bed, *sg = (float*)st.sigma;
   const float* dn = (const float*)st.dN;
-  if (st.precision == OTM_MIXED) {  // the return map in float32
-    const auto m = make_mat<float>(p, dt);
-    if (cond) run(k_mp_update<float, true, float>, dn, fd, bd, sg, m);
-    else run(k_mp_update<float, false, float>, dn, fd, bd, sg, m);
-  } else {  // float32 storage, float64 arithmetic
-    const auto m = make_mat<double>(p, dt);
-    if (cond) run(k_mp_update<float, true, double>, dn, fd, bd, sg, m);
-    else run(k_mp_update<float, false, double>, dn, fd, bd, sg, m);
-  }
+  if (st.precision == OTM_MIXED)  // the return map in float32
+    pick(float{}, float{}, dn, fd, bd, sg, make_mat<float>(p, dt));
+  else  // float32 storage, float64 arithmetic
+    pick(float{}, double{}, dn, fd, bd, sg, make_mat<double>(p, dt));
 }
 
 // ------------------------------------------------------------------- t = 0

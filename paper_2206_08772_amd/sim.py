@@ -218,7 +218,8 @@ class Sim:
         self.v0 = soa(v0_nodes, dev)
         if pair_capacity is None:
             P = self._count_pairs()
-            pair_capacity = int(P * capacity_margin) + 1024
+            # even, so that the MP update can load two pairs at once
+            pair_capacity = (int(P * capacity_margin) + 1024 + 1) // 2 * 2
         self.cap = int(pair_capacity)
         self.idx = torch.zeros(self.cap, dtype=torch.int32, device=dev)
         self.N = torch.zeros(self.cap, dtype=torch.float64, device=dev)

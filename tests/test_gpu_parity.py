@@ -233,6 +233,30 @@ def test_small_rod_100_steps_mixed(rod_oracle, precision):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_small_rod_odd_pair_capacity(rod_oracle, precision):
+    """The MP update loads two consecutive pairs at once only with an even
+    pair capacity (the default one is rounded up to even); an odd one takes
+    the one-pair-per-load path, held to the same bounds over 100 steps."""
+    from paper_2206_08772_amd.sim import Sim
+    w, st, p = rod_oracle
+    even, _ = make_sim(w, precision)
+    assert even.cap % 2 == 0
+    sim = Sim(w.x_nodes, w.x_mp, w.vol_mp, w.mass_mp, w.v0_nodes, p, precision=precision,
+              pair_capacity=even.cap + 1)
+    del even
+    sim.init()
+    sim.run(100, rebuild_every=int(p["rebuild_every"]))
+    sim.check_diag()
+    g = sim.fields()
+    assert np.array_equal(g["offsets"], st.offsets) and np.array_equal(g["idx"], st.idx)
+    errs = compare(gpu_fields(g, w.x_nodes, w.x_mp, p["T_r"]),
+                   oracle_fields(st, w.x_nodes, w.x_mp, p["T_r"]))
+    tol = {k: FP64_TOL for k in errs} if precision == "fp64" else MIXED_TOL
+    bad = {k: v for k, v in errs.items() if not v < tol[k]}
+    assert not bad, bad
+
+
 def test_segmented_scatter_is_bit_reproducible():
     w = W.config_by_name("small_rod")
     a, _ = _gpu_run(w, 20, scatter="segmented")
