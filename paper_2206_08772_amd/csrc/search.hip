@@ -640,7 +640,7 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
     const int32_t* __restrict__ cell_start, const double4* __restrict__ sorted,
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ stage, int64_t capacity,
     int32_t* __restrict__ idx, int32_t* __restrict__ block_max) {
-  __shared__ int32_t rows[kScanMPs * kRowCap];
+  __shared__ __align__(16) int32_t rows[kScanMPs * kRowCap];
   __shared__ uint8_t owner[kScanMPs * kRowCap];  // MP of each output element
   __shared__ int64_t off[kScanMPs + 1];
   __shared__ int32_t blk_max;
@@ -650,23 +650,29 @@ __global__ __launch_bounds__(256) void k_nbr_compact(
   if (p0 >= n_mp) return;
   const int nloc = (int)(n_mp - p0 < kScanMPs ? n_mp - p0 : kScanMPs);
   // every global input is requested before any is used (one memory latency
-  // instead of three in a row): the row starts, the total and the staged rows
+  // instead of three in a row): the row starts, the total and the staged rows,
+  // these in 16-byte pieces (a workgroup's rows start at a multiple of
+  // kScanMPs * kRowCap * 4 bytes, and a row's kRowCap ids fill whole pieces)
   static_assert(kScanMPs < 256, "one row start per thread");
-  constexpr int kPer = kScanMPs * kRowCap / 256;
-  static_assert(kPer * 256 == kScanMPs * kRowCap, "staged rows split evenly");
+  static_assert(kRowCap % 4 == 0, "rows of whole 16-byte pieces");
+  constexpr int kPieces = kScanMPs * kRowCap / 4;
+  constexpr int kPer = (kPieces + 255) / 256;
   const int64_t my_off = tid <= nloc ? offsets[p0 + tid] : 0;
   const int64_t total_pairs = offsets[n_mp];
-  int32_t st[kPer];
+  const int4* __restrict__ st4 = reinterpret_cast<const int4*>(stage + p0 * kRowCap);
+  int4* rows4 = reinterpret_cast<int4*>(rows);
+  const int npc = nloc * (kRowCap / 4);
+  int4 st[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int i = k * 256 + tid;
-    st[k] = i < nloc * kRowCap ? stage[p0 * kRowCap + i] : 0;
+    st[k] = i < npc ? st4[i] : make_int4(0, 0, 0, 0);
   }
   if (tid <= nloc) off[tid] = my_off;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int i = k * 256 + tid;
-    if (i < nloc * kRowCap) rows[i] = st[k];
+    if (i < npc) rows4[i] = st[k];
   }
   __syncthreads();
   // largest support of the workgroup (reduced once more by k_search_done;
