@@ -165,7 +165,10 @@ typedef struct otm_params {
 /* Device state of one simulation (host struct of device pointers). */
 typedef struct otm_state {
   int64_t n_nodes, n_mp;
-  int64_t pair_capacity;  /* length of nbr_idx and N; dN is [3][pair_capacity] */
+  int64_t pair_capacity;  /* length of nbr_idx and N; dN is [3][pair_capacity].
+                             Any value works; an even one (with nbr_idx 8-byte,
+                             N 16-byte and dN 16-byte (8-byte if float) aligned)
+                             lets the MP update load two pairs at once */
   int32_t precision;      /* OTM_FP64, OTM_MIXED or OTM_MIXED_STORAGE: types of
                              the void* fields (float in both mixed modes) */
   int32_t pad0;
