@@ -256,9 +256,10 @@ __global__ __launch_bounds__(kMpBlock) void k_mp_update(
   // Register sets alternate with the parity of the round.  Slot k of lane l
   // is pair k * kGather + l of the row, or with PAIRED pair q0 + k, q0 = the
   // row's start rounded down to even + 2 l (a slot before the start or past
-  // the end is unused).  Unused slots read pair 0 / node 0 and get weight 0,
-  // so all loads are branch-free; the pairs past the slots (long rows) are
-  // added after the pipeline.
+  // the end is unused).  Unused slots get weight 0 and gather node 0; their
+  // pair data is pair 0's (or, with PAIRED, the neighbouring pair loaded
+  // with a used one), so all loads are branch-free.  The pairs past the
+  // slots (long rows) are added after the pipeline.
   if (lists_ok && have_nodes) {
     const int lane = tid % kGather;
     const int grp = tid / kGather;
